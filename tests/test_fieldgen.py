@@ -1,0 +1,47 @@
+"""Input generator checks: divergence-free turbulence, normalisation, RNE quantisers."""
+import numpy as np
+import torch
+
+import fieldgen as fg
+
+
+def test_turbulence_divergence_free_and_normalised():
+    # |k| <= 2 on a 28-cell box: wavelengths >= 14 cells, so central differences resolve it
+    v = fg.turbulence_values(77, (24, 20, 28), n_modes=64, kmax=2.0)[0]
+    assert abs(np.linalg.norm(v, axis=-1).max() - 1.0) < 1e-12
+    # central-difference divergence vs gradient magnitude: O(kappa^2 dx^2) relative residue
+    div = ((v[1:-1, 1:-1, 2:, 0] - v[1:-1, 1:-1, :-2, 0]) + (v[1:-1, 2:, 1:-1, 1] - v[1:-1, :-2, 1:-1, 1])
+           + (v[2:, 1:-1, 1:-1, 2] - v[:-2, 1:-1, 1:-1, 2])) / 2
+    grad = np.abs(v[1:-1, 1:-1, 2:, 0] - v[1:-1, 1:-1, :-2, 0]) / 2
+    assert np.sqrt(np.mean(div ** 2)) < 0.05 * np.sqrt(np.mean(grad ** 2))
+
+
+def test_turbulence_slices_drift_and_cache_roundtrip():
+    a = fg.turbulence_values(78, (8, 8, 8), n_modes=16, n_slices=3)
+    b = fg.turbulence_values(78, (8, 8, 8), n_modes=16, n_slices=3)
+    np.testing.assert_array_equal(a, b)
+    assert not np.allclose(a[0], a[2])
+    assert abs(np.linalg.norm(a, axis=-1).max() - 1.0) < 1e-12
+
+
+def test_quantizers_round_to_nearest_even():
+    rng = np.random.default_rng(3)
+    x = np.concatenate([rng.normal(size=20000), rng.normal(size=2000) * 1e-6,
+                        [0.5 + 2 ** -12, 0.5 + 3 * 2 ** -12, 65504.0, 65520.0, 1e-9]])
+    # FP16: numpy's double -> half conversion is correctly rounded
+    np.testing.assert_array_equal(fg.quantize(x, fg.F16).view(np.float16), x.astype(np.float16))
+    np.testing.assert_array_equal(fg.quantize(x, fg.F32), x.astype(np.float32))
+    # BF16 from values that are exact in FP32 (no double rounding): torch's RNE
+    x32 = x.astype(np.float32).astype(np.float64)
+    ref = torch.from_numpy(x32.astype(np.float32)).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    np.testing.assert_array_equal(fg.quantize(x32, fg.BF16), ref)
+
+
+def test_seed_sets():
+    s = fg.uniform_seeds(2, 100000, (0, 0, 0), (256, 256, 256))
+    assert s.dtype == np.float32 and (s >= 0).all() and (s < 256).all()
+    assert abs(s.mean() - 128) < 1.0
+    b = fg.blob_seeds(3, 4, 2000, 512.0, 24.0, 8.0)
+    assert (b >= 0).all() and (b < 512).all() and b.shape == (8000, 3)
+    for k in range(4):
+        assert 6.5 < b[k * 2000:(k + 1) * 2000].std(axis=0).mean() < 9.5
