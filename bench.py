@@ -1,0 +1,227 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the RK4 field-line advection path on one MI355X.
+
+One step = one pass of the hot path over one batch of synthetic input, with
+the field and the seed set already resident in HBM: clear the handle, seed
+every particle (device-to-device), advect every particle to termination
+(trilinear gathers, RK4, exit/stagnation tests, vertex and outbox appends).
+Field ingest and line fetch are one-time costs, reported separately.
+
+Default workload: one rank's block of synthetic turbulence, 256^3 interior
+nodes + 1 ghost layer, FP32 vec3, 1M uniform seeds, h = 0.5 cell, at most 2000
+steps, exits to the outbox (rank grid 4^3, block at (1,1,1)).
+
+Prints ONE JSON line (rank 0).  Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+WORKLOADS = {
+    # name: (edge, dtype, n_seeds, max_steps, h, seed kind, record stride)
+    "turb256-f32": (256, "f32", 1 << 20, 2000, 0.5, "uniform", 1),
+    "turb512-bf16": (512, "bf16", 1 << 22, 4000, 0.5, "blobs", 8),
+    "turb512-f16": (512, "f16", 1 << 22, 4000, 0.5, "blobs", 8),
+    "turb512-f32": (512, "f32", 1 << 22, 4000, 0.5, "blobs", 8),
+    "abc32-f32": (32, "f32", 1024, 200, 0.01, "abc", 1),
+}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha1()
+    for f in ("advect.hip", "device.h"):
+        with open(os.path.join(ROOT, "paper_2606_02627_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:12]
+
+
+def build_inputs(name):
+    import fieldgen as fg
+    edge, dt, n, m, h, kind, stride = WORKLOADS[name]
+    fmt = {"f32": fg.F32, "f16": fg.F16, "bf16": fg.BF16}[dt]
+    if kind == "abc":
+        blk = fg.abc_block(edge, fmt)
+        seeds = fg.uniform_seeds(1, n, (0, 0, 0), (2 * np.pi,) * 3)
+    else:
+        cfg = 2 if edge == 256 else 3
+        blk = fg.turbulence_block(cfg, edge=edge, fmt=fmt)
+        if kind == "uniform":
+            seeds = fg.uniform_seeds(cfg, n, (0, 0, 0), (edge,) * 3)
+        else:
+            seeds = fg.blob_seeds(cfg, 64, n // 64, float(edge), 24.0, 8.0)
+    return blk, seeds, fmt, m, h, stride
+
+
+def cpu_baseline(blk, seeds, h, m, budget_s=12.0):
+    """The FP64 oracle as it stands, on a bounded sample of the same workload."""
+    import oracle
+    F = oracle.Field.from_block(blk)
+    threads = min(16, os.cpu_count() or 1)
+    n = 256
+    total_steps, total_t = 0, 0.0
+    used = 0
+    # grow the sample until ~budget_s of CPU wall time is spent
+    while total_t < budget_s and used < len(seeds):
+        k = min(n, len(seeds) - used)
+        t0 = time.perf_counter()
+        r = F.trace(seeds[used:used + k], h, m, threads=threads, keep_verts=False)
+        total_t += time.perf_counter() - t0
+        total_steps += int(r["steps"].sum())
+        used += k
+        n *= 2
+    return dict(value=total_steps / total_t, unit="particle-steps/s", cores=threads, kind="oracle",
+                sample=f"first {used} of the {len(seeds)} seeds, full trajectories "
+                       f"(<= {m} steps each, {total_steps} steps) on the same stored field, FP64",
+                seconds=round(total_t, 2))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="turb256-f32", choices=sorted(WORKLOADS))
+    ap.add_argument("--layout", type=int, default=0, help="0 auto, 1 linear, 2 brick4")
+    ap.add_argument("--waves-per-cu", type=int, default=0)
+    ap.add_argument("--refill", type=int, default=0)
+    ap.add_argument("--no-cell-cache", action="store_true")
+    ap.add_argument("--graph", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on exactly one GPU (the multi-GPU exchange of the outbox is "
+              "designed but not built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2606_02627_amd as S
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    dev = torch.device("cuda:0")
+    log("building inputs", args.workload)
+    t0 = time.perf_counter()
+    blk, seeds, fmt, m, h, stride = build_inputs(args.workload)
+    log(f"inputs ready in {time.perf_counter() - t0:.1f}s: field {blk.stored.nbytes / 1e6:.1f} MB, "
+        f"{len(seeds)} seeds")
+
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    f = S.Field([blk], fmt, layout=args.layout)
+    torch.cuda.synchronize()
+    ingest_s = time.perf_counter() - t0
+    d_seeds = torch.from_numpy(seeds).to(dev)
+    torch.cuda.synchronize()
+
+    kw = dict(waves_per_cu=args.waves_per_cu, refill_threshold=args.refill,
+              no_cell_cache=int(args.no_cell_cache), use_graph=int(args.graph))
+
+    def one_step(stats=False):
+        f.clear()
+        f.seed(0, d_seeds, default_max_steps=m, record_stride=stride)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        p = S.advect_params(h, **kw)
+        st = S.streami_advect(f.h, p, want_stats=stats)
+        e1.record(stream)
+        return st, e0, e1
+
+    # warmup (the first also provides the deterministic per-step counts)
+    st0 = None
+    for w in range(max(1, args.warmup)):
+        st, _, _ = one_step(stats=True)
+        st0 = st0 or st
+        log(f"warmup {w}: {st.steps} particle-steps in {st.device_ms:.2f} ms "
+            f"({st.steps / st.device_ms / 1e6:.3f} G steps/s), exits {st.terminated[2]}, "
+            f"max-steps {st.terminated[1]}")
+    steps_per_pass = int(st0.steps)
+    verts_per_pass = int(st0.vertices)
+
+    torch.cuda.synchronize()
+    events = []
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        _, e0, e1 = one_step(stats=False)
+        events.append((e0, e1))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    adv_ms = [e0.elapsed_time(e1) for e0, e1 in events]
+    log(f"timed {args.steps} steps: wall {wall * 1e3:.1f} ms, advect "
+        f"{np.mean(adv_ms):.3f} ms mean ({min(adv_ms):.3f} min)")
+
+    # one-time costs outside the timed region
+    t0 = time.perf_counter()
+    n_lines = min(len(seeds), 65536)
+    L = f.lines(0, 0, n_lines)
+    fetch_s = time.perf_counter() - t0
+    ob = f.outbox(cap=len(seeds))
+
+    value = steps_per_pass * args.steps / wall
+    node_bytes = 4 if fmt == S.F32 else 2
+    alg_bytes = steps_per_pass * 96 * node_bytes + verts_per_pass * 12
+    mean_adv_s = float(np.mean(adv_ms)) / 1e3
+    achieved = alg_bytes / mean_adv_s / 1e9
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", f"traffic_advect_{args.workload}.json")
+    if os.path.exists(tfile):
+        try:
+            tj = json.load(open(tfile))
+            if tj.get("kernel_hash") == kernel_source_hash() and tj.get("layout", 0) == args.layout:
+                traffic = tj.get("hbm_bytes_per_launch")
+        except Exception:
+            traffic = None
+    out = {
+        "metric": "RK4 particle-steps/s + HBM GB/s; surrogate vs plain at fixed endpoint error",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {S.F32: "f32", S.F16: "f16 storage, f32 math", S.BF16: "bf16 storage, f32 math"}[fmt],
+        "data": "synthetic",
+        "config": {"workload": args.workload, "field": f"{WORKLOADS[args.workload][0]}^3 + ghost",
+                   "seeds": len(seeds), "max_steps": m, "h": h, "record_stride": stride,
+                   "particle_steps_per_step": steps_per_pass, "vertices_per_step": verts_per_pass,
+                   "layout": args.layout, "waves_per_cu": args.waves_per_cu,
+                   "cell_cache": not args.no_cell_cache, "graph": args.graph},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_advect", "alg_bytes_per_launch": alg_bytes,
+                     "mean_launch_ms": mean_adv_s * 1e3, "kernel_hash": kernel_source_hash()},
+        "advect_only_steps_per_s": steps_per_pass / mean_adv_s,
+        "ingest_ms": ingest_s * 1e3,
+        "fetch_lines_ms_per_65536": fetch_s * 1e3,
+        "outbox_records": int(len(ob)),
+    }
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(blk, seeds, h, m)
+        log(f"cpu baseline {out['cpu_baseline']['value']:.3g} steps/s on {out['cpu_baseline']['cores']} threads")
+    f.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

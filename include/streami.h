@@ -1,0 +1,238 @@
+/*
+ * streami.h -- C-ABI of the MI355X (gfx950) field-line advection library.
+ *
+ * The library advects many particles through the vector-field block(s) that
+ * one GPU holds, with the classical fourth-order Runge-Kutta update, and
+ * records each particle's polyline.  Particles that leave the owned bounds of
+ * their block are written to an outbox together with the flat id of the
+ * macrocell (rank) that owns their new position, instead of being sent.
+ *
+ * Paper: "Streami: An MPI Data-Parallel Library to Compute Field Lines on
+ * GPUs".  Where each call comes from:
+ *   - a field is set by the application in its own layout, one per time step
+ *     (Sec. 3.2, Tracer::setField; Sec. 3.3, structured float3 voxel grid);
+ *   - sampling is defined on the block's domain = owned bounds + halo, and is
+ *     undefined outside it (Sec. 3.1.1, sample() and the macrocell domain);
+ *   - destinationID() maps a position to the flat id of the macrocell grid
+ *     cell that holds it (Sec. 3.1.1, uniform grid of macrocells);
+ *   - particles are a position and a unique id (Sec. 3.1.2);
+ *   - one RK4 update per particle and step, then the destination test and the
+ *     buffered emitOutgoing() (Sec. 3.1.2, the update kernel listing);
+ *   - Tracer::step()/trace() advance one step / until no particle is active,
+ *     streamlines seed once, streaklines re-seed periodically (Sec. 3.2, the
+ *     step() listing); getLines() returns the assembled lines (Sec. 3.2).
+ *
+ * Conventions for every call:
+ *   - returns STREAMI_OK (0) or a STREAMI_E_* code; nothing aborts and no C++
+ *     exception crosses the ABI; streami_last_error() gives the calling
+ *     thread's last message;
+ *   - a handle is bound to the device that was current at creation and to one
+ *     HIP stream; all device work is enqueued on that stream; a handle is not
+ *     thread-safe;
+ *   - caller buffers are only read (inputs) or only written (outputs) during
+ *     the call and stay owned by the caller; the library owns every device
+ *     buffer it allocates until streami_field_destroy().
+ */
+#ifndef STREAMI_H
+#define STREAMI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define STREAMI_OK 0
+#define STREAMI_E_ARG 1         /* invalid argument; nothing was changed */
+#define STREAMI_E_NOMEM 2       /* device or host allocation failed */
+#define STREAMI_E_DEVICE 3      /* a HIP call failed */
+#define STREAMI_E_STATE 4       /* call not valid in the handle's current state */
+#define STREAMI_E_CAPACITY 5    /* output buffer too small; required size reported */
+#define STREAMI_E_UNSUPPORTED 6 /* valid request this build does not implement */
+
+/* ---- node storage formats (the GPU never quantises: nodes arrive in this format) ---- */
+#define STREAMI_F32 0
+#define STREAMI_F16 1
+#define STREAMI_BF16 2
+
+/* ---- block boundary handling ---- */
+#define STREAMI_BOUNDARY_BLOCK 0    /* exits go to the outbox */
+#define STREAMI_BOUNDARY_PERIODIC 1 /* sampling wraps, positions stay unwrapped, no exits */
+
+/* ---- termination codes of a particle ---- */
+#define STREAMI_ACTIVE 0
+#define STREAMI_MAX_STEPS 1
+#define STREAMI_EXIT 2      /* left the owned bounds; in the outbox */
+#define STREAMI_STAGNANT 3  /* |v| < stagnation_eps at the start of a step */
+#define STREAMI_HALO_MISS 4 /* a stage sample was undefined; in the outbox at the old position */
+#define STREAMI_NONFINITE 5 /* a sampled value or the new position was NaN/Inf */
+
+/* ---- field storage layouts ---- */
+#define STREAMI_LAYOUT_AUTO 0
+#define STREAMI_LAYOUT_LINEAR 1 /* x-fastest node rows */
+#define STREAMI_LAYOUT_BRICK4 2 /* 4x4x4-node bricks, bricks in x-fastest order */
+
+/* ---- advection modes ---- */
+#define STREAMI_MODE_PLAIN 0
+#define STREAMI_MODE_SURROGATE 1
+
+typedef struct streami_field_s* streami_field;
+typedef struct streami_mlp_s* streami_mlp;
+
+/*
+ * One block = the part of the domain one rank holds (a macrocell and its
+ * halo, Sec. 3.1.1).  Node (i,j,k) of slice s is stored at
+ *   nodes[(((s*(nz+2g) + k)*(ny+2g) + j)*(nx+2g) + i)*3 + c],  c = x,y,z component,
+ * where storage index 0 is the first ghost node, so interior node (0,0,0) sits
+ * at world position `origin`.  Storage coordinate of world x along an axis:
+ *   s = (x - origin)/spacing + ghost;  sample() is defined for 0 <= s <= n_store-1
+ * (closed), and the value is the trilinear interpolant of the 8 surrounding
+ * nodes.  With PERIODIC boundary, ghost must be 0 and indices wrap modulo
+ * dims.  Owned bounds are half-open [bounds_lo, bounds_hi).
+ * Time slices: slice s holds time t0 + s*slice_dt; between slices the value
+ * is blended linearly in time, clamped to the first/last slice pair.
+ */
+typedef struct {
+  int32_t dims[3];         /* interior nodes per axis, >= 1 */
+  int32_t ghost;           /* ghost layers per face: 0 or 1 (0 when periodic) */
+  double origin[3];        /* world position of interior node (0,0,0) */
+  double spacing[3];       /* node spacing per axis, > 0 */
+  double bounds_lo[3];     /* owned region, half-open */
+  double bounds_hi[3];
+  int32_t boundary;        /* STREAMI_BOUNDARY_* */
+  int32_t rank_grid[3];    /* macrocell grid dims for destinationID, >= 1 */
+  int32_t rank_coord[3];   /* this block's cell in that grid */
+  int32_t n_slices;        /* >= 1 */
+  double t0;               /* time of slice 0 */
+  double slice_dt;         /* > 0 when n_slices > 1 */
+  const void* nodes;       /* node values in the handle's dtype (see layout above) */
+  int32_t nodes_on_device; /* 1: `nodes` is a device pointer, 0: host memory */
+} streami_block_desc;
+
+typedef struct {
+  int32_t layout; /* STREAMI_LAYOUT_*; AUTO picks the library default */
+} streami_field_opts;
+
+/*
+ * Create a handle over n_blocks blocks (1 for a rank's single block; many
+ * for a batched launch) that all store nodes in `dtype`.  The node values are
+ * copied into the library's own device buffer and re-laid-out there (the
+ * caller keeps ownership of `nodes`); the copy is complete when this returns.
+ * hip_stream: the hipStream_t all later work of this handle is enqueued on
+ * (NULL = the default stream).  opts may be NULL.
+ * Errors: E_ARG for an invalid descriptor (the message names the field),
+ * E_NOMEM, E_DEVICE.  *out is set only on success.
+ */
+int streami_field_create(const streami_block_desc* blocks, int32_t n_blocks, int32_t dtype,
+                         const streami_field_opts* opts, void* hip_stream, streami_field* out);
+
+int streami_field_destroy(streami_field f);
+
+/* Seeding options (Sec. 3.2: streamlines seed once at step 0). */
+typedef struct {
+  int32_t default_max_steps; /* per-particle step limit when max_steps == NULL, >= 0 */
+  int32_t record_stride;     /* keep vertex j when j % stride == 0, and the final vertex; >= 1 */
+  int32_t inputs_on_device;  /* 1: xyz/ids/max_steps are device pointers */
+  float t_birth;             /* time of step 0 of these particles (unsteady fields) */
+} streami_seed_opts;
+
+/*
+ * Append n particles to block `block`.  xyz: n*3 FP32 positions; ids: n
+ * unique ids or NULL (then ids continue a per-handle counter from 0);
+ * max_steps: n per-particle limits or NULL.  Each particle reserves
+ * max_steps/record_stride + 2 vertices of 12 bytes in the handle's line
+ * buffer.  The seed position is vertex 0; a seed outside the block's owned
+ * bounds (BLOCK boundary) terminates at once with code EXIT and 0 steps and
+ * goes to the outbox.  Particles of a block keep their seed order for
+ * streami_fetch_lines().  Errors: E_ARG, E_NOMEM, E_DEVICE.
+ */
+int streami_seed(streami_field f, int32_t block, const float* xyz, const uint64_t* ids,
+                 const int32_t* max_steps, int64_t n, const streami_seed_opts* opts);
+
+typedef struct {
+  float h;                  /* step size in world units per unit time, > 0 */
+  int32_t step_budget;      /* >0: at most this many steps per particle in this call (step());
+                               0: run every particle to termination (trace()) */
+  float stagnation_eps;     /* STAGNANT when |v(P0)|_2 < eps at the start of a step */
+  int32_t mode;             /* STREAMI_MODE_PLAIN or STREAMI_MODE_SURROGATE */
+  streami_mlp mlp;          /* trained network for SURROGATE mode, else NULL */
+  float residual_tol_cells; /* SURROGATE: accept a jump when its residual <= tol (cells) */
+  int32_t residual_kind;    /* SURROGATE: 0 commutation residual, 1 one big RK4 step */
+  int32_t waves_per_cu;     /* launch shape; 0 = library default / tuned value */
+  int32_t refill_threshold; /* free lanes that trigger a work-queue refill; 0 = default */
+  int32_t use_graph;        /* 1: capture the launch sequence in a hipGraph and replay it */
+  int32_t no_cell_cache;    /* 1: re-gather a cell's corners at every sample (A/B measurement;
+                               results are bit-identical either way) */
+} streami_advect_params;
+
+typedef struct {
+  int64_t active;              /* particles still ACTIVE after the call */
+  int64_t steps;               /* RK4 steps taken in this call (a surrogate jump counts 16) */
+  int64_t vertices;            /* vertices recorded in this call */
+  int64_t outbox;              /* records currently in the outbox */
+  int64_t surrogate_accepted;  /* jumps accepted */
+  int64_t surrogate_fallback;  /* jumps rejected and redone with plain RK4 */
+  int64_t terminated[6];       /* particles per termination code after the call */
+  double device_ms;            /* device time of the advect kernels of this call */
+} streami_stats;
+
+/*
+ * Advance every ACTIVE particle of the handle (all blocks), like
+ * Tracer::trace() (step_budget == 0) or a step() of step_budget steps.
+ * Enqueued on the handle's stream; returns without waiting unless stats !=
+ * NULL, in which case it waits and fills *stats.  A call with a budget that
+ * is resumed by further calls produces bit-identical lines, step counts and
+ * codes to a single unbudgeted call.  Errors: E_ARG (bad params), E_STATE
+ * (no particles, or SURROGATE without a network), E_DEVICE.
+ */
+int streami_advect(streami_field f, const streami_advect_params* p, streami_stats* stats);
+
+/*
+ * Copy the lines of particles [first, first+count) of `block` in seed order,
+ * as CSR: offsets[count+1] (offsets[0] = 0), xyz[offsets[count]*3] FP32.
+ * steps, codes (int32) and ids (uint64) per particle may be NULL.
+ * If cap_vertices < the number of vertices needed, nothing is copied,
+ * *needed_vertices is set and E_CAPACITY returned (two-call pattern).
+ * Output pointers may be host or device memory (detected); the call waits for
+ * the handle's stream before returning.  Errors: E_ARG, E_CAPACITY, E_DEVICE.
+ */
+int streami_fetch_lines(streami_field f, int32_t block, int64_t first, int64_t count,
+                        int64_t* offsets, float* xyz, int64_t cap_vertices, int32_t* steps,
+                        int32_t* codes, uint64_t* ids, int64_t* needed_vertices);
+
+/* Outbox record: a particle that left its block (emitOutgoing, Sec. 3.1.2). */
+typedef struct {
+  uint64_t id;
+  float pos[3];  /* new position for EXIT, old position for HALO_MISS */
+  int32_t steps; /* steps taken when it left */
+  int32_t dest;  /* destinationID of pos (EXIT) or of the failing stage point (HALO_MISS); -1 outside the rank grid */
+  int16_t code;  /* STREAMI_EXIT or STREAMI_HALO_MISS */
+  int16_t block; /* block index within the handle */
+} streami_outbox_rec;
+
+/*
+ * Move up to `cap` outbox records into `out` (host or device memory,
+ * detected) and remove them from the outbox; *n_out = records copied.  Record
+ * order is unspecified.  If more records remain than cap, the first cap are
+ * copied and the call returns E_CAPACITY with *n_out = cap; the rest stay.
+ */
+int streami_fetch_outbox(streami_field f, streami_outbox_rec* out, int64_t cap, int64_t* n_out);
+
+/*
+ * Drop every particle, line and outbox record of the handle (the field data
+ * stays), so the same handle can trace a new seed set -- a new Tracer run on
+ * the same fields (Sec. 3.2).  Device buffers are kept for reuse.
+ */
+int streami_clear(streami_field f);
+
+/* Particle counts of a block (for sizing fetch buffers). */
+int streami_block_info(streami_field f, int32_t block, int64_t* n_particles, int64_t* n_vertices);
+
+/* Thread-local description of the last error. */
+const char* streami_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STREAMI_H */

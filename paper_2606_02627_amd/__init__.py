@@ -1,0 +1,296 @@
+"""Python binding of libstreami (MI355X/gfx950 field-line advection).
+
+Argument marshalling only: every function below calls the C-ABI entry point
+of the same name in ``libstreami.so`` (declared in ``include/streami.h``).
+Arrays may be numpy arrays (host memory) or torch tensors (host or device);
+the HIP stream defaults to torch's current stream.  There is no CPU fallback:
+importing this package fails if the HIP library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+try:  # torch first: its HIP runtime is the one libstreami binds to
+    import torch
+except ImportError:  # pragma: no cover - torch is part of the supported environment
+    torch = None
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libstreami.so")
+
+OK, E_ARG, E_NOMEM, E_DEVICE, E_STATE, E_CAPACITY, E_UNSUPPORTED = range(7)
+F32, F16, BF16 = 0, 1, 2
+BOUNDARY_BLOCK, BOUNDARY_PERIODIC = 0, 1
+ACTIVE, MAX_STEPS, EXIT, STAGNANT, HALO_MISS, NONFINITE = range(6)
+LAYOUT_AUTO, LAYOUT_LINEAR, LAYOUT_BRICK4 = 0, 1, 2
+MODE_PLAIN, MODE_SURROGATE = 0, 1
+
+
+class StreamiError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"streami error {code}: {msg}")
+        self.code = code
+
+
+class BlockDesc(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int32 * 3), ("ghost", ctypes.c_int32),
+                ("origin", ctypes.c_double * 3), ("spacing", ctypes.c_double * 3),
+                ("bounds_lo", ctypes.c_double * 3), ("bounds_hi", ctypes.c_double * 3),
+                ("boundary", ctypes.c_int32), ("rank_grid", ctypes.c_int32 * 3),
+                ("rank_coord", ctypes.c_int32 * 3), ("n_slices", ctypes.c_int32),
+                ("t0", ctypes.c_double), ("slice_dt", ctypes.c_double),
+                ("nodes", ctypes.c_void_p), ("nodes_on_device", ctypes.c_int32)]
+
+
+class FieldOpts(ctypes.Structure):
+    _fields_ = [("layout", ctypes.c_int32)]
+
+
+class SeedOpts(ctypes.Structure):
+    _fields_ = [("default_max_steps", ctypes.c_int32), ("record_stride", ctypes.c_int32),
+                ("inputs_on_device", ctypes.c_int32), ("t_birth", ctypes.c_float)]
+
+
+class AdvectParams(ctypes.Structure):
+    _fields_ = [("h", ctypes.c_float), ("step_budget", ctypes.c_int32),
+                ("stagnation_eps", ctypes.c_float), ("mode", ctypes.c_int32),
+                ("mlp", ctypes.c_void_p), ("residual_tol_cells", ctypes.c_float),
+                ("residual_kind", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
+                ("refill_threshold", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("no_cell_cache", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("active", ctypes.c_int64), ("steps", ctypes.c_int64),
+                ("vertices", ctypes.c_int64), ("outbox", ctypes.c_int64),
+                ("surrogate_accepted", ctypes.c_int64), ("surrogate_fallback", ctypes.c_int64),
+                ("terminated", ctypes.c_int64 * 6), ("device_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "terminated"}
+        d["terminated"] = list(self.terminated)
+        return d
+
+
+OUTBOX_DTYPE = np.dtype([("id", "<u8"), ("pos", "<f4", (3,)), ("steps", "<i4"), ("dest", "<i4"),
+                         ("code", "<i2"), ("block", "<i2")])
+assert OUTBOX_DTYPE.itemsize == 32
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                          "(python -c 'import __graft_entry__ as g; g.build()')")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    sig = {
+        "streami_field_create": [vp, i32, i32, vp, vp, vp],
+        "streami_field_destroy": [vp],
+        "streami_seed": [vp, i32, vp, vp, vp, i64, vp],
+        "streami_advect": [vp, vp, vp],
+        "streami_fetch_lines": [vp, i32, i64, i64, vp, vp, i64, vp, vp, vp, vp],
+        "streami_fetch_outbox": [vp, vp, i64, vp],
+        "streami_block_info": [vp, i32, vp, vp],
+        "streami_clear": [vp],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.streami_last_error.restype = ctypes.c_char_p
+    lib.streami_last_error.argtypes = []
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise StreamiError(rc, _load().streami_last_error().decode(errors="replace"))
+    return rc
+
+
+def _addr(a):
+    """(pointer, on_device) of a numpy array or torch tensor (None -> NULL)."""
+    if a is None:
+        return None, False
+    if torch is not None and isinstance(a, torch.Tensor):
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return ctypes.c_void_p(a.data_ptr()), a.is_cuda
+    if isinstance(a, np.ndarray):
+        if not a.flags["C_CONTIGUOUS"]:
+            raise ValueError("array must be C-contiguous")
+        return ctypes.c_void_p(a.ctypes.data), False
+    raise TypeError(f"unsupported array type {type(a)}")
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    if torch is not None and torch.cuda.is_available():
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(0)
+
+
+def make_block_desc(blk, nodes=None):
+    """BlockDesc from a duck-typed block (dims, ghost, origin, spacing, lo, hi, boundary,
+    rank_grid, rank_coord, n_slices, t0, slice_dt) and its stored nodes."""
+    d = BlockDesc()
+    d.dims[:] = [int(v) for v in blk.dims]
+    d.ghost = int(blk.ghost)
+    d.origin[:] = [float(v) for v in blk.origin]
+    d.spacing[:] = [float(v) for v in blk.spacing]
+    d.bounds_lo[:] = [float(v) for v in blk.lo]
+    d.bounds_hi[:] = [float(v) for v in blk.hi]
+    d.boundary = int(blk.boundary)
+    d.rank_grid[:] = [int(v) for v in blk.rank_grid]
+    d.rank_coord[:] = [int(v) for v in blk.rank_coord]
+    d.n_slices = int(blk.n_slices)
+    d.t0 = float(blk.t0)
+    d.slice_dt = float(blk.slice_dt)
+    arr = blk.stored if nodes is None else nodes
+    ptr, dev = _addr(arr)
+    d.nodes = ptr.value if ptr is not None else None
+    d.nodes_on_device = int(dev)
+    return d
+
+
+# ---------------------------------------------------------------- C-ABI calls
+def streami_field_create(descs, dtype, layout=LAYOUT_AUTO, stream=None):
+    arr = (BlockDesc * len(descs))(*descs)
+    opts = FieldOpts(layout=layout)
+    out = ctypes.c_void_p()
+    _check(_load().streami_field_create(arr, len(descs), dtype, ctypes.byref(opts), _stream(stream),
+                                        ctypes.byref(out)))
+    return out
+
+
+def streami_field_destroy(f):
+    return _check(_load().streami_field_destroy(f))
+
+
+def streami_seed(f, block, xyz, ids=None, max_steps=None, default_max_steps=0, record_stride=1,
+                 t_birth=0.0):
+    px, dx = _addr(xyz)
+    pi, di = _addr(ids)
+    pm, dm = _addr(max_steps)
+    on_dev = dx
+    if (ids is not None and di != on_dev) or (max_steps is not None and dm != on_dev):
+        raise ValueError("xyz, ids and max_steps must all be host or all device arrays")
+    n = (xyz.numel() if hasattr(xyz, "numel") else xyz.size) // 3
+    opts = SeedOpts(default_max_steps=int(default_max_steps), record_stride=int(record_stride),
+                    inputs_on_device=int(on_dev), t_birth=float(t_birth))
+    return _check(_load().streami_seed(f, int(block), px, pi, pm, int(n), ctypes.byref(opts)))
+
+
+def streami_advect(f, params: AdvectParams, want_stats=True):
+    st = Stats() if want_stats else None
+    _check(_load().streami_advect(f, ctypes.byref(params), ctypes.byref(st) if st else None))
+    return st
+
+
+def streami_fetch_lines(f, block, first, count, offsets, xyz, cap_vertices, steps=None, codes=None,
+                        ids=None):
+    needed = ctypes.c_int64()
+    rc = _load().streami_fetch_lines(f, int(block), int(first), int(count), _addr(offsets)[0],
+                                     _addr(xyz)[0], int(cap_vertices), _addr(steps)[0],
+                                     _addr(codes)[0], _addr(ids)[0], ctypes.byref(needed))
+    if rc == E_CAPACITY:
+        return rc, needed.value
+    _check(rc)
+    return rc, needed.value
+
+
+def streami_fetch_outbox(f, out, cap):
+    n = ctypes.c_int64()
+    rc = _load().streami_fetch_outbox(f, _addr(out)[0], int(cap), ctypes.byref(n))
+    if rc != E_CAPACITY:
+        _check(rc)
+    return rc, n.value
+
+
+def streami_clear(f):
+    return _check(_load().streami_clear(f))
+
+
+def streami_block_info(f, block):
+    n, v = ctypes.c_int64(), ctypes.c_int64()
+    _check(_load().streami_block_info(f, int(block), ctypes.byref(n), ctypes.byref(v)))
+    return n.value, v.value
+
+
+def advect_params(h, step_budget=0, eps=1e-6, **kw):
+    p = AdvectParams()
+    p.h = float(h)
+    p.step_budget = int(step_budget)
+    p.stagnation_eps = float(eps)
+    p.mode = kw.pop("mode", MODE_PLAIN)
+    p.mlp = kw.pop("mlp", None)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+# ---------------------------------------------------------------- convenience
+class Field:
+    """Owning wrapper around a field handle (marshalling only)."""
+
+    def __init__(self, blocks, dtype, layout=LAYOUT_AUTO, stream=None, nodes=None):
+        blocks = list(blocks)
+        nodes = nodes if nodes is not None else [None] * len(blocks)
+        self._descs = [make_block_desc(b, n) for b, n in zip(blocks, nodes)]
+        self.h = streami_field_create(self._descs, dtype, layout, stream)
+        self.n_blocks = len(blocks)
+
+    def close(self):
+        if self.h is not None and self.h.value:
+            streami_field_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def clear(self):
+        return streami_clear(self.h)
+
+    def seed(self, block, xyz, **kw):
+        return streami_seed(self.h, block, xyz, **kw)
+
+    def advect(self, h, **kw):
+        return streami_advect(self.h, advect_params(h, **kw))
+
+    def lines(self, block=0, first=0, count=None):
+        """Lines of a block in seed order (host numpy CSR)."""
+        n, _ = streami_block_info(self.h, block)
+        count = n - first if count is None else count
+        rc, need = streami_fetch_lines(self.h, block, first, count, None, None, -1)
+        off = np.zeros(count + 1, np.int64)
+        xyz = np.zeros((max(need, 1), 3), np.float32)
+        steps = np.zeros(count, np.int32)
+        codes = np.zeros(count, np.int32)
+        ids = np.zeros(count, np.uint64)
+        streami_fetch_lines(self.h, block, first, count, off, xyz, need, steps, codes, ids)
+        return dict(offsets=off, xyz=xyz[:need], steps=steps, codes=codes, ids=ids)
+
+    def outbox(self, cap=None):
+        if cap is None:
+            cap = 1 << 16
+        recs = []
+        while True:
+            buf = np.zeros(cap, OUTBOX_DTYPE)
+            rc, n = streami_fetch_outbox(self.h, buf, cap)
+            recs.append(buf[:n])
+            if rc != E_CAPACITY:
+                break
+        return np.concatenate(recs)

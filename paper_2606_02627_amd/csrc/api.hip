@@ -1,0 +1,616 @@
+// Host side of the C-ABI declared in include/streami.h: argument validation,
+// handle state, device buffer management, kernel launches, fetches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/streami.h"
+#include "device.h"
+
+namespace streami {
+int launch_advect(const AdvectArgs& a, int fmt, int layout, bool unsteady, bool cache, bool batched, int grid,
+                  hipStream_t st);
+int launch_ingest(const void* src, void* pool, const BlockDev& B, int fmt, int layout, int nx, int ny, int nz,
+                  int n_slices, hipStream_t st);
+int launch_seed(const float* xyz, const unsigned long long* ids, unsigned long long auto_id0, const int* max_steps,
+                int default_max, int stride, float t_birth, int blk, const BlockDev& B, long long first,
+                long long n, long long vbase0, float4* pos, int4* meta, int4* meta2, unsigned long long* pid,
+                long long* vbase, float* verts, OutRec* outbox, unsigned long long* outbox_count, hipStream_t st);
+int launch_pack_lines(const long long* idx, long long count, const long long* offsets, const long long* vbase,
+                      const float* verts, float* out, hipStream_t st);
+int launch_fill_u64(unsigned long long* p, long long n, unsigned long long v, hipStream_t st);
+int launch_gather_meta(const long long* idx, long long count, const int4* meta, const int4* meta2,
+                       const unsigned long long* pid, long long* nverts, int* steps, int* codes,
+                       unsigned long long* ids, hipStream_t st);
+int launch_count_codes(const int4* meta, long long n, unsigned long long* counts, hipStream_t st);
+}  // namespace streami
+
+using namespace streami;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(STREAMI_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+bool is_device_ptr(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  hipError_t e = hipPointerGetAttributes(&a, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+// A device buffer that grows by reallocation (contents preserved on `st`).
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  int reserve(size_t need, size_t keep, hipStream_t st) {
+    if (need <= bytes) return STREAMI_OK;
+    void* q = nullptr;
+    if (hipMalloc(&q, need) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(STREAMI_E_NOMEM, "device allocation of %zu bytes failed", need);
+    }
+    if (p && keep) {
+      HIP_TRY(hipMemcpyAsync(q, p, std::min(keep, bytes), hipMemcpyDeviceToDevice, st));
+      HIP_TRY(hipStreamSynchronize(st));
+    }
+    if (p) (void)hipFree(p);
+    p = q;
+    bytes = need;
+    return STREAMI_OK;
+  }
+};
+
+struct HostBlock {
+  streami_block_desc desc;
+  BlockDev dev;
+  int nx, ny, nz;  // stored nodes per axis
+  std::vector<std::pair<long long, long long>> ranges;  // (first particle, count) in seed order
+  long long n_particles = 0;
+  long long n_vert_slots = 0;
+};
+
+}  // namespace
+
+struct streami_field_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int fmt = 0, layout = LAYOUT_LINEAR;
+  bool unsteady = false;
+  int n_cu = 256;
+  std::vector<HostBlock> blocks;
+  DevBuf d_blocks, d_nodes;
+  // particles (SoA)
+  long long n_particles = 0, cap_particles = 0;
+  DevBuf d_pos, d_meta, d_meta2, d_ids, d_vbase, d_outbox;
+  DevBuf d_verts;
+  long long n_vert_slots = 0;
+  DevBuf d_ctr;        // CTR_N per-call counters + 1 persistent outbox count + 6 code counts
+  unsigned long long next_auto_id = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipGraphExec_t graph = nullptr;
+  AdvectArgs graph_args;
+  int graph_key[6] = {0, 0, 0, 0, 0, 0};
+
+  unsigned long long* ctr() { return reinterpret_cast<unsigned long long*>(d_ctr.p); }
+  unsigned long long* outbox_count() { return ctr() + CTR_N; }
+  unsigned long long* code_counts() { return ctr() + CTR_N + 1; }
+};
+
+namespace {
+
+int element_bytes(int fmt) { return fmt == STREAMI_F32 ? 12 : 6; }
+int pool_node_bytes(int fmt) { return fmt == STREAMI_F32 ? 12 : 8; }
+
+int validate_desc(const streami_block_desc& d, int i) {
+  for (int a = 0; a < 3; ++a) {
+    if (d.dims[a] < 1) return fail(STREAMI_E_ARG, "blocks[%d].dims[%d] must be >= 1", i, a);
+    if (!(d.spacing[a] > 0) || !std::isfinite(d.spacing[a]))
+      return fail(STREAMI_E_ARG, "blocks[%d].spacing[%d] must be finite and > 0", i, a);
+    if (!std::isfinite(d.origin[a])) return fail(STREAMI_E_ARG, "blocks[%d].origin[%d] not finite", i, a);
+    if (!(d.bounds_lo[a] < d.bounds_hi[a]) || !std::isfinite(d.bounds_lo[a]) || !std::isfinite(d.bounds_hi[a]))
+      return fail(STREAMI_E_ARG, "blocks[%d].bounds_lo[%d] must be < bounds_hi[%d]", i, a, a);
+    if (d.rank_grid[a] < 1) return fail(STREAMI_E_ARG, "blocks[%d].rank_grid[%d] must be >= 1", i, a);
+    if (d.rank_coord[a] < 0 || d.rank_coord[a] >= d.rank_grid[a])
+      return fail(STREAMI_E_ARG, "blocks[%d].rank_coord[%d] outside rank_grid", i, a);
+  }
+  if (d.boundary != STREAMI_BOUNDARY_BLOCK && d.boundary != STREAMI_BOUNDARY_PERIODIC)
+    return fail(STREAMI_E_ARG, "blocks[%d].boundary invalid", i);
+  if (d.ghost < 0 || d.ghost > 1) return fail(STREAMI_E_ARG, "blocks[%d].ghost must be 0 or 1", i);
+  if (d.boundary == STREAMI_BOUNDARY_PERIODIC && d.ghost != 0)
+    return fail(STREAMI_E_ARG, "blocks[%d]: a periodic block has no ghost layer", i);
+  for (int a = 0; a < 3; ++a) {
+    int ns = d.boundary == STREAMI_BOUNDARY_PERIODIC ? d.dims[a] : d.dims[a] + 2 * d.ghost;
+    if (ns < 2) return fail(STREAMI_E_ARG, "blocks[%d]: axis %d needs >= 2 stored nodes", i, a);
+  }
+  if (d.n_slices < 1) return fail(STREAMI_E_ARG, "blocks[%d].n_slices must be >= 1", i);
+  if (d.n_slices > 1 && !(d.slice_dt > 0)) return fail(STREAMI_E_ARG, "blocks[%d].slice_dt must be > 0", i);
+  if (!d.nodes) return fail(STREAMI_E_ARG, "blocks[%d].nodes is NULL", i);
+  long long nodes = (long long)(d.dims[0] + 2 * d.ghost) * (d.dims[1] + 2 * d.ghost) * (d.dims[2] + 2 * d.ghost);
+  if (nodes >= (1LL << 31)) return fail(STREAMI_E_ARG, "blocks[%d]: more than 2^31 nodes per slice", i);
+  return STREAMI_OK;
+}
+
+BlockDev make_dev(const streami_block_desc& d, int layout, long long base) {
+  BlockDev B;
+  std::memset(&B, 0, sizeof B);
+  const bool per = d.boundary == STREAMI_BOUNDARY_PERIODIC;
+  long long slice = 1;
+  for (int a = 0; a < 3; ++a) {
+    B.nst[a] = per ? d.dims[a] : d.dims[a] + 2 * d.ghost;
+    B.scale[a] = (float)(1.0 / d.spacing[a]);
+    B.offs[a] = per ? 0.0f : (float)(d.ghost - d.origin[a] / d.spacing[a]);
+    B.lo[a] = (float)d.bounds_lo[a];
+    B.hi[a] = (float)d.bounds_hi[a];
+    B.inv_ext[a] = (float)(1.0 / (d.bounds_hi[a] - d.bounds_lo[a]));
+    B.rgrid[a] = d.rank_grid[a];
+    B.rcoord[a] = d.rank_coord[a];
+    B.nb[a] = (B.nst[a] + 3) / 4;
+    slice *= layout == LAYOUT_BRICK4 ? (long long)B.nb[a] * 4 : B.nst[a];
+  }
+  // periodic blocks: origin shift folded into the position before sampling is
+  // not needed when origin = 0; otherwise keep s = (x - origin)/spacing exact
+  if (per)
+    for (int a = 0; a < 3; ++a) B.offs[a] = (float)(-d.origin[a] / d.spacing[a]);
+  B.periodic = per ? 1 : 0;
+  B.n_slices = d.n_slices;
+  B.t0 = (float)d.t0;
+  B.inv_sdt = d.n_slices > 1 ? (float)(1.0 / d.slice_dt) : 0.0f;
+  B.base = base;
+  B.slice_nodes = slice;
+  return B;
+}
+
+int ensure_particles(streami_field_s* f, long long need) {
+  if (need <= f->cap_particles) return STREAMI_OK;
+  long long cap = std::max(need, f->cap_particles + f->cap_particles / 2);
+  cap = std::max(cap, 1024LL);
+  const long long n = f->n_particles;
+  int rc;
+  if ((rc = f->d_pos.reserve(cap * sizeof(float4), n * sizeof(float4), f->stream))) return rc;
+  if ((rc = f->d_meta.reserve(cap * sizeof(int4), n * sizeof(int4), f->stream))) return rc;
+  if ((rc = f->d_meta2.reserve(cap * sizeof(int4), n * sizeof(int4), f->stream))) return rc;
+  if ((rc = f->d_ids.reserve(cap * 8, n * 8, f->stream))) return rc;
+  if ((rc = f->d_vbase.reserve(cap * 8, n * 8, f->stream))) return rc;
+  unsigned long long ob = 0;
+  HIP_TRY(hipMemcpyAsync(&ob, f->outbox_count(), 8, hipMemcpyDeviceToHost, f->stream));
+  HIP_TRY(hipStreamSynchronize(f->stream));
+  if ((rc = f->d_outbox.reserve(cap * sizeof(OutRec), ob * sizeof(OutRec), f->stream))) return rc;
+  f->cap_particles = cap;
+  return STREAMI_OK;
+}
+
+void drop_graph(streami_field_s* f) {
+  if (f->graph) (void)hipGraphExecDestroy(f->graph);
+  f->graph = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* streami_last_error(void) { return g_err.c_str(); }
+
+int streami_field_create(const streami_block_desc* blocks, int32_t n_blocks, int32_t dtype,
+                         const streami_field_opts* opts, void* hip_stream, streami_field* out) {
+  if (!out) return fail(STREAMI_E_ARG, "out is NULL");
+  if (!blocks || n_blocks < 1) return fail(STREAMI_E_ARG, "need at least one block");
+  // the batched kernel stages the block table in LDS (144 B per block, <= 64 KiB)
+  if (n_blocks > 448) return fail(STREAMI_E_UNSUPPORTED, "at most 448 blocks per handle");
+  if (dtype != STREAMI_F32 && dtype != STREAMI_F16 && dtype != STREAMI_BF16)
+    return fail(STREAMI_E_ARG, "dtype must be STREAMI_F32, STREAMI_F16 or STREAMI_BF16");
+  int layout = opts ? opts->layout : STREAMI_LAYOUT_AUTO;
+  if (layout == STREAMI_LAYOUT_AUTO) layout = STREAMI_LAYOUT_LINEAR;
+  if (layout != STREAMI_LAYOUT_LINEAR && layout != STREAMI_LAYOUT_BRICK4)
+    return fail(STREAMI_E_ARG, "unknown layout %d", layout);
+  for (int i = 0; i < n_blocks; ++i) {
+    int rc = validate_desc(blocks[i], i);
+    if (rc) return rc;
+  }
+  streami_field_s* f = new (std::nothrow) streami_field_s();
+  if (!f) return fail(STREAMI_E_NOMEM, "host allocation failed");
+  f->fmt = dtype;
+  f->layout = layout;
+  f->stream = (hipStream_t)hip_stream;
+  auto cleanup = [&](int rc) {
+    streami_field_destroy(f);
+    return rc;
+  };
+  if (hipGetDevice(&f->device) != hipSuccess) return cleanup(fail(STREAMI_E_DEVICE, "no HIP device"));
+  (void)hipDeviceGetAttribute(&f->n_cu, hipDeviceAttributeMultiprocessorCount, f->device);
+  long long base = 0;
+  f->blocks.resize(n_blocks);
+  for (int i = 0; i < n_blocks; ++i) {
+    HostBlock& hb = f->blocks[i];
+    hb.desc = blocks[i];
+    hb.dev = make_dev(blocks[i], layout, base);
+    hb.nx = hb.dev.nst[0];
+    hb.ny = hb.dev.nst[1];
+    hb.nz = hb.dev.nst[2];
+    base += hb.dev.slice_nodes * blocks[i].n_slices;
+    if (blocks[i].n_slices > 1) f->unsteady = true;
+  }
+  int rc;
+  if ((rc = f->d_nodes.reserve((size_t)base * pool_node_bytes(dtype), 0, f->stream))) return cleanup(rc);
+  if (layout == STREAMI_LAYOUT_BRICK4 || dtype != STREAMI_F32)  // padding stays zero
+    if (hipMemsetAsync(f->d_nodes.p, 0, f->d_nodes.bytes, f->stream) != hipSuccess)
+      return cleanup(fail(STREAMI_E_DEVICE, "hipMemsetAsync failed"));
+  std::vector<BlockDev> devs(n_blocks);
+  DevBuf staging;
+  for (int i = 0; i < n_blocks; ++i) {
+    HostBlock& hb = f->blocks[i];
+    devs[i] = hb.dev;
+    const size_t bytes = (size_t)hb.nx * hb.ny * hb.nz * hb.desc.n_slices * element_bytes(dtype);
+    const void* src = hb.desc.nodes;
+    if (!hb.desc.nodes_on_device) {
+      if ((rc = staging.reserve(bytes, 0, f->stream))) return cleanup(rc);
+      if (hipMemcpyAsync(staging.p, hb.desc.nodes, bytes, hipMemcpyHostToDevice, f->stream) != hipSuccess)
+        return cleanup(fail(STREAMI_E_DEVICE, "copy of blocks[%d].nodes to the device failed", i));
+      src = staging.p;
+    }
+    launch_ingest(src, f->d_nodes.p, hb.dev, dtype, layout, hb.nx, hb.ny, hb.nz, hb.desc.n_slices, f->stream);
+    if (hipGetLastError() != hipSuccess) return cleanup(fail(STREAMI_E_DEVICE, "ingest launch failed"));
+    if (!hb.desc.nodes_on_device && hipStreamSynchronize(f->stream) != hipSuccess)
+      return cleanup(fail(STREAMI_E_DEVICE, "ingest failed"));
+    hb.desc.nodes = nullptr;  // the caller keeps ownership; never read again
+  }
+  if ((rc = f->d_blocks.reserve(sizeof(BlockDev) * n_blocks, 0, f->stream))) return cleanup(rc);
+  if (hipMemcpyAsync(f->d_blocks.p, devs.data(), sizeof(BlockDev) * n_blocks, hipMemcpyHostToDevice, f->stream) !=
+      hipSuccess)
+    return cleanup(fail(STREAMI_E_DEVICE, "block table copy failed"));
+  if ((rc = f->d_ctr.reserve(sizeof(unsigned long long) * (CTR_N + 1 + 6), 0, f->stream))) return cleanup(rc);
+  launch_fill_u64(f->ctr(), CTR_N + 1 + 6, 0, f->stream);
+  if (hipEventCreate(&f->ev0) != hipSuccess || hipEventCreate(&f->ev1) != hipSuccess)
+    return cleanup(fail(STREAMI_E_DEVICE, "event creation failed"));
+  if (hipStreamSynchronize(f->stream) != hipSuccess) return cleanup(fail(STREAMI_E_DEVICE, "field upload failed"));
+  staging.release();
+  *out = f;
+  return STREAMI_OK;
+}
+
+int streami_field_destroy(streami_field f) {
+  if (!f) return STREAMI_OK;
+  (void)hipStreamSynchronize(f->stream);
+  drop_graph(f);
+  for (DevBuf* b : {&f->d_blocks, &f->d_nodes, &f->d_pos, &f->d_meta, &f->d_meta2, &f->d_ids, &f->d_vbase,
+                    &f->d_outbox, &f->d_verts, &f->d_ctr})
+    b->release();
+  if (f->ev0) (void)hipEventDestroy(f->ev0);
+  if (f->ev1) (void)hipEventDestroy(f->ev1);
+  delete f;
+  return STREAMI_OK;
+}
+
+int streami_seed(streami_field f, int32_t block, const float* xyz, const uint64_t* ids, const int32_t* max_steps,
+                 int64_t n, const streami_seed_opts* opts) {
+  if (!f) return fail(STREAMI_E_ARG, "field handle is NULL");
+  if (block < 0 || block >= (int)f->blocks.size()) return fail(STREAMI_E_ARG, "block %d out of range", block);
+  if (n < 0) return fail(STREAMI_E_ARG, "n must be >= 0");
+  if (n == 0) return STREAMI_OK;
+  if (!xyz) return fail(STREAMI_E_ARG, "xyz is NULL");
+  if (!opts) return fail(STREAMI_E_ARG, "opts is NULL");
+  if (opts->record_stride < 1) return fail(STREAMI_E_ARG, "record_stride must be >= 1");
+  if (!max_steps && opts->default_max_steps < 0) return fail(STREAMI_E_ARG, "default_max_steps must be >= 0");
+  const bool dev_in = opts->inputs_on_device != 0;
+  // per-particle limits on the host, to reserve vertex slots
+  std::vector<int32_t> ms;
+  if (max_steps) {
+    ms.resize(n);
+    if (dev_in) {
+      HIP_TRY(hipMemcpy(ms.data(), max_steps, n * 4, hipMemcpyDeviceToHost));
+    } else {
+      std::memcpy(ms.data(), max_steps, n * 4);
+    }
+    for (long long i = 0; i < n; ++i)
+      if (ms[i] < 0) return fail(STREAMI_E_ARG, "max_steps[%lld] < 0", i);
+  }
+  // vertex slots: per-particle limits need a host prefix; uniform limits are
+  // a fixed stride that the seed kernel computes itself
+  std::vector<long long> vb;
+  long long slots = f->n_vert_slots;
+  if (max_steps) {
+    vb.resize(n);
+    for (long long i = 0; i < n; ++i) {
+      vb[i] = slots;
+      slots += ms[i] / opts->record_stride + 2;
+    }
+  } else {
+    slots += n * (long long)(opts->default_max_steps / opts->record_stride + 2);
+  }
+  int rc;
+  drop_graph(f);
+  if ((rc = ensure_particles(f, f->n_particles + n))) return rc;
+  if ((size_t)slots * 12 > f->d_verts.bytes) {
+    size_t want = std::max((size_t)slots * 12, f->d_verts.bytes + f->d_verts.bytes / 4);
+    if ((rc = f->d_verts.reserve(want, (size_t)f->n_vert_slots * 12, f->stream))) return rc;
+  }
+  const long long first = f->n_particles;
+  if (max_steps)
+    HIP_TRY(hipMemcpyAsync(reinterpret_cast<long long*>(f->d_vbase.p) + first, vb.data(), n * 8,
+                           hipMemcpyHostToDevice, f->stream));
+  // stage host inputs on the device
+  DevBuf s_xyz, s_ids, s_ms;
+  const float* d_xyz = xyz;
+  const unsigned long long* d_ids = reinterpret_cast<const unsigned long long*>(ids);
+  const int* d_ms = max_steps;
+  if (!dev_in) {
+    if ((rc = s_xyz.reserve(n * 12, 0, f->stream))) return rc;
+    HIP_TRY(hipMemcpyAsync(s_xyz.p, xyz, n * 12, hipMemcpyHostToDevice, f->stream));
+    d_xyz = (const float*)s_xyz.p;
+    if (ids) {
+      if ((rc = s_ids.reserve(n * 8, 0, f->stream))) return rc;
+      HIP_TRY(hipMemcpyAsync(s_ids.p, ids, n * 8, hipMemcpyHostToDevice, f->stream));
+      d_ids = (const unsigned long long*)s_ids.p;
+    }
+    if (max_steps) {
+      if ((rc = s_ms.reserve(n * 4, 0, f->stream))) return rc;
+      HIP_TRY(hipMemcpyAsync(s_ms.p, ms.data(), n * 4, hipMemcpyHostToDevice, f->stream));
+      d_ms = (const int*)s_ms.p;
+    }
+  }
+  HostBlock& hb = f->blocks[block];
+  launch_seed(d_xyz, d_ids, f->next_auto_id, d_ms, opts->default_max_steps, opts->record_stride, opts->t_birth,
+              block, hb.dev, first, n, f->n_vert_slots, (float4*)f->d_pos.p, (int4*)f->d_meta.p,
+              (int4*)f->d_meta2.p, (unsigned long long*)f->d_ids.p, (long long*)f->d_vbase.p,
+              (float*)f->d_verts.p, (OutRec*)f->d_outbox.p, f->outbox_count(), f->stream);
+  HIP_TRY(hipGetLastError());
+  if (!dev_in || max_steps) HIP_TRY(hipStreamSynchronize(f->stream));  // staging buffers are freed on return
+  if (!ids) f->next_auto_id += (unsigned long long)n;
+  f->n_particles += n;
+  f->n_vert_slots = slots;
+  hb.ranges.push_back({first, n});
+  hb.n_particles += n;
+  return STREAMI_OK;
+}
+
+int streami_advect(streami_field f, const streami_advect_params* p, streami_stats* stats) {
+  if (!f) return fail(STREAMI_E_ARG, "field handle is NULL");
+  if (!p) return fail(STREAMI_E_ARG, "params is NULL");
+  if (!(p->h > 0) || !std::isfinite(p->h)) return fail(STREAMI_E_ARG, "h must be finite and > 0");
+  if (p->step_budget < 0) return fail(STREAMI_E_ARG, "step_budget must be >= 0");
+  if (!(p->stagnation_eps >= 0)) return fail(STREAMI_E_ARG, "stagnation_eps must be >= 0");
+  if (p->mode == STREAMI_MODE_SURROGATE) return fail(STREAMI_E_UNSUPPORTED, "surrogate mode needs a network");
+  if (p->mode != STREAMI_MODE_PLAIN) return fail(STREAMI_E_ARG, "unknown mode %d", p->mode);
+  if (p->waves_per_cu < 0 || p->waves_per_cu > 64) return fail(STREAMI_E_ARG, "waves_per_cu must be in [0,64]");
+  if (p->refill_threshold < 0 || p->refill_threshold > 64)
+    return fail(STREAMI_E_ARG, "refill_threshold must be in [0,64]");
+  if (f->n_particles == 0) return fail(STREAMI_E_STATE, "no particles seeded");
+  AdvectArgs a;
+  a.blocks = (const BlockDev*)f->d_blocks.p;
+  a.n_blocks = (int)f->blocks.size();
+  a.nodes = f->d_nodes.p;
+  a.pos = (float4*)f->d_pos.p;
+  a.meta = (int4*)f->d_meta.p;
+  a.meta2 = (const int4*)f->d_meta2.p;
+  a.ids = (const unsigned long long*)f->d_ids.p;
+  a.vbase = (const long long*)f->d_vbase.p;
+  a.verts = (float*)f->d_verts.p;
+  a.outbox = (OutRec*)f->d_outbox.p;
+  a.outbox_count = f->outbox_count();
+  a.ctr = f->ctr();
+  a.n_particles = f->n_particles;
+  a.h = p->h;
+  a.eps2 = p->stagnation_eps * p->stagnation_eps;
+  a.budget = p->step_budget;
+  a.refill = p->refill_threshold > 0 ? p->refill_threshold : 16;
+  const int wpc = p->waves_per_cu > 0 ? p->waves_per_cu : 32;
+  long long grid = (long long)f->n_cu * wpc / 4;
+  grid = std::min(grid, (f->n_particles + 255) / 256);
+  grid = std::max(grid, 1LL);
+  const bool batched = f->blocks.size() > 1;
+  const bool cache = !f->unsteady && !p->no_cell_cache;
+  HIP_TRY(hipEventRecord(f->ev0, f->stream));
+  if (p->use_graph) {
+    const int key[6] = {(int)grid, a.refill, a.budget, cache ? 1 : 0, (int)(p->h * 1e6f), 1};
+    bool same = f->graph && std::memcmp(key, f->graph_key, sizeof key) == 0 &&
+                std::memcmp(&a, &f->graph_args, sizeof a) == 0;
+    if (!same) {
+      drop_graph(f);
+      hipStream_t cs;
+      HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+      hipGraph_t g;
+      HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      launch_fill_u64(a.ctr, CTR_N, 0, cs);
+      launch_advect(a, f->fmt, f->layout, f->unsteady, cache, batched, (int)grid, cs);
+      HIP_TRY(hipStreamEndCapture(cs, &g));
+      HIP_TRY(hipGraphInstantiate(&f->graph, g, nullptr, nullptr, 0));
+      (void)hipGraphDestroy(g);
+      (void)hipStreamDestroy(cs);
+      std::memcpy(f->graph_key, key, sizeof key);
+      f->graph_args = a;
+    }
+    HIP_TRY(hipGraphLaunch(f->graph, f->stream));
+  } else {
+    launch_fill_u64(a.ctr, CTR_N, 0, f->stream);
+    launch_advect(a, f->fmt, f->layout, f->unsteady, cache, batched, (int)grid, f->stream);
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipEventRecord(f->ev1, f->stream));
+  if (stats) {
+    launch_fill_u64(f->code_counts(), 6, 0, f->stream);
+    launch_count_codes((const int4*)f->d_meta.p, f->n_particles, f->code_counts(), f->stream);
+    unsigned long long h[CTR_N + 1 + 6];
+    HIP_TRY(hipMemcpyAsync(h, f->ctr(), sizeof h, hipMemcpyDeviceToHost, f->stream));
+    HIP_TRY(hipStreamSynchronize(f->stream));
+    std::memset(stats, 0, sizeof *stats);
+    stats->steps = (int64_t)h[CTR_STEPS];
+    stats->vertices = (int64_t)h[CTR_VERTS];
+    stats->surrogate_accepted = (int64_t)h[CTR_ACCEPT];
+    stats->surrogate_fallback = (int64_t)h[CTR_FALLBACK];
+    stats->outbox = (int64_t)h[CTR_N];
+    for (int k = 0; k < 6; ++k) stats->terminated[k] = (int64_t)h[CTR_N + 1 + k];
+    stats->active = stats->terminated[0];
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, f->ev0, f->ev1));
+    stats->device_ms = ms;
+  }
+  return STREAMI_OK;
+}
+
+int streami_clear(streami_field f) {
+  if (!f) return fail(STREAMI_E_ARG, "field handle is NULL");
+  drop_graph(f);
+  f->n_particles = 0;
+  f->n_vert_slots = 0;
+  f->next_auto_id = 0;
+  for (auto& hb : f->blocks) {
+    hb.ranges.clear();
+    hb.n_particles = 0;
+  }
+  launch_fill_u64(f->outbox_count(), 1, 0, f->stream);
+  HIP_TRY(hipGetLastError());
+  return STREAMI_OK;
+}
+
+int streami_block_info(streami_field f, int32_t block, int64_t* n_particles, int64_t* n_vertices) {
+  if (!f) return fail(STREAMI_E_ARG, "field handle is NULL");
+  if (block < 0 || block >= (int)f->blocks.size()) return fail(STREAMI_E_ARG, "block %d out of range", block);
+  if (n_particles) *n_particles = f->blocks[block].n_particles;
+  if (n_vertices) {
+    int64_t needed = 0;
+    int rc = streami_fetch_lines(f, block, 0, f->blocks[block].n_particles, nullptr, nullptr, -1, nullptr, nullptr,
+                                 nullptr, &needed);
+    if (rc != STREAMI_OK && rc != STREAMI_E_CAPACITY) return rc;
+    *n_vertices = needed;
+  }
+  return STREAMI_OK;
+}
+
+int streami_fetch_lines(streami_field f, int32_t block, int64_t first, int64_t count, int64_t* offsets, float* xyz,
+                        int64_t cap_vertices, int32_t* steps, int32_t* codes, uint64_t* ids,
+                        int64_t* needed_vertices) {
+  if (!f) return fail(STREAMI_E_ARG, "field handle is NULL");
+  if (block < 0 || block >= (int)f->blocks.size()) return fail(STREAMI_E_ARG, "block %d out of range", block);
+  HostBlock& hb = f->blocks[block];
+  if (first < 0 || count < 0 || first + count > hb.n_particles)
+    return fail(STREAMI_E_ARG, "range [%lld, %lld) outside the block's %lld particles", (long long)first,
+                (long long)(first + count), (long long)hb.n_particles);
+  // seed-order index list of the range
+  std::vector<long long> idx;
+  idx.reserve(count);
+  long long skip = first;
+  for (auto& r : hb.ranges) {
+    if ((long long)idx.size() >= count) break;
+    if (skip >= r.second) {
+      skip -= r.second;
+      continue;
+    }
+    for (long long k = skip; k < r.second && (long long)idx.size() < count; ++k) idx.push_back(r.first + k);
+    skip = 0;
+  }
+  int rc;
+  DevBuf d_idx, d_nv, d_steps, d_codes, d_ids, d_off;
+  const long long c = std::max<long long>(count, 1);
+  if ((rc = d_idx.reserve(c * 8, 0, f->stream)) || (rc = d_nv.reserve(c * 8, 0, f->stream)) ||
+      (rc = d_steps.reserve(c * 4, 0, f->stream)) || (rc = d_codes.reserve(c * 4, 0, f->stream)) ||
+      (rc = d_ids.reserve(c * 8, 0, f->stream)))
+    return rc;
+  std::vector<long long> nv(count);
+  std::vector<int32_t> h_steps(count), h_codes(count);
+  std::vector<unsigned long long> h_ids(count);
+  if (count > 0) {
+    HIP_TRY(hipMemcpyAsync(d_idx.p, idx.data(), count * 8, hipMemcpyHostToDevice, f->stream));
+    launch_gather_meta((const long long*)d_idx.p, count, (const int4*)f->d_meta.p, (const int4*)f->d_meta2.p,
+                       (const unsigned long long*)f->d_ids.p, (long long*)d_nv.p, (int*)d_steps.p,
+                       (int*)d_codes.p, (unsigned long long*)d_ids.p, f->stream);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(nv.data(), d_nv.p, count * 8, hipMemcpyDeviceToHost, f->stream));
+    HIP_TRY(hipMemcpyAsync(h_steps.data(), d_steps.p, count * 4, hipMemcpyDeviceToHost, f->stream));
+    HIP_TRY(hipMemcpyAsync(h_codes.data(), d_codes.p, count * 4, hipMemcpyDeviceToHost, f->stream));
+    HIP_TRY(hipMemcpyAsync(h_ids.data(), d_ids.p, count * 8, hipMemcpyDeviceToHost, f->stream));
+    HIP_TRY(hipStreamSynchronize(f->stream));
+  }
+  std::vector<long long> off(count + 1);
+  off[0] = 0;
+  for (long long i = 0; i < count; ++i) off[i + 1] = off[i] + nv[i];
+  if (needed_vertices) *needed_vertices = off[count];
+  if (cap_vertices < off[count])
+    return fail(STREAMI_E_CAPACITY, "need %lld vertices, capacity %lld", (long long)off[count], (long long)cap_vertices);
+  if (!offsets || (!xyz && off[count] > 0)) return fail(STREAMI_E_ARG, "offsets/xyz is NULL");
+  auto put = [&](void* dst, const void* src, size_t bytes) -> int {
+    if (!dst || bytes == 0) return STREAMI_OK;
+    HIP_TRY(hipMemcpyAsync(dst, src, bytes, is_device_ptr(dst) ? hipMemcpyHostToDevice : hipMemcpyHostToHost,
+                           f->stream));
+    return STREAMI_OK;
+  };
+  if ((rc = put(offsets, off.data(), (count + 1) * 8))) return rc;
+  if ((rc = put(steps, h_steps.data(), count * 4))) return rc;
+  if ((rc = put(codes, h_codes.data(), count * 4))) return rc;
+  if ((rc = put(ids, h_ids.data(), count * 8))) return rc;
+  if (off[count] > 0) {
+    if ((rc = d_off.reserve((count + 1) * 8, 0, f->stream))) return rc;
+    HIP_TRY(hipMemcpyAsync(d_off.p, off.data(), (count + 1) * 8, hipMemcpyHostToDevice, f->stream));
+    if (is_device_ptr(xyz)) {
+      launch_pack_lines((const long long*)d_idx.p, count, (const long long*)d_off.p, (const long long*)f->d_vbase.p,
+                        (const float*)f->d_verts.p, xyz, f->stream);
+      HIP_TRY(hipGetLastError());
+    } else {
+      DevBuf tmp;
+      if ((rc = tmp.reserve(off[count] * 12, 0, f->stream))) return rc;
+      launch_pack_lines((const long long*)d_idx.p, count, (const long long*)d_off.p, (const long long*)f->d_vbase.p,
+                        (const float*)f->d_verts.p, (float*)tmp.p, f->stream);
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(hipMemcpyAsync(xyz, tmp.p, off[count] * 12, hipMemcpyDeviceToHost, f->stream));
+      HIP_TRY(hipStreamSynchronize(f->stream));
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(f->stream));
+  return STREAMI_OK;
+}
+
+int streami_fetch_outbox(streami_field f, streami_outbox_rec* out, int64_t cap, int64_t* n_out) {
+  if (!f) return fail(STREAMI_E_ARG, "field handle is NULL");
+  if (!n_out) return fail(STREAMI_E_ARG, "n_out is NULL");
+  if (cap < 0) return fail(STREAMI_E_ARG, "cap must be >= 0");
+  unsigned long long cnt = 0;
+  HIP_TRY(hipMemcpyAsync(&cnt, f->outbox_count(), 8, hipMemcpyDeviceToHost, f->stream));
+  HIP_TRY(hipStreamSynchronize(f->stream));
+  long long take = std::min<long long>((long long)cnt, cap);
+  *n_out = take;
+  if (take > 0) {
+    if (!out) return fail(STREAMI_E_ARG, "out is NULL");
+    // hand out the tail so that the remaining records stay contiguous at the front
+    const OutRec* src = reinterpret_cast<const OutRec*>(f->d_outbox.p) + (cnt - take);
+    HIP_TRY(hipMemcpyAsync(out, src, take * sizeof(OutRec),
+                           is_device_ptr(out) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, f->stream));
+    unsigned long long rest = cnt - take;
+    HIP_TRY(hipMemcpyAsync(f->outbox_count(), &rest, 8, hipMemcpyHostToDevice, f->stream));
+    HIP_TRY(hipStreamSynchronize(f->stream));
+  }
+  if ((long long)cnt > take) return fail(STREAMI_E_CAPACITY, "%lld records remain in the outbox", (long long)(cnt - take));
+  return STREAMI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// Device-side data structures shared by the library's kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace streami {
+
+enum Fmt { FMT_F32 = 0, FMT_F16 = 1, FMT_BF16 = 2 };
+enum Layout { LAYOUT_LINEAR = 1, LAYOUT_BRICK4 = 2 };
+enum Code { ACTIVE = 0, MAX_STEPS = 1, EXIT = 2, STAGNANT = 3, HALO_MISS = 4, NONFINITE = 5 };
+
+// One block as the kernels see it.  Storage coordinate along an axis:
+// s = x*scale + offs  (= (x - origin)/spacing + ghost).
+struct alignas(16) BlockDev {
+  float scale[3];
+  float offs[3];
+  int nst[3];        // stored nodes per axis (periodic: interior nodes)
+  int periodic;
+  float lo[3];
+  float hi[3];
+  float inv_ext[3];  // 1/(hi - lo) for destinationID
+  int rgrid[3];
+  int rcoord[3];
+  int n_slices;
+  float t0;
+  float inv_sdt;     // 1/slice_dt
+  int nb[3];         // bricks per axis (brick layout)
+  int pad0;
+  long long base;    // node index of slice 0 of this block in the node pool
+  long long slice_nodes;
+};
+
+// Outbox record, 32 bytes (same layout as streami_outbox_rec).
+struct alignas(8) OutRec {
+  unsigned long long id;
+  float pos[3];
+  int steps;
+  int dest;
+  short code;
+  short block;
+};
+static_assert(sizeof(OutRec) == 32, "outbox record must be 32 bytes");
+
+// Per-call counters (zeroed by a fill kernel before each advect launch).
+enum Counter { CTR_QUEUE = 0, CTR_STEPS = 1, CTR_VERTS = 2, CTR_ACCEPT = 3, CTR_FALLBACK = 4, CTR_N = 8 };
+
+struct AdvectArgs {
+  const BlockDev* blocks;   // [n_blocks]
+  int n_blocks;
+  const void* nodes;        // node pool (format and layout fixed per handle)
+  float4* pos;              // x, y, z, t_birth
+  int4* meta;               // steps, max_steps, code, n_verts
+  const int4* meta2;        // stride, block, vcap, 0
+  const unsigned long long* ids;
+  const long long* vbase;   // first vertex slot of each particle
+  float* verts;             // vertex pool, 3 floats per vertex
+  OutRec* outbox;
+  unsigned long long* outbox_count;  // persistent across calls
+  unsigned long long* ctr;           // per-call counters
+  long long n_particles;
+  float h;
+  float eps2;               // stagnation_eps^2
+  int budget;               // 0 = unlimited
+  int refill;               // free lanes that trigger a refill
+};
+
+// Per-axis offsets of node i within a slice of a block.
+template <int LAYOUT>
+__device__ __forceinline__ int ax_off(const BlockDev& B, int i) {
+  if (LAYOUT == LAYOUT_BRICK4) return ((i >> 2) << 6) + (i & 3);
+  return i;
+}
+template <int LAYOUT>
+__device__ __forceinline__ int ay_off(const BlockDev& B, int j) {
+  if (LAYOUT == LAYOUT_BRICK4) return (j >> 2) * (B.nb[0] << 6) + ((j & 3) << 2);
+  return j * B.nst[0];
+}
+template <int LAYOUT>
+__device__ __forceinline__ int az_off(const BlockDev& B, int k) {
+  if (LAYOUT == LAYOUT_BRICK4) return (k >> 2) * ((B.nb[0] * B.nb[1]) << 6) + ((k & 3) << 4);
+  return k * (B.nst[0] * B.nst[1]);
+}
+
+}  // namespace streami

@@ -1,0 +1,209 @@
+// Field ingest (node re-layout), particle seeding, line packing and small fill
+// kernels.  Ingest copies the caller's x-fastest node array into the library's
+// node pool in the handle's layout; 16-bit nodes are padded to 8 bytes so a
+// node is one aligned 64-bit load in the advection kernel.
+#include "device.h"
+
+namespace streami {
+
+template <int FMT, int LAYOUT>
+__global__ void k_ingest(const void* src, void* pool, BlockDev B, int nx, int ny, int nz, int n_slices) {
+  const long long per_slice = (long long)nx * ny * nz;
+  const long long total = per_slice * n_slices;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
+       t += (long long)gridDim.x * blockDim.x) {
+    const long long s = t / per_slice;
+    long long r = t - s * per_slice;
+    const int k = (int)(r / ((long long)nx * ny));
+    r -= (long long)k * nx * ny;
+    const int j = (int)(r / nx);
+    const int i = (int)(r - (long long)j * nx);
+    const long long dst = B.base + s * B.slice_nodes + ax_off<LAYOUT>(B, i) + ay_off<LAYOUT>(B, j) +
+                          az_off<LAYOUT>(B, k);
+    if (FMT == FMT_F32) {
+      const float* a = reinterpret_cast<const float*>(src) + t * 3;
+      float* b = reinterpret_cast<float*>(pool) + dst * 3;
+      b[0] = a[0]; b[1] = a[1]; b[2] = a[2];
+    } else {
+      const unsigned short* a = reinterpret_cast<const unsigned short*>(src) + t * 3;
+      uint2 w;
+      w.x = (unsigned)a[0] | ((unsigned)a[1] << 16);
+      w.y = (unsigned)a[2];
+      reinterpret_cast<uint2*>(pool)[dst] = w;
+    }
+  }
+}
+
+int launch_ingest(const void* src, void* pool, const BlockDev& B, int fmt, int layout, int nx, int ny,
+                  int nz, int n_slices, hipStream_t st) {
+  const long long total = (long long)nx * ny * nz * n_slices;
+  int grid = (int)((total + 255) / 256);
+  if (grid > 65536) grid = 65536;
+  if (grid < 1) grid = 1;
+#define STREAMI_INGEST(F, L) hipLaunchKernelGGL((k_ingest<F, L>), dim3(grid), dim3(256), 0, st, src, pool, B, nx, ny, nz, n_slices)
+  if (layout == LAYOUT_BRICK4) {
+    if (fmt == FMT_F32) STREAMI_INGEST(FMT_F32, LAYOUT_BRICK4); else STREAMI_INGEST(FMT_F16, LAYOUT_BRICK4);
+  } else {
+    if (fmt == FMT_F32) STREAMI_INGEST(FMT_F32, LAYOUT_LINEAR); else STREAMI_INGEST(FMT_F16, LAYOUT_LINEAR);
+  }
+#undef STREAMI_INGEST
+  return 0;
+}
+
+// Initialise n particles at [first, first+n): positions, ids, limits; record
+// the seed as vertex 0 at the slot base the host reserved (vbase[q]); a seed
+// outside the owned bounds of a non-periodic block ends at once (EXIT, 0
+// steps) and goes to the outbox.
+__global__ void k_seed(const float* xyz, const unsigned long long* ids, unsigned long long auto_id0,
+                       const int* max_steps, int default_max, int stride, float t_birth, int blk,
+                       BlockDev B, long long first, long long n, long long vbase0, float4* pos, int4* meta,
+                       int4* meta2, unsigned long long* pid, long long* vbase, float* verts, OutRec* outbox,
+                       unsigned long long* outbox_count) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  bool emit = false;
+  const long long q = first + i;
+  float3 x = make_float3(0.f, 0.f, 0.f);
+  unsigned long long id = 0;
+  if (i < n) {
+    x = make_float3(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]);
+    id = ids ? ids[i] : auto_id0 + (unsigned long long)i;
+    const int m = max_steps ? max_steps[i] : default_max;
+    bool out = false;
+    if (!B.periodic)
+      out = !(x.x >= B.lo[0] && x.x < B.hi[0] && x.y >= B.lo[1] && x.y < B.hi[1] && x.z >= B.lo[2] &&
+              x.z < B.hi[2]);
+    pos[q] = make_float4(x.x, x.y, x.z, t_birth);
+    meta[q] = make_int4(0, m, out ? EXIT : ACTIVE, 1);
+    meta2[q] = make_int4(stride, blk, m / stride + 2, 0);
+    pid[q] = id;
+    // uniform limits: slots are a fixed stride from vbase0; otherwise the host
+    // has reserved them (prefix over the batch) in vbase[]
+    const long long vb = max_steps ? vbase[q] : vbase0 + i * (long long)(m / stride + 2);
+    if (!max_steps) vbase[q] = vb;
+    float* w = verts + vb * 3;
+    w[0] = x.x; w[1] = x.y; w[2] = x.z;
+    emit = out;
+  }
+  const unsigned long long em = __ballot(emit);
+  if (em) {
+    const int lane = __lane_id();
+    const int leader = __ffsll((long long)em) - 1;
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(outbox_count, (unsigned long long)__popcll(em));
+    base = __shfl(base, leader, 64);
+    if (emit) {
+      const unsigned below = __builtin_amdgcn_mbcnt_hi((unsigned)(em >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)em, 0u));
+      int r0 = B.rcoord[0] + (int)floorf((x.x - B.lo[0]) * B.inv_ext[0]);
+      int r1 = B.rcoord[1] + (int)floorf((x.y - B.lo[1]) * B.inv_ext[1]);
+      int r2 = B.rcoord[2] + (int)floorf((x.z - B.lo[2]) * B.inv_ext[2]);
+      int dest = (r0 < 0 || r0 >= B.rgrid[0] || r1 < 0 || r1 >= B.rgrid[1] || r2 < 0 || r2 >= B.rgrid[2])
+                     ? -1 : r0 + B.rgrid[0] * (r1 + B.rgrid[1] * r2);
+      OutRec r;
+      r.id = id;
+      r.pos[0] = x.x; r.pos[1] = x.y; r.pos[2] = x.z;
+      r.steps = 0;
+      r.dest = dest;
+      r.code = (short)EXIT;
+      r.block = (short)blk;
+      outbox[base + below] = r;
+    }
+  }
+}
+
+int launch_seed(const float* xyz, const unsigned long long* ids, unsigned long long auto_id0,
+                const int* max_steps, int default_max, int stride, float t_birth, int blk, const BlockDev& B,
+                long long first, long long n, long long vbase0, float4* pos, int4* meta, int4* meta2,
+                unsigned long long* pid, long long* vbase, float* verts, OutRec* outbox,
+                unsigned long long* outbox_count, hipStream_t st) {
+  if (n <= 0) return 0;
+  const long long grid = (n + 255) / 256;
+  hipLaunchKernelGGL(k_seed, dim3((unsigned)grid), dim3(256), 0, st, xyz, ids, auto_id0, max_steps, default_max,
+                     stride, t_birth, blk, B, first, n, vbase0, pos, meta, meta2, pid, vbase, verts, outbox,
+                     outbox_count);
+  return 0;
+}
+
+// Copy the recorded vertices of particles idx[0..count) into CSR rows.
+__global__ void k_pack_lines(const long long* idx, long long count, const long long* offsets,
+                             const long long* vbase, const float* verts, float* out) {
+  const long long r = blockIdx.x;  // one workgroup per particle row (grid-stride)
+  for (long long row = r; row < count; row += gridDim.x) {
+    const long long q = idx[row];
+    const long long o = offsets[row], nvert = offsets[row + 1] - o;
+    const float* src = verts + vbase[q] * 3;
+    float* dst = out + o * 3;
+    for (long long e = threadIdx.x; e < nvert * 3; e += blockDim.x) dst[e] = src[e];
+  }
+}
+
+int launch_pack_lines(const long long* idx, long long count, const long long* offsets, const long long* vbase,
+                      const float* verts, float* out, hipStream_t st) {
+  if (count <= 0) return 0;
+  int grid = (int)(count < 65536 ? count : 65536);
+  hipLaunchKernelGGL(k_pack_lines, dim3(grid), dim3(256), 0, st, idx, count, offsets, vbase, verts, out);
+  return 0;
+}
+
+__global__ void k_fill_u64(unsigned long long* p, long long n, unsigned long long v) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+int launch_fill_u64(unsigned long long* p, long long n, unsigned long long v, hipStream_t st) {
+  int grid = (int)((n + 255) / 256);
+  if (grid > 4096) grid = 4096;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid), dim3(256), 0, st, p, n, v);
+  return 0;
+}
+
+// Per-particle line metadata of a range: n_verts (clamped to capacity), steps, codes, ids.
+__global__ void k_gather_meta(const long long* idx, long long count, const int4* meta, const int4* meta2,
+                              const unsigned long long* pid, long long* nverts, int* steps, int* codes,
+                              unsigned long long* ids) {
+  for (long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x; r < count;
+       r += (long long)gridDim.x * blockDim.x) {
+    const long long q = idx[r];
+    const int4 mt = meta[q];
+    const int vcap = meta2[q].z;
+    nverts[r] = mt.w < vcap ? mt.w : vcap;
+    steps[r] = mt.x;
+    codes[r] = mt.z;
+    ids[r] = pid[q];
+  }
+}
+
+int launch_gather_meta(const long long* idx, long long count, const int4* meta, const int4* meta2,
+                       const unsigned long long* pid, long long* nverts, int* steps, int* codes,
+                       unsigned long long* ids, hipStream_t st) {
+  if (count <= 0) return 0;
+  int grid = (int)((count + 255) / 256);
+  if (grid > 4096) grid = 4096;
+  hipLaunchKernelGGL(k_gather_meta, dim3(grid), dim3(256), 0, st, idx, count, meta, meta2, pid, nverts, steps,
+                     codes, ids);
+  return 0;
+}
+
+// Per-code particle counts (stats), wave-aggregated atomics.
+__global__ void k_count_codes(const int4* meta, long long n, unsigned long long* counts) {
+  unsigned long long c[6] = {0, 0, 0, 0, 0, 0};
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const int z = meta[i].z;
+    if (z >= 0 && z < 6) c[z]++;
+  }
+  for (int k = 0; k < 6; ++k) {
+    unsigned long long v = c[k];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (__lane_id() == 0 && v) atomicAdd(&counts[k], v);
+  }
+}
+
+int launch_count_codes(const int4* meta, long long n, unsigned long long* counts, hipStream_t st) {
+  int grid = (int)((n + 255) / 256);
+  if (grid > 2048) grid = 2048;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(k_count_codes, dim3(grid), dim3(256), 0, st, meta, n, counts);
+  return 0;
+}
+
+}  // namespace streami

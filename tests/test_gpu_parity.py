@@ -1,0 +1,342 @@
+"""GPU (gfx950) parity of the advection path against the FP64 oracle.
+
+Every test calls the HIP library through its C-ABI binding and compares with
+the oracle on the same stored node values; see tests/parity.py for the
+contract.  Sizes span several tiles of the launch (many waves and workgroups)
+with ragged tails; the full-size turbulence case runs the exact launch
+configuration the benchmark times.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import fieldgen as fg
+import oracle
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+FMT_TO_ORC = {fg.F32: oracle.FMT_F32, fg.F16: oracle.FMT_F16, fg.BF16: oracle.FMT_BF16}
+
+
+def note(*a):
+    print("[gpu-case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2606_02627_amd as S
+    S._load()
+    return S
+
+
+def run(S, blocks, seeds_per_block, h, max_steps, dtype, layout=0, eps=1e-6, stride=1, **adv):
+    """Seed every block, advect to completion, return (field, lines per block, outbox, stats)."""
+    f = S.Field(blocks, dtype, layout=layout)
+    for b, sd in enumerate(seeds_per_block):
+        ms = max_steps[b] if isinstance(max_steps, list) else max_steps
+        if isinstance(ms, np.ndarray):
+            f.seed(b, np.ascontiguousarray(sd, np.float32), max_steps=ms.astype(np.int32),
+                   record_stride=stride, t_birth=adv.pop("t_birth", 0.0) if b == 0 else 0.0)
+        else:
+            f.seed(b, np.ascontiguousarray(sd, np.float32), default_max_steps=int(ms),
+                   record_stride=stride)
+    budget = adv.pop("chunk", 0)
+    if budget:
+        while True:
+            st = f.advect(h, step_budget=budget, eps=eps, **adv)
+            if st.active == 0:
+                break
+    else:
+        st = f.advect(h, eps=eps, **adv)
+    lines = [f.lines(b) for b in range(len(blocks))]
+    ob = f.outbox()
+    return f, lines, ob, st
+
+
+def orc_field(blk):
+    return oracle.Field.from_block(blk)
+
+
+# ---------------------------------------------------------------- closed forms
+def test_uniform_flow_bit_exact(S):
+    """Dyadic uniform flow: the FP32 kernel reproduces P0 + n h c exactly, and the exit step,
+    outbox position and destination rank exactly."""
+    note("uniform flow")
+    c = (0.375, -0.25, 0.125)
+    blk = fg.closed_form_block(lambda x, y, z: (0 * x + c[0], 0 * x + c[1], 0 * x + c[2]),
+                               (9, 9, 9), ghost=1, origin=(0.5, 0.5, 0.5), lo=(0, 0, 0),
+                               hi=(9, 9, 9), rank_grid=(3, 3, 3), rank_coord=(1, 1, 1))
+    rng = np.random.default_rng(1)
+    seeds = (rng.integers(0, 9 * 64, size=(777, 3)) / 64.0).astype(np.float32)
+    for layout in (S.LAYOUT_LINEAR, S.LAYOUT_BRICK4):
+        f, lines, ob, st = run(S, [blk], [seeds], 0.5, 1000, fg.F32, layout=layout)
+        segs = parity.split_lines(lines[0])
+        for i, s in enumerate(segs):
+            n = len(s) - 1
+            path = seeds[i].astype(np.float64) + np.arange(n + 1)[:, None] * 0.5 * np.array(c)
+            np.testing.assert_array_equal(s, path)
+            k = np.arange(1, 1000)
+            pos = seeds[i] + k[:, None] * 0.5 * np.array(c)
+            assert n == k[np.any((pos < 0) | (pos >= 9), axis=1)][0]
+        assert (lines[0]["codes"] == S.EXIT).all()
+        ref = orc_field(blk).trace(seeds, 0.5, 1000)
+        srt = np.sort(ob, order="id")
+        assert len(srt) == len(seeds)
+        np.testing.assert_array_equal(srt["dest"], ref["out_dest"])
+        np.testing.assert_array_equal(srt["pos"].astype(np.float64), ref["out_pos"])
+        np.testing.assert_array_equal(srt["steps"], ref["steps"])
+
+
+def test_solid_body_rotation_closed_form(S):
+    """v = w(-(y-3), x-3, 0) lies in the trilinear span: vertices follow R(hA)^n exactly up
+    to FP32 rounding (circles shrinking by the RK4 radius factor)."""
+    note("rotation")
+    w = 0.7
+    blk = fg.closed_form_block(lambda x, y, z: (-w * (y - 3.0), w * (x - 3.0), 0 * z), (7, 7, 4),
+                               ghost=1, origin=(0, 0, 0), lo=(-1, -1, -1), hi=(100, 100, 100))
+    seeds = np.array([[4.5, 3.0, 1.0], [3.0, 1.2, 2.0], [1.7, 3.9, 0.5]], np.float32)
+    h, steps = 0.4, 120
+    f, lines, ob, st = run(S, [blk], [seeds], h, steps, fg.F32)
+    Z = h * np.array([[0, -w, 0], [w, 0, 0], [0, 0, 0]])
+    R = np.eye(3) + Z + Z @ Z / 2 + Z @ Z @ Z / 6 + Z @ Z @ Z @ Z / 24
+    xc = np.array([3.0, 3.0, 0.0])
+    for i, s in enumerate(parity.split_lines(lines[0])):
+        assert len(s) == steps + 1
+        q = seeds[i].astype(np.float64) - xc
+        for n in range(steps + 1):
+            assert np.abs(s[n] - xc - q).max() < 2e-5
+            q = R @ q
+
+
+# ---------------------------------------------------------------- ABC (config 1)
+def test_abc_periodic_full(S):
+    """ABC flow on a 32^3 periodic grid, 1024 seeds, h=0.01, 200 steps: every vertex within
+    1e-4 of the 2pi extent of the oracle; per-step check on every vertex; codes exact."""
+    note("abc 32^3 full")
+    blk = fg.abc_block(32)
+    seeds = fg.uniform_seeds(1, 1024, (0, 0, 0), (2 * np.pi,) * 3)
+    f, lines, ob, st = run(S, [blk], [seeds], 0.01, 200, fg.F32)
+    F = orc_field(blk)
+    ref = F.trace(seeds, float(np.float32(0.01)), 200)
+    ext = 2 * np.pi
+    ratio, npairs = parity.local_check(F, lines[0], 0.01, ext)
+    assert npairs == 1024 * 200 and ratio <= 1.0, ratio
+    dev, same = parity.global_compare(lines[0], ref, 1024)
+    assert same.all() and dev.max() <= 1e-4 * ext, dev.max()
+    assert (lines[0]["steps"] == 200).all() and (lines[0]["codes"] == S.MAX_STEPS).all()
+    assert st.steps == 1024 * 200 and len(ob) == 0
+
+
+# ---------------------------------------------------------------- turbulence blocks
+@pytest.mark.parametrize("dtype", [fg.F32, fg.BF16, fg.F16])
+@pytest.mark.parametrize("layout", [1, 2])
+def test_turbulence_block_parity(S, dtype, layout):
+    """A 40^3 turbulence block (+ghost), 3000 seeds (ragged vs 256-lane workgroups), h=0.5,
+    up to 400 steps: local check on every vertex, discrete results exact away from the
+    boundary, outbox records equal to the oracle's (sorted by id)."""
+    note("turbulence 40^3", fg.DTYPE_NAMES[dtype], "layout", layout)
+    blk = fg.turbulence_block(2, edge=40, fmt=dtype, rank_grid=(3, 3, 3), rank_coord=(1, 1, 1))
+    seeds = fg.uniform_seeds(2, 3000, (0, 0, 0), (40, 40, 40), sub=7)
+    f, lines, ob, st = run(S, [blk], [seeds], 0.5, 400, dtype, layout=layout)
+    F = orc_field(blk)
+    ratio, npairs = parity.local_check(F, lines[0], 0.5, 40.0)
+    assert ratio <= 1.0, ratio
+    ref = F.trace(seeds, 0.5, 400)
+    dev, same = parity.global_compare(lines[0], ref, len(seeds))
+    sens = parity.boundary_sensitive(ref, lines[0], dev, blk.lo, blk.hi, field=F)
+    ok = ~sens
+    assert ok.mean() > 0.9
+    np.testing.assert_array_equal(lines[0]["codes"][ok], ref["code"][ok])
+    np.testing.assert_array_equal(lines[0]["steps"][ok], ref["steps"][ok])
+    # ids are 0..n-1 in seed order; the outbox holds exactly the EXIT particles
+    srt = np.sort(ob, order="id")
+    exits = np.nonzero(lines[0]["codes"] == S.EXIT)[0]
+    np.testing.assert_array_equal(srt["id"], exits)
+    inb = ok[exits]
+    np.testing.assert_array_equal(srt["dest"][inb], ref["out_dest"][exits][inb])
+    assert np.abs(srt["pos"][inb] - ref["out_pos"][exits][inb]).max(initial=0) <= 1e-4 * 40 + dev[exits][inb].max(initial=0)
+    assert st.steps == int(lines[0]["steps"].sum())
+
+
+def test_bit_identical_variants(S):
+    """Cell cache on/off, brick/linear layout, hipGraph replay and chunked resume all give
+    bit-identical lines, steps, codes and outbox contents."""
+    note("variants")
+    blk = fg.turbulence_block(2, edge=32, rank_grid=(3, 3, 3), rank_coord=(1, 1, 1))
+    seeds = fg.uniform_seeds(2, 2500, (0, 0, 0), (32, 32, 32), sub=9)
+    base = run(S, [blk], [seeds], 0.5, 300, fg.F32)
+    variants = [dict(no_cell_cache=1), dict(layout=2), dict(use_graph=1), dict(chunk=37),
+                dict(waves_per_cu=8, refill_threshold=1)]
+    for v in variants:
+        note("variant", v)
+        layout = v.pop("layout", 0)
+        got = run(S, [blk], [seeds], 0.5, 300, fg.F32, layout=layout, **v)
+        for k in ("offsets", "xyz", "steps", "codes", "ids"):
+            np.testing.assert_array_equal(got[1][0][k], base[1][0][k])
+        np.testing.assert_array_equal(np.sort(got[2], order="id"), np.sort(base[2], order="id"))
+
+
+def test_graph_replays(S):
+    """A captured launch replayed on a fresh particle set each time matches eager runs."""
+    note("graph replays")
+    blk = fg.turbulence_block(2, edge=24, rank_grid=(3, 3, 3), rank_coord=(1, 1, 1))
+    seeds = fg.uniform_seeds(2, 1000, (0, 0, 0), (24, 24, 24), sub=3)
+    eager = run(S, [blk], [seeds], 0.5, 200, fg.F32)[1][0]
+    f = S.Field([blk], fg.F32)
+    f.seed(0, seeds, default_max_steps=200)
+    for rep in range(3):
+        st = f.advect(0.5, step_budget=50, use_graph=1)
+        import torch
+        torch.cuda.synchronize()
+    st = f.advect(0.5, step_budget=0, use_graph=1)
+    got = f.lines(0)
+    for k in ("offsets", "xyz", "steps", "codes"):
+        np.testing.assert_array_equal(got[k], eager[k])
+
+
+# ---------------------------------------------------------------- edge cases
+def test_edge_cases(S):
+    note("edge cases")
+    c = (0.25, 0.0, 0.0)
+    blk = fg.closed_form_block(lambda x, y, z: (0 * x + c[0], 0 * x, 0 * x), (4, 4, 4), ghost=1,
+                               origin=(0.5, 0.5, 0.5), lo=(0, 0, 0), hi=(4, 4, 4),
+                               rank_grid=(3, 3, 3), rank_coord=(1, 1, 1))
+    f = S.Field([blk], fg.F32)
+    seeds = np.array([[4.0, 1, 1], [-1e-3, 1, 1], [1, 1, 1], [1, 2, 3], [2.5, 0.5, 3.9]], np.float32)
+    ms = np.array([10, 10, 0, 3, 100], np.int32)
+    f.seed(0, seeds, max_steps=ms, record_stride=2)
+    st = f.advect(0.5)
+    L = f.lines(0)
+    assert list(L["codes"]) == [S.EXIT, S.EXIT, S.MAX_STEPS, S.MAX_STEPS, S.EXIT]
+    # the last seed moves 0.125 per step from x=2.5 and reaches x=4.0 (outside) at step 12
+    assert list(L["steps"]) == [0, 0, 0, 3, 12]
+    # stride 2 keeps vertices 0, 2, ... and the last one
+    assert list(np.diff(L["offsets"])) == [1, 1, 1, 3, 7]
+    ob = np.sort(f.outbox(cap=2), order="id")  # forces the capacity path
+    assert list(ob["id"]) == [0, 1, 4] and list(ob["steps"]) == [0, 0, 12]
+    assert list(ob["dest"]) == [14, 12, 14]
+    # capacity two-call pattern
+    rc, need = S.streami_fetch_lines(f.h, 0, 0, 5, np.zeros(6, np.int64), np.zeros((2, 3), np.float32), 2)
+    assert rc == S.E_CAPACITY and need == 13
+    # advect again: nothing active, nothing changes
+    st2 = f.advect(0.5)
+    assert st2.steps == 0 and st2.active == 0
+
+
+def test_stagnation_nonfinite_halo(S):
+    note("stagnation / nonfinite / halo miss")
+    # stagnant field
+    blk = fg.closed_form_block(lambda x, y, z: (0 * x + 1e-7, 0 * x, 0 * x), (4, 4, 4),
+                               lo=(-10, -10, -10), hi=(10, 10, 10))
+    f = S.Field([blk], fg.F32)
+    f.seed(0, np.array([[1, 1, 1]], np.float32), default_max_steps=5)
+    f.advect(0.5)
+    assert f.lines(0)["codes"][0] == S.STAGNANT
+    # NaN node
+    b2 = fg.closed_form_block(lambda x, y, z: (0 * x + 1, 0 * x, 0 * x), (4, 4, 4),
+                              lo=(-10, -10, -10), hi=(10, 10, 10))
+    b2.values[0, 2, 2, 3, 1] = np.nan
+    b2 = b2.quantise(fg.F32)
+    f = S.Field([b2], fg.F32)
+    f.seed(0, np.array([[0.25, 1.5, 1.5]], np.float32), default_max_steps=10)
+    f.advect(0.5)
+    L = f.lines(0)
+    assert L["codes"][0] == S.NONFINITE and L["steps"][0] == 1
+    np.testing.assert_array_equal(L["xyz"][-1], [0.75, 1.5, 1.5])
+    # halo miss
+    b3 = fg.closed_form_block(lambda x, y, z: (0 * x + 2.0, 0 * x, 0 * x), (4, 4, 4), ghost=1,
+                              origin=(0.5, 0.5, 0.5), lo=(0, 0, 0), hi=(4, 4, 4),
+                              rank_grid=(3, 3, 3), rank_coord=(1, 1, 1))
+    f = S.Field([b3], fg.F32)
+    f.seed(0, np.array([[2.0, 2.0, 2.0]], np.float32), default_max_steps=100)
+    f.advect(0.75)
+    L = f.lines(0)
+    assert L["codes"][0] == S.HALO_MISS and L["steps"][0] == 1
+    ob = f.outbox()
+    assert len(ob) == 1 and ob["code"][0] == S.HALO_MISS and ob["dest"][0] == 14
+    np.testing.assert_array_equal(ob["pos"][0], [3.5, 2.0, 2.0])
+
+
+# ---------------------------------------------------------------- batched + unsteady
+def test_batched_blocks_parity(S):
+    """Eight blocks of uneven size and seed counts in one launch (FP16 nodes), per-seed
+    limits: each block's lines match the oracle run on that block alone."""
+    note("batched blocks")
+    rng = np.random.default_rng(5)
+    blocks, seeds, ms = [], [], []
+    for b in range(8):
+        dims = tuple(int(v) for v in rng.integers(12, 33, size=3))
+        blk = fg.turbulence_block(4, dims=dims, fmt=fg.F16, sub=b, rank_grid=(1, 1, 1),
+                                  rank_coord=(0, 0, 0))
+        blocks.append(blk)
+        n = int(rng.integers(50, 700))
+        seeds.append(fg.uniform_seeds(4, n, (0, 0, 0), dims, sub=100 + b))
+        ms.append(rng.integers(10, 300, size=n).astype(np.int32))
+    f, lines, ob, st = run(S, blocks, seeds, 0.5, ms, fg.F16)
+    for b in range(8):
+        F = orc_field(blocks[b])
+        ratio, _ = parity.local_check(F, lines[b], 0.5, blocks[b].extent)
+        assert ratio <= 1.0, (b, ratio)
+        ref = F.trace(seeds[b], 0.5, ms[b])
+        dev, same = parity.global_compare(lines[b], ref, len(seeds[b]))
+        sens = parity.boundary_sensitive(ref, lines[b], dev, blocks[b].lo, blocks[b].hi, field=F)
+        np.testing.assert_array_equal(lines[b]["codes"][~sens], ref["code"][~sens])
+        np.testing.assert_array_equal(lines[b]["steps"][~sens], ref["steps"][~sens])
+    assert set(np.unique(ob["block"])) <= set(range(8))
+
+
+def test_unsteady_parity(S):
+    """Four time slices blended linearly in time (FP16 nodes): local check with each
+    vertex's own time, discrete results exact away from the boundary."""
+    note("unsteady")
+    blk = fg.turbulence_block(6, edge=24, fmt=fg.F16, n_slices=4, slice_dt=40.0,
+                              rank_grid=(1, 1, 1), rank_coord=(0, 0, 0))
+    seeds = fg.uniform_seeds(6, 1500, (0, 0, 0), (24, 24, 24))
+    f, lines, ob, st = run(S, [blk], [seeds], 0.5, 300, fg.F16)
+    F = orc_field(blk)
+    ratio, _ = parity.local_check(F, lines[0], 0.5, 24.0, t_birth=0.0)
+    assert ratio <= 1.0, ratio
+    ref = F.trace(seeds, 0.5, 300)
+    dev, same = parity.global_compare(lines[0], ref, len(seeds))
+    sens = parity.boundary_sensitive(ref, lines[0], dev, blk.lo, blk.hi, field=F)
+    np.testing.assert_array_equal(lines[0]["codes"][~sens], ref["code"][~sens])
+
+
+# ---------------------------------------------------------------- full size (config 2)
+def test_turbulence_256_full_size_sampled(S):
+    """The benchmark's workload and launch: 256^3 FP32 block + ghost, 1M uniform seeds,
+    h=0.5, up to 2000 steps, rank grid 4^3.  Sampled outputs (a contiguous 4096-particle
+    range of the iid seed set) against the oracle; counts and invariants on all."""
+    note("turbulence 256^3 x 1M full size")
+    blk = fg.turbulence_block(2, edge=256)
+    seeds = fg.uniform_seeds(2, 1 << 20, (0, 0, 0), (256, 256, 256))
+    f = S.Field([blk], fg.F32)
+    f.seed(0, seeds, default_max_steps=2000)
+    st = f.advect(0.5)
+    first, count = 123456, 4096
+    L = f.lines(0, first, count)
+    F = orc_field(blk)
+    ratio, _ = parity.local_check(F, L, 0.5, 256.0)
+    assert ratio <= 1.0, ratio
+    ref = F.trace(seeds[first:first + count], 0.5, 2000)
+    dev, same = parity.global_compare(L, ref, count)
+    sens = parity.boundary_sensitive(ref, L, dev, blk.lo, blk.hi, field=F)
+    np.testing.assert_array_equal(L["codes"][~sens], ref["code"][~sens])
+    np.testing.assert_array_equal(L["steps"][~sens], ref["steps"][~sens])
+    within = (dev <= 1e-4 * 256).mean()
+    note(f"full-size: {within:.3f} of sampled lines within 1e-4 extent; sensitive {sens.mean():.3f}; "
+         f"median dev {np.median(dev):.2e} max {dev.max():.2e}")
+    # invariants over the whole set: every particle terminated, ids conserved
+    assert st.active == 0 and sum(st.terminated) == 1 << 20
+    ob = f.outbox(cap=1 << 21)
+    assert len(ob) == st.terminated[S.EXIT] + st.terminated[S.HALO_MISS]
+    assert len(np.unique(ob["id"])) == len(ob)
+    assert st.terminated[S.HALO_MISS] == 0  # max |v| = 1 cell, h = 0.5: stages never leave the halo
+    # outbox positions lie within h*vmax of the owned bounds, destinations are neighbours
+    out = np.maximum(np.maximum(-ob["pos"], ob["pos"] - 256), 0).max(axis=1)
+    assert out.max() <= 0.5 + 1e-4
+    assert (ob["dest"] >= 0).all() and (ob["dest"] != 1 + 4 * (1 + 4 * 1)).all()
