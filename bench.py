@@ -46,7 +46,7 @@ WORKLOADS = {
 
 def kernel_source_hash() -> str:
     h = hashlib.sha1()
-    for f in ("advect.hip", "device.h"):
+    for f in ("advect_impl.h", "device.h"):
         with open(os.path.join(ROOT, "paper_2606_02627_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:12]
@@ -104,6 +104,8 @@ def main():
     ap.add_argument("--no-cell-cache", action="store_true")
     ap.add_argument("--graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run a plain 1 GiB device copy first (scale for the HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -123,6 +125,14 @@ def main():
         f"{len(seeds)} seeds")
 
     stream = torch.cuda.current_stream()
+    if args.calib_copy:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log("calibration copy: 3 x 1 GiB device-to-device")
     t0 = time.perf_counter()
     f = S.Field([blk], fmt, layout=args.layout)
     torch.cuda.synchronize()

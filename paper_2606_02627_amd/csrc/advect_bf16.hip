@@ -1,0 +1,9 @@
+// Advection kernels for BF16 node storage (see advect_impl.h).
+#include "advect_impl.h"
+
+namespace streami {
+int launch_advect_bf16(const AdvectArgs& a, int layout, bool periodic, int mode, bool batched, int grid,
+                      hipStream_t st) {
+  return launch_advect_fmt<FMT_BF16>(a, layout, periodic, mode, batched, grid, st);
+}
+}  // namespace streami

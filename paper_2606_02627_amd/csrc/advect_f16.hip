@@ -1,0 +1,9 @@
+// Advection kernels for F16 node storage (see advect_impl.h).
+#include "advect_impl.h"
+
+namespace streami {
+int launch_advect_f16(const AdvectArgs& a, int layout, bool periodic, int mode, bool batched, int grid,
+                      hipStream_t st) {
+  return launch_advect_fmt<FMT_F16>(a, layout, periodic, mode, batched, grid, st);
+}
+}  // namespace streami

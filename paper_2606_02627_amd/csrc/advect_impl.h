@@ -1,0 +1,472 @@
+// RK4 particle advection through one or many vector-field blocks (gfx950).
+//
+// Per particle and step (the paper's update kernel, Sec. 3.1.2): four samples
+// of the field -- each a cell location plus a trilinear vec3 interpolation
+// (Sec. 2: the update step is dominated by cell location and interpolation;
+// Sec. 3.3: a structured field addressed by offset computation) -- the RK4
+// combination, then the destination test against the owned bounds; particles
+// that leave go to the outbox with destinationID() of their new position
+// (Sec. 3.1.1), others append a polyline vertex (Sec. 3.2, assembleOutput).
+//
+// gfx950 design (measured: the kernel is VALU-issue bound once the field is
+// cached, so the per-step instruction count is what matters):
+//  * one lane per particle, persistent grid; a wave refills its free lanes
+//    from a global work counter with one atomic per refill (ballot + mbcnt),
+//    so long and short trajectories share waves without idling;
+//  * each lane keeps the 8 corner vectors of the cell it sampled last in
+//    registers; a particle moves ~0.1-0.3 cells per step, so most of the four
+//    samples of a step re-use them and only a cell change issues the gather;
+//  * addresses are 32-bit byte offsets from a per-block base (uniform for a
+//    single block), the byte offset of the cell's first corner doubles as the
+//    cache key, and cell location is branch-free (med3 domain test);
+//  * nodes are FP32 (12 B) or FP16/BF16 padded to 8 B, so a node is one
+//    aligned load; 16-bit values are widened in registers, all arithmetic FP32;
+//  * the outbox append is wave-aggregated (one atomic per wave and event).
+#pragma once
+#include "device.h"
+
+namespace streami {
+
+enum SampleMode { SM_CACHED = 0, SM_UNCACHED = 1, SM_UNSTEADY = 2 };
+
+__device__ __forceinline__ float lerpf(float a, float b, float t) { return fmaf(t, b - a, a); }
+
+__device__ __forceinline__ bool finite3(float3 v) {
+  return __builtin_isfinite(v.x) && __builtin_isfinite(v.y) && __builtin_isfinite(v.z);
+}
+
+// x/6 correctly rounded via one correction step of x*(1/6): exact whenever
+// x/6 is representable (keeps dyadic straight lines bit-exact).
+__device__ __forceinline__ float div6(float x) {
+  const float r = 1.0f / 6.0f;
+  float q = x * r;
+  float e = fmaf(-q, 6.0f, x);
+  return fmaf(e, r, q);
+}
+
+template <int FMT>
+struct NodeBytes { static constexpr unsigned v = 8; };
+template <>
+struct NodeBytes<FMT_F32> { static constexpr unsigned v = 12; };
+
+template <int FMT>
+__device__ __forceinline__ float3 load_node(const char* p);
+
+template <>
+__device__ __forceinline__ float3 load_node<FMT_F32>(const char* p) {
+  const float* q = reinterpret_cast<const float*>(p);
+  return make_float3(q[0], q[1], q[2]);
+}
+
+template <>
+__device__ __forceinline__ float3 load_node<FMT_F16>(const char* p) {
+  const uint2 w = *reinterpret_cast<const uint2*>(p);
+  _Float16 a = __builtin_bit_cast(_Float16, (unsigned short)(w.x & 0xffffu));
+  _Float16 b = __builtin_bit_cast(_Float16, (unsigned short)(w.x >> 16));
+  _Float16 c = __builtin_bit_cast(_Float16, (unsigned short)(w.y & 0xffffu));
+  return make_float3((float)a, (float)b, (float)c);
+}
+
+template <>
+__device__ __forceinline__ float3 load_node<FMT_BF16>(const char* p) {
+  const uint2 w = *reinterpret_cast<const uint2*>(p);
+  return make_float3(__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xffff0000u),
+                     __uint_as_float(w.y << 16));
+}
+
+// Byte offsets of node index i/j/k within one slice of a block.
+template <int LAYOUT, unsigned NB>
+__device__ __forceinline__ unsigned off_x(int i) {
+  if (LAYOUT == LAYOUT_BRICK4) return __umul24((unsigned)(((i >> 2) << 6) + (i & 3)), NB);
+  return __umul24((unsigned)i, NB);
+}
+template <int LAYOUT, unsigned NB>
+__device__ __forceinline__ unsigned off_y(const BlockDev& B, int j) {
+  if (LAYOUT == LAYOUT_BRICK4) return __umul24((unsigned)(j >> 2), B.ys) + (unsigned)(j & 3) * (4 * NB);
+  return __umul24((unsigned)j, B.ys);
+}
+template <int LAYOUT, unsigned NB>
+__device__ __forceinline__ unsigned off_z(const BlockDev& B, int k) {
+  if (LAYOUT == LAYOUT_BRICK4) return __umul24((unsigned)(k >> 2), B.zs) + (unsigned)(k & 3) * (16 * NB);
+  return __umul24((unsigned)k, B.zs);
+}
+
+// Cell location along one axis, without branches.  Block: defined iff
+// 0 <= s <= n-1 (closed); i0 = min(floor(s), n-2), f = s - i0.  Periodic:
+// i0 = floor(s) mod n (exact in float for |s| < 2^24), i1 = (i0+1) mod n.
+// Undefined coordinates still produce in-range indices.
+template <bool PERIODIC>
+__device__ __forceinline__ void locate_axis(float x, float scale, float offs, float fn, float inv_fn,
+                                            int& i0, int& i1, float& f, bool& ok) {
+  const float s = fmaf(x, scale, offs);
+  if (PERIODIC) {
+    ok = ok && (__builtin_fabsf(s) < 8388608.0f);
+    const float fl = floorf(s);
+    f = s - fl;
+    const float q = floorf(fl * inv_fn);
+    float w = fmaf(-q, fn, fl);
+    w = (w < 0.0f) ? w + fn : w;
+    w = (w >= fn) ? w - fn : w;
+    w = __builtin_amdgcn_fmed3f(w, 0.0f, fn - 1.0f);
+    i0 = (int)w;
+    i1 = (w + 1.0f >= fn) ? 0 : i0 + 1;
+  } else {
+    ok = ok && (s == __builtin_amdgcn_fmed3f(s, 0.0f, fn - 1.0f));
+    const float fl = fmaxf(fminf(floorf(s), fn - 2.0f), 0.0f);
+    f = s - fl;
+    i0 = (int)fl;
+    i1 = i0 + 1;
+  }
+}
+
+__device__ __forceinline__ float3 trilinear(const float3 c[8], float fx, float fy, float fz) {
+  float3 v;
+  v.x = lerpf(lerpf(lerpf(c[0].x, c[1].x, fx), lerpf(c[2].x, c[3].x, fx), fy),
+              lerpf(lerpf(c[4].x, c[5].x, fx), lerpf(c[6].x, c[7].x, fx), fy), fz);
+  v.y = lerpf(lerpf(lerpf(c[0].y, c[1].y, fx), lerpf(c[2].y, c[3].y, fx), fy),
+              lerpf(lerpf(c[4].y, c[5].y, fx), lerpf(c[6].y, c[7].y, fx), fy), fz);
+  v.z = lerpf(lerpf(lerpf(c[0].z, c[1].z, fx), lerpf(c[2].z, c[3].z, fx), fy),
+              lerpf(lerpf(c[4].z, c[5].z, fx), lerpf(c[6].z, c[7].z, fx), fy), fz);
+  return v;
+}
+
+// sample(): the field value at (x, t); false where the block holds no data
+// for x (Sec. 3.1.1).
+template <int FMT, int LAYOUT, bool PERIODIC, int MODE>
+struct Sampler {
+  static constexpr unsigned NB = NodeBytes<FMT>::v;
+  unsigned key;
+  float3 c[8];
+
+  __device__ __forceinline__ void reset() { key = 0xffffffffu; }
+
+  __device__ __forceinline__ void gather(const BlockDev& B, const char* base, unsigned o000, int x0, int x1,
+                                         int y0, int y1, int z0, int z1, float3 d[8]) {
+    // signed deltas: a periodic wrap steps back to index 0 (a slice is < 2 GiB,
+    // so every byte offset and delta fits in int)
+    int dx, r10, r01;
+    if (PERIODIC || LAYOUT == LAYOUT_BRICK4) {
+      dx = (int)off_x<LAYOUT, NB>(x1) - (int)off_x<LAYOUT, NB>(x0);
+      r10 = (int)off_y<LAYOUT, NB>(B, y1) - (int)off_y<LAYOUT, NB>(B, y0);
+      r01 = (int)off_z<LAYOUT, NB>(B, z1) - (int)off_z<LAYOUT, NB>(B, z0);
+    } else {
+      dx = (int)NB;
+      r10 = (int)B.ys;
+      r01 = (int)B.zs;
+    }
+    const char* p00 = base + o000;
+    const char* p10 = p00 + r10;
+    const char* p01 = p00 + r01;
+    const char* p11 = p01 + r10;
+    d[0] = load_node<FMT>(p00);
+    d[1] = load_node<FMT>(p00 + dx);
+    d[2] = load_node<FMT>(p10);
+    d[3] = load_node<FMT>(p10 + dx);
+    d[4] = load_node<FMT>(p01);
+    d[5] = load_node<FMT>(p01 + dx);
+    d[6] = load_node<FMT>(p11);
+    d[7] = load_node<FMT>(p11 + dx);
+  }
+
+  __device__ __forceinline__ bool operator()(const BlockDev& B, const char* base, float3 x, float t,
+                                             float3& v) {
+    bool ok = true;
+    int x0, x1, y0, y1, z0, z1;
+    float fx, fy, fz;
+    locate_axis<PERIODIC>(x.x, B.scale[0], B.offs[0], B.fn[0], B.inv_fn[0], x0, x1, fx, ok);
+    locate_axis<PERIODIC>(x.y, B.scale[1], B.offs[1], B.fn[1], B.inv_fn[1], y0, y1, fy, ok);
+    locate_axis<PERIODIC>(x.z, B.scale[2], B.offs[2], B.fn[2], B.inv_fn[2], z0, z1, fz, ok);
+    const unsigned o000 = off_x<LAYOUT, NB>(x0) + off_y<LAYOUT, NB>(B, y0) + off_z<LAYOUT, NB>(B, z0);
+    if (MODE == SM_CACHED) {
+      if (ok && o000 != key) {
+        gather(B, base, o000, x0, x1, y0, y1, z0, z1, c);
+        key = o000;
+      }
+      v = trilinear(c, fx, fy, fz);
+    } else if (MODE == SM_UNCACHED) {
+      if (ok) gather(B, base, o000, x0, x1, y0, y1, z0, z1, c);
+      v = trilinear(c, fx, fy, fz);
+    } else {
+      // linear blend of the two slices bracketing t, clamped at the ends
+      float3 d[8];
+      if (ok) {
+        int s = 0;
+        float al = 0.0f;
+        if (B.n_slices > 1) {
+          const float u = (t - B.t0) * B.inv_sdt;
+          const float fs = fminf(fmaxf(floorf(u), 0.0f), (float)(B.n_slices - 2));
+          s = (int)fs;
+          al = fminf(fmaxf(u - fs, 0.0f), 1.0f);
+        }
+        const char* b0 = base + (size_t)s * B.slice_bytes;
+        gather(B, b0, o000, x0, x1, y0, y1, z0, z1, d);
+        float3 v0 = trilinear(d, fx, fy, fz);
+        if (B.n_slices > 1) {
+          gather(B, b0 + B.slice_bytes, o000, x0, x1, y0, y1, z0, z1, d);
+          const float3 v1 = trilinear(d, fx, fy, fz);
+          v0.x = lerpf(v0.x, v1.x, al);
+          v0.y = lerpf(v0.y, v1.y, al);
+          v0.z = lerpf(v0.z, v1.z, al);
+        }
+        v = v0;
+      } else {
+        v = make_float3(0.f, 0.f, 0.f);
+      }
+    }
+    return ok;
+  }
+};
+
+// One classical RK4 update from (P, t).  Returns ACTIVE when the step was
+// taken (P1 set) or the termination code; for HALO_MISS `fail` is the stage
+// point whose sample was undefined.  A non-finite k makes the next stage point
+// (or, for k4, the new position) non-finite, so NONFINITE is detected where an
+// undefined stage point is non-finite, or the new position is.
+template <class S>
+__device__ __forceinline__ int rk4_step(S& smp, const BlockDev& B, const char* base, float3 P, float t,
+                                        float h, float eps2, float3& P1, float3& fail) {
+  float3 k, q, sum;
+  if (!smp(B, base, P, t, k)) { fail = P; return HALO_MISS; }
+  if (fmaf(k.x, k.x, fmaf(k.y, k.y, k.z * k.z)) < eps2) return STAGNANT;
+  const float hh = 0.5f * h;
+  sum = k;  // k1 + 2 k2 + 2 k3 + k4, accumulated as the stages come in
+  q = make_float3(fmaf(hh, k.x, P.x), fmaf(hh, k.y, P.y), fmaf(hh, k.z, P.z));
+  if (!smp(B, base, q, t + hh, k)) { fail = q; return finite3(q) ? HALO_MISS : NONFINITE; }
+  sum = make_float3(fmaf(2.0f, k.x, sum.x), fmaf(2.0f, k.y, sum.y), fmaf(2.0f, k.z, sum.z));
+  q = make_float3(fmaf(hh, k.x, P.x), fmaf(hh, k.y, P.y), fmaf(hh, k.z, P.z));
+  if (!smp(B, base, q, t + hh, k)) { fail = q; return finite3(q) ? HALO_MISS : NONFINITE; }
+  sum = make_float3(fmaf(2.0f, k.x, sum.x), fmaf(2.0f, k.y, sum.y), fmaf(2.0f, k.z, sum.z));
+  q = make_float3(fmaf(h, k.x, P.x), fmaf(h, k.y, P.y), fmaf(h, k.z, P.z));
+  if (!smp(B, base, q, t + h, k)) { fail = q; return finite3(q) ? HALO_MISS : NONFINITE; }
+  sum = make_float3(sum.x + k.x, sum.y + k.y, sum.z + k.z);
+  P1 = make_float3(P.x + div6(h * sum.x), P.y + div6(h * sum.y), P.z + div6(h * sum.z));
+  if (!finite3(P1)) return NONFINITE;
+  return ACTIVE;
+}
+
+// destinationID(): flat macrocell id of x, -1 outside the macrocell grid.
+__device__ __forceinline__ int dest_id(const BlockDev& B, float3 x) {
+  int r0 = B.rcoord[0] + (int)floorf((x.x - B.lo[0]) * B.inv_ext[0]);
+  int r1 = B.rcoord[1] + (int)floorf((x.y - B.lo[1]) * B.inv_ext[1]);
+  int r2 = B.rcoord[2] + (int)floorf((x.z - B.lo[2]) * B.inv_ext[2]);
+  if (r0 < 0 || r0 >= B.rgrid[0] || r1 < 0 || r1 >= B.rgrid[1] || r2 < 0 || r2 >= B.rgrid[2]) return -1;
+  return r0 + B.rgrid[0] * (r1 + B.rgrid[1] * r2);
+}
+
+__device__ __forceinline__ bool inside(const BlockDev& B, float3 x) {
+  return x.x >= B.lo[0] && x.x < B.hi[0] && x.y >= B.lo[1] && x.y < B.hi[1] && x.z >= B.lo[2] &&
+         x.z < B.hi[2];
+}
+
+__device__ __forceinline__ unsigned lanes_below(unsigned long long m) {
+  return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+extern __shared__ BlockDev g_lds_blocks[];
+
+template <int FMT, int LAYOUT, bool PERIODIC, int MODE, bool BATCHED>
+__global__ void __launch_bounds__(256) k_advect(AdvectArgs A) {
+  constexpr unsigned NB = NodeBytes<FMT>::v;
+  BlockDev B0;
+  const char* base0 = nullptr;
+  if constexpr (BATCHED) {
+    for (int i = threadIdx.x; i < A.n_blocks; i += blockDim.x) g_lds_blocks[i] = A.blocks[i];
+    __syncthreads();
+  } else {
+    B0 = A.blocks[0];
+    base0 = reinterpret_cast<const char*>(A.nodes) + (size_t)B0.base * NB;
+  }
+  const int lane = __lane_id();
+  int p = -1;  // particle index (< 2^31, enforced at seeding)
+  float3 P = make_float3(0.f, 0.f, 0.f);
+  float tb = 0.f;
+  int n = 0, m = 0, nv = 0, stride = 1, blk = 0, left = 0, until_rec = 0;
+  const char* lbase = base0;
+  // this wave's current log chunk [cpos, cend) (wave-uniform)
+  unsigned long long cpos = 0, cend = 0;
+  bool log_ok = true;
+  unsigned my_steps = 0, my_verts = 0;
+  Sampler<FMT, LAYOUT, PERIODIC, MODE> smp;
+  smp.reset();
+  bool queue_done = false;  // wave-uniform
+  const unsigned long long all = __ballot(1);
+
+  while (true) {
+    const unsigned long long dead = __ballot(p < 0);
+    if (!queue_done && dead != 0 && (__popcll(dead) >= A.refill || dead == all)) {
+      const int cnt = __popcll(dead);
+      const int leader = __ffsll((long long)dead) - 1;
+      unsigned long long qbase = 0;
+      if (lane == leader) qbase = atomicAdd(&A.ctr[CTR_QUEUE], (unsigned long long)cnt);
+      qbase = __shfl(qbase, leader, 64);
+      if (qbase + cnt >= (unsigned long long)A.n_particles) queue_done = true;
+      if (p < 0) {
+        const long long my = (long long)(qbase + lanes_below(dead));
+        if (my < A.n_particles) {
+          const int4 mt = A.meta[my];
+          if (mt.z == ACTIVE) {
+            p = (int)my;
+            const float4 ps = A.pos[my];
+            P = make_float3(ps.x, ps.y, ps.z);
+            tb = ps.w;
+            n = mt.x; m = mt.y; nv = mt.w;
+            const int4 m2 = A.meta2[my];
+            stride = m2.x; blk = m2.y;
+            until_rec = stride - n % stride;
+            left = A.budget > 0 ? A.budget : 0x7fffffff;
+            if constexpr (BATCHED)
+              lbase = reinterpret_cast<const char*>(A.nodes) + (size_t)g_lds_blocks[blk].base * NB;
+            smp.reset();
+          }
+        }
+      }
+    }
+    if (queue_done && __ballot(p < 0) == all) break;
+
+    int term = ACTIVE;
+    int dest = -1;
+    float3 opos = P;
+    bool rec = false;  // a vertex (P, index nv) to append this iteration
+    if (p >= 0) {
+      const BlockDev& B = BATCHED ? g_lds_blocks[blk] : B0;
+      if (n >= m) {
+        term = MAX_STEPS;
+      } else {
+        float3 P1, fail;
+        const float t = fmaf((float)n, A.h, tb);
+        const int st = rk4_step(smp, B, lbase, P, t, A.h, A.eps2, P1, fail);
+        if (st == ACTIVE) {
+          P = P1;
+          ++n;
+          --left;
+          ++my_steps;
+          const bool out = !PERIODIC && !inside(B, P);
+          const bool on_stride = --until_rec == 0;
+          if (on_stride) until_rec = stride;
+          rec = out || n == m || on_stride;
+          if (out) {
+            term = EXIT;
+            dest = dest_id(B, P);
+            opos = P;
+          } else if (n == m) {
+            term = MAX_STEPS;
+          }
+        } else {
+          term = st;
+          if (st == HALO_MISS) {
+            dest = dest_id(B, fail);
+            opos = P;
+          }
+          rec = until_rec != stride;  // the final vertex is always kept
+        }
+      }
+    }
+    // wave-aggregated vertex append into this wave's log chunk (assembleOutput)
+    const unsigned long long vm = __ballot(rec);
+    if (vm != 0) {
+      const unsigned cnt = (unsigned)__popcll(vm);
+      if (cpos + cnt > cend) {
+        // mark the unused tail of the old chunk (< 64 records) so fetches skip it
+        if (log_ok && cpos + lane < cend) A.log.pj[cpos + lane] = make_uint2(0xffffffffu, 0xffffffffu);
+        unsigned long long nb = 0;
+        if (lane == 0) nb = atomicAdd(A.log.count, (unsigned long long)LOG_CHUNK);
+        nb = __shfl(nb, 0, 64);
+        if (nb + LOG_CHUNK > (unsigned long long)A.log.cap) {
+          log_ok = false;  // cannot happen when the host sized the log; never write past it
+          if (lane == 0) atomicOr(&A.ctr[CTR_OVERFLOW], 1ull);
+        }
+        cpos = nb;
+        cend = nb + LOG_CHUNK;
+      }
+      if (rec && log_ok) {
+        const unsigned long long r = cpos + lanes_below(vm);
+        A.log.x[r] = P.x;
+        A.log.y[r] = P.y;
+        A.log.z[r] = P.z;
+        A.log.pj[r] = make_uint2((unsigned)p, (unsigned)nv);
+      }
+      if (rec) {
+        ++nv;
+        ++my_verts;
+      }
+      cpos += cnt;
+    }
+    // wave-aggregated outbox append (emitOutgoing)
+    const bool emit = (term == EXIT || term == HALO_MISS);
+    const unsigned long long em = __ballot(emit);
+    if (em != 0) {
+      const int leader = __ffsll((long long)em) - 1;
+      unsigned long long obase = 0;
+      if (lane == leader) obase = atomicAdd(A.outbox_count, (unsigned long long)__popcll(em));
+      obase = __shfl(obase, leader, 64);
+      if (emit) {
+        OutRec r;
+        r.id = A.ids[p];
+        r.pos[0] = opos.x; r.pos[1] = opos.y; r.pos[2] = opos.z;
+        r.steps = n;
+        r.dest = dest;
+        r.code = (short)term;
+        r.block = (short)blk;
+        A.outbox[obase + lanes_below(em)] = r;
+      }
+    }
+    if (p >= 0 && (term != ACTIVE || left <= 0)) {
+      A.pos[p] = make_float4(P.x, P.y, P.z, tb);
+      A.meta[p] = make_int4(n, m, term, nv);
+      p = -1;
+    }
+  }
+  // mark the unused tail of this wave's last chunk
+  if (log_ok)
+    for (unsigned long long r = cpos + lane; r < cend; r += 64) A.log.pj[r] = make_uint2(0xffffffffu, 0xffffffffu);
+  const unsigned long long s = wave_sum((unsigned long long)my_steps), v = wave_sum((unsigned long long)my_verts);
+  if (lane == 0) {
+    if (s) atomicAdd(&A.ctr[CTR_STEPS], s);
+    if (v) {
+      atomicAdd(&A.ctr[CTR_VERTS], v);
+      atomicAdd(A.log.real, v);
+    }
+  }
+}
+
+template <int FMT, int LAYOUT, bool PERIODIC, int MODE, bool BATCHED>
+static void launch_variant(const AdvectArgs& a, int grid, hipStream_t st) {
+  const size_t lds = BATCHED ? sizeof(BlockDev) * (size_t)a.n_blocks : 0;
+  hipLaunchKernelGGL((k_advect<FMT, LAYOUT, PERIODIC, MODE, BATCHED>), dim3(grid), dim3(256), lds, st, a);
+}
+
+// All variants of one storage format.  Periodic blocks are supported for a
+// single steady block (the batched and unsteady kernels assume BLOCK boundaries).
+template <int FMT>
+int launch_advect_fmt(const AdvectArgs& a, int layout, bool periodic, int mode, bool batched, int grid,
+                      hipStream_t st) {
+#define STREAMI_L(LAY)                                                                              \
+  if (batched) {                                                                                    \
+    if (periodic) return -1;                                                                        \
+    if (mode == SM_CACHED) launch_variant<FMT, LAY, false, SM_CACHED, true>(a, grid, st);           \
+    else if (mode == SM_UNCACHED) launch_variant<FMT, LAY, false, SM_UNCACHED, true>(a, grid, st);  \
+    else launch_variant<FMT, LAY, false, SM_UNSTEADY, true>(a, grid, st);                          \
+  } else if (periodic) {                                                                            \
+    if (mode == SM_CACHED) launch_variant<FMT, LAY, true, SM_CACHED, false>(a, grid, st);           \
+    else if (mode == SM_UNCACHED) launch_variant<FMT, LAY, true, SM_UNCACHED, false>(a, grid, st);  \
+    else return -1;                                                                                 \
+  } else {                                                                                          \
+    if (mode == SM_CACHED) launch_variant<FMT, LAY, false, SM_CACHED, false>(a, grid, st);          \
+    else if (mode == SM_UNCACHED) launch_variant<FMT, LAY, false, SM_UNCACHED, false>(a, grid, st); \
+    else launch_variant<FMT, LAY, false, SM_UNSTEADY, false>(a, grid, st);                         \
+  }                                                                                                 \
+  return 0;
+  if (layout == LAYOUT_BRICK4) {
+    STREAMI_L(LAYOUT_BRICK4)
+  } else {
+    STREAMI_L(LAYOUT_LINEAR)
+  }
+#undef STREAMI_L
+}
+
+}  // namespace streami

@@ -16,16 +16,22 @@
 #include "device.h"
 
 namespace streami {
-int launch_advect(const AdvectArgs& a, int fmt, int layout, bool unsteady, bool cache, bool batched, int grid,
-                  hipStream_t st);
+int launch_advect_f32(const AdvectArgs& a, int layout, bool periodic, int mode, bool batched, int grid,
+                      hipStream_t st);
+int launch_advect_f16(const AdvectArgs& a, int layout, bool periodic, int mode, bool batched, int grid,
+                      hipStream_t st);
+int launch_advect_bf16(const AdvectArgs& a, int layout, bool periodic, int mode, bool batched, int grid,
+                       hipStream_t st);
 int launch_ingest(const void* src, void* pool, const BlockDev& B, int fmt, int layout, int nx, int ny, int nz,
                   int n_slices, hipStream_t st);
 int launch_seed(const float* xyz, const unsigned long long* ids, unsigned long long auto_id0, const int* max_steps,
                 int default_max, int stride, float t_birth, int blk, const BlockDev& B, long long first,
-                long long n, long long vbase0, float4* pos, int4* meta, int4* meta2, unsigned long long* pid,
-                long long* vbase, float* verts, OutRec* outbox, unsigned long long* outbox_count, hipStream_t st);
-int launch_pack_lines(const long long* idx, long long count, const long long* offsets, const long long* vbase,
-                      const float* verts, float* out, hipStream_t st);
+                long long n, float4* pos, int4* meta, int4* meta2, unsigned long long* pid, const VertexLog& log,
+                OutRec* outbox, unsigned long long* outbox_count, hipStream_t st);
+int launch_scatter_lines(const VertexLog& log, long long n_rec, long long n_particles, const int* row_of,
+                         const long long* offsets, float* out, hipStream_t st);
+int launch_mark_rows(const long long* idx, long long count, int* row_of, hipStream_t st);
+int launch_fill_u32(unsigned* p, long long n, unsigned v, hipStream_t st);
 int launch_fill_u64(unsigned long long* p, long long n, unsigned long long v, hipStream_t st);
 int launch_gather_meta(const long long* idx, long long count, const int4* meta, const int4* meta2,
                        const unsigned long long* pid, long long* nverts, int* steps, int* codes,
@@ -77,6 +83,7 @@ struct DevBuf {
   }
   int reserve(size_t need, size_t keep, hipStream_t st) {
     if (need <= bytes) return STREAMI_OK;
+    if (!keep) release();  // nothing to preserve: never hold both buffers
     void* q = nullptr;
     if (hipMalloc(&q, need) != hipSuccess) {
       (void)hipGetLastError();
@@ -99,7 +106,6 @@ struct HostBlock {
   int nx, ny, nz;  // stored nodes per axis
   std::vector<std::pair<long long, long long>> ranges;  // (first particle, count) in seed order
   long long n_particles = 0;
-  long long n_vert_slots = 0;
 };
 
 }  // namespace
@@ -109,15 +115,19 @@ struct streami_field_s {
   hipStream_t stream = nullptr;
   int fmt = 0, layout = LAYOUT_LINEAR;
   bool unsteady = false;
+  bool periodic = false;
   int n_cu = 256;
   std::vector<HostBlock> blocks;
   DevBuf d_blocks, d_nodes;
   // particles (SoA)
   long long n_particles = 0, cap_particles = 0;
-  DevBuf d_pos, d_meta, d_meta2, d_ids, d_vbase, d_outbox;
-  DevBuf d_verts;
-  long long n_vert_slots = 0;
-  DevBuf d_ctr;        // CTR_N per-call counters + 1 persistent outbox count + 6 code counts
+  DevBuf d_pos, d_meta, d_meta2, d_ids, d_outbox;
+  // vertex log (see VertexLog): capacity in records, and the sum over all
+  // particles of the vertices each may still record at most
+  DevBuf d_logx, d_logy, d_logz, d_logpj;
+  long long log_cap = 0;
+  long long vert_bound = 0;
+  DevBuf d_ctr;        // CTR_N per-call counters, PER_N persistent counters, 6 code counts
   unsigned long long next_auto_id = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipGraphExec_t graph = nullptr;
@@ -125,9 +135,22 @@ struct streami_field_s {
   int graph_key[6] = {0, 0, 0, 0, 0, 0};
 
   unsigned long long* ctr() { return reinterpret_cast<unsigned long long*>(d_ctr.p); }
-  unsigned long long* outbox_count() { return ctr() + CTR_N; }
-  unsigned long long* code_counts() { return ctr() + CTR_N + 1; }
+  unsigned long long* persist() { return ctr() + CTR_N; }
+  unsigned long long* outbox_count() { return persist() + PER_OUTBOX; }
+  unsigned long long* code_counts() { return persist() + PER_N; }
+  VertexLog log() {
+    VertexLog l;
+    l.x = (float*)d_logx.p;
+    l.y = (float*)d_logy.p;
+    l.z = (float*)d_logz.p;
+    l.pj = (uint2*)d_logpj.p;
+    l.count = persist() + PER_LOG;
+    l.real = persist() + PER_LOG_REAL;
+    l.cap = log_cap;
+    return l;
+  }
 };
+constexpr int N_COUNTERS = CTR_N + PER_N + 6;
 
 namespace {
 
@@ -163,7 +186,7 @@ int validate_desc(const streami_block_desc& d, int i) {
   return STREAMI_OK;
 }
 
-BlockDev make_dev(const streami_block_desc& d, int layout, long long base) {
+BlockDev make_dev(const streami_block_desc& d, int layout, int fmt, long long base) {
   BlockDev B;
   std::memset(&B, 0, sizeof B);
   const bool per = d.boundary == STREAMI_BOUNDARY_PERIODIC;
@@ -190,7 +213,33 @@ BlockDev make_dev(const streami_block_desc& d, int layout, long long base) {
   B.inv_sdt = d.n_slices > 1 ? (float)(1.0 / d.slice_dt) : 0.0f;
   B.base = base;
   B.slice_nodes = slice;
+  const long long nb = pool_node_bytes(fmt);
+  long long ys, zs;
+  if (layout == LAYOUT_BRICK4) {
+    ys = (long long)B.nb[0] * 64 * nb;
+    zs = (long long)B.nb[0] * B.nb[1] * 64 * nb;
+  } else {
+    ys = (long long)B.nst[0] * nb;
+    zs = (long long)B.nst[0] * B.nst[1] * nb;
+  }
+  B.ys = (unsigned)ys;
+  B.zs = (unsigned)zs;
+  B.slice_bytes = (unsigned)std::min<long long>(slice * nb, 0xffffffffLL);
+  for (int a = 0; a < 3; ++a) {
+    B.fn[a] = (float)B.nst[a];
+    B.inv_fn[a] = (float)(1.0 / B.nst[a]);
+  }
   return B;
+}
+
+// The kernels address a slice with 32-bit byte offsets and 24-bit row/plane
+// multiplies: a slice must stay below 2 GiB and a z plane below 16 MiB.
+int check_geometry(const BlockDev& B, int i) {
+  if (B.ys >= (1u << 24) || B.zs >= (1u << 24))
+    return fail(STREAMI_E_UNSUPPORTED, "blocks[%d]: a z plane of nodes exceeds 16 MiB", i);
+  if ((long long)B.slice_bytes >= (1LL << 31))
+    return fail(STREAMI_E_UNSUPPORTED, "blocks[%d]: one time slice exceeds 2 GiB; split the block", i);
+  return STREAMI_OK;
 }
 
 int ensure_particles(streami_field_s* f, long long need) {
@@ -203,12 +252,34 @@ int ensure_particles(streami_field_s* f, long long need) {
   if ((rc = f->d_meta.reserve(cap * sizeof(int4), n * sizeof(int4), f->stream))) return rc;
   if ((rc = f->d_meta2.reserve(cap * sizeof(int4), n * sizeof(int4), f->stream))) return rc;
   if ((rc = f->d_ids.reserve(cap * 8, n * 8, f->stream))) return rc;
-  if ((rc = f->d_vbase.reserve(cap * 8, n * 8, f->stream))) return rc;
   unsigned long long ob = 0;
   HIP_TRY(hipMemcpyAsync(&ob, f->outbox_count(), 8, hipMemcpyDeviceToHost, f->stream));
   HIP_TRY(hipStreamSynchronize(f->stream));
   if ((rc = f->d_outbox.reserve(cap * sizeof(OutRec), ob * sizeof(OutRec), f->stream))) return rc;
   f->cap_particles = cap;
+  return STREAMI_OK;
+}
+
+// Make the vertex log hold every record still to come: the records reserved so
+// far, the vertices particles may still record, and `slack` more (unused chunk
+// tails of one launch).  Grows by reallocation, keeping the reserved records.
+int ensure_log(streami_field_s* f, long long slack) {
+  unsigned long long c[PER_N];
+  HIP_TRY(hipMemcpyAsync(c, f->persist(), sizeof c, hipMemcpyDeviceToHost, f->stream));
+  HIP_TRY(hipStreamSynchronize(f->stream));
+  const long long count = (long long)std::min<unsigned long long>(c[PER_LOG], (unsigned long long)f->log_cap);
+  // a wave abandons < 64 records of a chunk when it switches chunks: reserve
+  // the remaining bound plus 1/8 for those tails, plus `slack` for last chunks
+  const long long remaining = std::max<long long>(f->vert_bound - (long long)c[PER_LOG_REAL], 0);
+  const long long need = (long long)c[PER_LOG] + remaining + remaining / 8 + slack;
+  if (need <= f->log_cap) return STREAMI_OK;
+  const long long cap = std::max(need, f->log_cap + f->log_cap / 4);
+  int rc;
+  if ((rc = f->d_logx.reserve(cap * 4, count * 4, f->stream))) return rc;
+  if ((rc = f->d_logy.reserve(cap * 4, count * 4, f->stream))) return rc;
+  if ((rc = f->d_logz.reserve(cap * 4, count * 4, f->stream))) return rc;
+  if ((rc = f->d_logpj.reserve(cap * 8, count * 8, f->stream))) return rc;
+  f->log_cap = cap;
   return STREAMI_OK;
 }
 
@@ -255,13 +326,17 @@ int streami_field_create(const streami_block_desc* blocks, int32_t n_blocks, int
   for (int i = 0; i < n_blocks; ++i) {
     HostBlock& hb = f->blocks[i];
     hb.desc = blocks[i];
-    hb.dev = make_dev(blocks[i], layout, base);
+    hb.dev = make_dev(blocks[i], layout, dtype, base);
+    if (int rc0 = check_geometry(hb.dev, i)) return cleanup(rc0);
     hb.nx = hb.dev.nst[0];
     hb.ny = hb.dev.nst[1];
     hb.nz = hb.dev.nst[2];
     base += hb.dev.slice_nodes * blocks[i].n_slices;
     if (blocks[i].n_slices > 1) f->unsteady = true;
+    if (blocks[i].boundary == STREAMI_BOUNDARY_PERIODIC) f->periodic = true;
   }
+  if (f->periodic && (n_blocks > 1 || f->unsteady))
+    return cleanup(fail(STREAMI_E_UNSUPPORTED, "periodic boundaries are supported for one steady block"));
   int rc;
   if ((rc = f->d_nodes.reserve((size_t)base * pool_node_bytes(dtype), 0, f->stream))) return cleanup(rc);
   if (layout == STREAMI_LAYOUT_BRICK4 || dtype != STREAMI_F32)  // padding stays zero
@@ -290,8 +365,8 @@ int streami_field_create(const streami_block_desc* blocks, int32_t n_blocks, int
   if (hipMemcpyAsync(f->d_blocks.p, devs.data(), sizeof(BlockDev) * n_blocks, hipMemcpyHostToDevice, f->stream) !=
       hipSuccess)
     return cleanup(fail(STREAMI_E_DEVICE, "block table copy failed"));
-  if ((rc = f->d_ctr.reserve(sizeof(unsigned long long) * (CTR_N + 1 + 6), 0, f->stream))) return cleanup(rc);
-  launch_fill_u64(f->ctr(), CTR_N + 1 + 6, 0, f->stream);
+  if ((rc = f->d_ctr.reserve(sizeof(unsigned long long) * N_COUNTERS, 0, f->stream))) return cleanup(rc);
+  launch_fill_u64(f->ctr(), N_COUNTERS, 0, f->stream);
   if (hipEventCreate(&f->ev0) != hipSuccess || hipEventCreate(&f->ev1) != hipSuccess)
     return cleanup(fail(STREAMI_E_DEVICE, "event creation failed"));
   if (hipStreamSynchronize(f->stream) != hipSuccess) return cleanup(fail(STREAMI_E_DEVICE, "field upload failed"));
@@ -304,8 +379,8 @@ int streami_field_destroy(streami_field f) {
   if (!f) return STREAMI_OK;
   (void)hipStreamSynchronize(f->stream);
   drop_graph(f);
-  for (DevBuf* b : {&f->d_blocks, &f->d_nodes, &f->d_pos, &f->d_meta, &f->d_meta2, &f->d_ids, &f->d_vbase,
-                    &f->d_outbox, &f->d_verts, &f->d_ctr})
+  for (DevBuf* b : {&f->d_blocks, &f->d_nodes, &f->d_pos, &f->d_meta, &f->d_meta2, &f->d_ids, &f->d_outbox,
+                    &f->d_logx, &f->d_logy, &f->d_logz, &f->d_logpj, &f->d_ctr})
     b->release();
   if (f->ev0) (void)hipEventDestroy(f->ev0);
   if (f->ev1) (void)hipEventDestroy(f->ev1);
@@ -319,6 +394,7 @@ int streami_seed(streami_field f, int32_t block, const float* xyz, const uint64_
   if (block < 0 || block >= (int)f->blocks.size()) return fail(STREAMI_E_ARG, "block %d out of range", block);
   if (n < 0) return fail(STREAMI_E_ARG, "n must be >= 0");
   if (n == 0) return STREAMI_OK;
+  if (f->n_particles + n >= (1LL << 31)) return fail(STREAMI_E_ARG, "more than 2^31 particles per handle");
   if (!xyz) return fail(STREAMI_E_ARG, "xyz is NULL");
   if (!opts) return fail(STREAMI_E_ARG, "opts is NULL");
   if (opts->record_stride < 1) return fail(STREAMI_E_ARG, "record_stride must be >= 1");
@@ -336,30 +412,21 @@ int streami_seed(streami_field f, int32_t block, const float* xyz, const uint64_
     for (long long i = 0; i < n; ++i)
       if (ms[i] < 0) return fail(STREAMI_E_ARG, "max_steps[%lld] < 0", i);
   }
-  // vertex slots: per-particle limits need a host prefix; uniform limits are
-  // a fixed stride that the seed kernel computes itself
-  std::vector<long long> vb;
-  long long slots = f->n_vert_slots;
-  if (max_steps) {
-    vb.resize(n);
-    for (long long i = 0; i < n; ++i) {
-      vb[i] = slots;
-      slots += ms[i] / opts->record_stride + 2;
-    }
-  } else {
-    slots += n * (long long)(opts->default_max_steps / opts->record_stride + 2);
+  // every particle may record at most max_steps/stride + 2 vertices
+  long long bound = 0;
+  for (long long i = 0; i < n; ++i) {
+    const int m = max_steps ? ms[i] : opts->default_max_steps;
+    bound += m / opts->record_stride + 2;
   }
   int rc;
   drop_graph(f);
   if ((rc = ensure_particles(f, f->n_particles + n))) return rc;
-  if ((size_t)slots * 12 > f->d_verts.bytes) {
-    size_t want = std::max((size_t)slots * 12, f->d_verts.bytes + f->d_verts.bytes / 4);
-    if ((rc = f->d_verts.reserve(want, (size_t)f->n_vert_slots * 12, f->stream))) return rc;
+  f->vert_bound += bound;
+  if ((rc = ensure_log(f, 0))) {
+    f->vert_bound -= bound;
+    return rc;
   }
   const long long first = f->n_particles;
-  if (max_steps)
-    HIP_TRY(hipMemcpyAsync(reinterpret_cast<long long*>(f->d_vbase.p) + first, vb.data(), n * 8,
-                           hipMemcpyHostToDevice, f->stream));
   // stage host inputs on the device
   DevBuf s_xyz, s_ids, s_ms;
   const float* d_xyz = xyz;
@@ -382,14 +449,12 @@ int streami_seed(streami_field f, int32_t block, const float* xyz, const uint64_
   }
   HostBlock& hb = f->blocks[block];
   launch_seed(d_xyz, d_ids, f->next_auto_id, d_ms, opts->default_max_steps, opts->record_stride, opts->t_birth,
-              block, hb.dev, first, n, f->n_vert_slots, (float4*)f->d_pos.p, (int4*)f->d_meta.p,
-              (int4*)f->d_meta2.p, (unsigned long long*)f->d_ids.p, (long long*)f->d_vbase.p,
-              (float*)f->d_verts.p, (OutRec*)f->d_outbox.p, f->outbox_count(), f->stream);
+              block, hb.dev, first, n, (float4*)f->d_pos.p, (int4*)f->d_meta.p, (int4*)f->d_meta2.p,
+              (unsigned long long*)f->d_ids.p, f->log(), (OutRec*)f->d_outbox.p, f->outbox_count(), f->stream);
   HIP_TRY(hipGetLastError());
-  if (!dev_in || max_steps) HIP_TRY(hipStreamSynchronize(f->stream));  // staging buffers are freed on return
+  if (!dev_in) HIP_TRY(hipStreamSynchronize(f->stream));  // staging buffers are freed on return
   if (!ids) f->next_auto_id += (unsigned long long)n;
   f->n_particles += n;
-  f->n_vert_slots = slots;
   hb.ranges.push_back({first, n});
   hb.n_particles += n;
   return STREAMI_OK;
@@ -415,8 +480,6 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
   a.meta = (int4*)f->d_meta.p;
   a.meta2 = (const int4*)f->d_meta2.p;
   a.ids = (const unsigned long long*)f->d_ids.p;
-  a.vbase = (const long long*)f->d_vbase.p;
-  a.verts = (float*)f->d_verts.p;
   a.outbox = (OutRec*)f->d_outbox.p;
   a.outbox_count = f->outbox_count();
   a.ctr = f->ctr();
@@ -429,11 +492,21 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
   long long grid = (long long)f->n_cu * wpc / 4;
   grid = std::min(grid, (f->n_particles + 255) / 256);
   grid = std::max(grid, 1LL);
+  {
+    int rc = ensure_log(f, grid * 4 * (long long)LOG_CHUNK);
+    if (rc) return rc;
+  }
+  a.log = f->log();
   const bool batched = f->blocks.size() > 1;
-  const bool cache = !f->unsteady && !p->no_cell_cache;
+  const int mode = f->unsteady ? 2 : (p->no_cell_cache ? 1 : 0);
+  auto launch = [&](hipStream_t st) {
+    if (f->fmt == STREAMI_F32) return launch_advect_f32(a, f->layout, f->periodic, mode, batched, (int)grid, st);
+    if (f->fmt == STREAMI_F16) return launch_advect_f16(a, f->layout, f->periodic, mode, batched, (int)grid, st);
+    return launch_advect_bf16(a, f->layout, f->periodic, mode, batched, (int)grid, st);
+  };
   HIP_TRY(hipEventRecord(f->ev0, f->stream));
   if (p->use_graph) {
-    const int key[6] = {(int)grid, a.refill, a.budget, cache ? 1 : 0, (int)(p->h * 1e6f), 1};
+    const int key[6] = {(int)grid, a.refill, a.budget, mode, (int)(p->h * 1e6f), 1};
     bool same = f->graph && std::memcmp(key, f->graph_key, sizeof key) == 0 &&
                 std::memcmp(&a, &f->graph_args, sizeof a) == 0;
     if (!same) {
@@ -443,7 +516,7 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
       hipGraph_t g;
       HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
       launch_fill_u64(a.ctr, CTR_N, 0, cs);
-      launch_advect(a, f->fmt, f->layout, f->unsteady, cache, batched, (int)grid, cs);
+      launch(cs);
       HIP_TRY(hipStreamEndCapture(cs, &g));
       HIP_TRY(hipGraphInstantiate(&f->graph, g, nullptr, nullptr, 0));
       (void)hipGraphDestroy(g);
@@ -454,14 +527,14 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
     HIP_TRY(hipGraphLaunch(f->graph, f->stream));
   } else {
     launch_fill_u64(a.ctr, CTR_N, 0, f->stream);
-    launch_advect(a, f->fmt, f->layout, f->unsteady, cache, batched, (int)grid, f->stream);
+    launch(f->stream);
   }
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipEventRecord(f->ev1, f->stream));
   if (stats) {
     launch_fill_u64(f->code_counts(), 6, 0, f->stream);
     launch_count_codes((const int4*)f->d_meta.p, f->n_particles, f->code_counts(), f->stream);
-    unsigned long long h[CTR_N + 1 + 6];
+    unsigned long long h[N_COUNTERS];
     HIP_TRY(hipMemcpyAsync(h, f->ctr(), sizeof h, hipMemcpyDeviceToHost, f->stream));
     HIP_TRY(hipStreamSynchronize(f->stream));
     std::memset(stats, 0, sizeof *stats);
@@ -469,8 +542,9 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
     stats->vertices = (int64_t)h[CTR_VERTS];
     stats->surrogate_accepted = (int64_t)h[CTR_ACCEPT];
     stats->surrogate_fallback = (int64_t)h[CTR_FALLBACK];
-    stats->outbox = (int64_t)h[CTR_N];
-    for (int k = 0; k < 6; ++k) stats->terminated[k] = (int64_t)h[CTR_N + 1 + k];
+    stats->outbox = (int64_t)h[CTR_N + PER_OUTBOX];
+    for (int k = 0; k < 6; ++k) stats->terminated[k] = (int64_t)h[CTR_N + PER_N + k];
+    if (h[CTR_OVERFLOW]) return fail(STREAMI_E_DEVICE, "vertex log overflow (internal sizing error)");
     stats->active = stats->terminated[0];
     float ms = 0;
     HIP_TRY(hipEventElapsedTime(&ms, f->ev0, f->ev1));
@@ -483,13 +557,13 @@ int streami_clear(streami_field f) {
   if (!f) return fail(STREAMI_E_ARG, "field handle is NULL");
   drop_graph(f);
   f->n_particles = 0;
-  f->n_vert_slots = 0;
+  f->vert_bound = 0;
   f->next_auto_id = 0;
   for (auto& hb : f->blocks) {
     hb.ranges.clear();
     hb.n_particles = 0;
   }
-  launch_fill_u64(f->outbox_count(), 1, 0, f->stream);
+  launch_fill_u64(f->persist(), PER_N, 0, f->stream);
   HIP_TRY(hipGetLastError());
   return STREAMI_OK;
 }
@@ -570,21 +644,29 @@ int streami_fetch_lines(streami_field f, int32_t block, int64_t first, int64_t c
   if ((rc = put(codes, h_codes.data(), count * 4))) return rc;
   if ((rc = put(ids, h_ids.data(), count * 8))) return rc;
   if (off[count] > 0) {
+    // scatter the log records of the requested particles into CSR rows
+    DevBuf d_row;
+    unsigned long long cnt[PER_N];
+    HIP_TRY(hipMemcpyAsync(cnt, f->persist(), sizeof cnt, hipMemcpyDeviceToHost, f->stream));
+    HIP_TRY(hipStreamSynchronize(f->stream));
+    const long long n_rec = (long long)std::min<unsigned long long>(cnt[PER_LOG], (unsigned long long)f->log_cap);
     if ((rc = d_off.reserve((count + 1) * 8, 0, f->stream))) return rc;
+    if ((rc = d_row.reserve(std::max<long long>(f->n_particles, 1) * 4, 0, f->stream))) return rc;
     HIP_TRY(hipMemcpyAsync(d_off.p, off.data(), (count + 1) * 8, hipMemcpyHostToDevice, f->stream));
-    if (is_device_ptr(xyz)) {
-      launch_pack_lines((const long long*)d_idx.p, count, (const long long*)d_off.p, (const long long*)f->d_vbase.p,
-                        (const float*)f->d_verts.p, xyz, f->stream);
-      HIP_TRY(hipGetLastError());
-    } else {
-      DevBuf tmp;
+    launch_fill_u32((unsigned*)d_row.p, f->n_particles, 0xffffffffu, f->stream);
+    launch_mark_rows((const long long*)d_idx.p, count, (int*)d_row.p, f->stream);
+    const bool dev_out = is_device_ptr(xyz);
+    DevBuf tmp;
+    float* dst = xyz;
+    if (!dev_out) {
       if ((rc = tmp.reserve(off[count] * 12, 0, f->stream))) return rc;
-      launch_pack_lines((const long long*)d_idx.p, count, (const long long*)d_off.p, (const long long*)f->d_vbase.p,
-                        (const float*)f->d_verts.p, (float*)tmp.p, f->stream);
-      HIP_TRY(hipGetLastError());
-      HIP_TRY(hipMemcpyAsync(xyz, tmp.p, off[count] * 12, hipMemcpyDeviceToHost, f->stream));
-      HIP_TRY(hipStreamSynchronize(f->stream));
+      dst = (float*)tmp.p;
     }
+    launch_scatter_lines(f->log(), n_rec, f->n_particles, (const int*)d_row.p, (const long long*)d_off.p, dst,
+                         f->stream);
+    HIP_TRY(hipGetLastError());
+    if (!dev_out) HIP_TRY(hipMemcpyAsync(xyz, tmp.p, off[count] * 12, hipMemcpyDeviceToHost, f->stream));
+    HIP_TRY(hipStreamSynchronize(f->stream));
   }
   HIP_TRY(hipStreamSynchronize(f->stream));
   return STREAMI_OK;

@@ -28,6 +28,12 @@ struct alignas(16) BlockDev {
   int pad0;
   long long base;    // node index of slice 0 of this block in the node pool
   long long slice_nodes;
+  // byte-offset geometry used by the advection kernel (all < 2^32)
+  unsigned ys, zs;       // linear: bytes per y row / z plane; brick4: bytes per brick row / plane
+  unsigned slice_bytes;  // bytes per time slice
+  unsigned pad1;
+  float fn[3];           // stored nodes per axis as float
+  float inv_fn[3];       // 1/fn (periodic wrap)
 };
 
 // Outbox record, 32 bytes (same layout as streami_outbox_rec).
@@ -42,7 +48,29 @@ struct alignas(8) OutRec {
 static_assert(sizeof(OutRec) == 32, "outbox record must be 32 bytes");
 
 // Per-call counters (zeroed by a fill kernel before each advect launch).
-enum Counter { CTR_QUEUE = 0, CTR_STEPS = 1, CTR_VERTS = 2, CTR_ACCEPT = 3, CTR_FALLBACK = 4, CTR_N = 8 };
+enum Counter {
+  CTR_QUEUE = 0, CTR_STEPS = 1, CTR_VERTS = 2, CTR_ACCEPT = 3, CTR_FALLBACK = 4, CTR_OVERFLOW = 5, CTR_N = 8
+};
+
+// Persistent counters (survive across advect calls; reset by streami_clear).
+enum Persist { PER_OUTBOX = 0, PER_LOG = 1, PER_LOG_REAL = 2, PER_N = 4 };
+
+// Vertex log: a wave appends the vertices its lanes produce in one step as a
+// contiguous run (ballot + mbcnt) inside a chunk it reserved with one atomic,
+// so every store is part of a full, coalesced line.  Each record carries the
+// particle index and the vertex's index within that particle's line; fetching
+// scatters records to their CSR rows without sorting.
+constexpr int LOG_CHUNK = 1024;  // records per wave reservation
+
+struct VertexLog {
+  float* x;
+  float* y;
+  float* z;
+  uint2* pj;                       // (particle index, vertex index)
+  unsigned long long* count;       // records reserved (incl. unused chunk tails)
+  unsigned long long* real;        // records written
+  long long cap;                   // records the buffers hold
+};
 
 struct AdvectArgs {
   const BlockDev* blocks;   // [n_blocks]
@@ -52,8 +80,7 @@ struct AdvectArgs {
   int4* meta;               // steps, max_steps, code, n_verts
   const int4* meta2;        // stride, block, vcap, 0
   const unsigned long long* ids;
-  const long long* vbase;   // first vertex slot of each particle
-  float* verts;             // vertex pool, 3 floats per vertex
+  VertexLog log;
   OutRec* outbox;
   unsigned long long* outbox_count;  // persistent across calls
   unsigned long long* ctr;           // per-call counters

@@ -50,15 +50,14 @@ int launch_ingest(const void* src, void* pool, const BlockDev& B, int fmt, int l
   return 0;
 }
 
-// Initialise n particles at [first, first+n): positions, ids, limits; record
-// the seed as vertex 0 at the slot base the host reserved (vbase[q]); a seed
-// outside the owned bounds of a non-periodic block ends at once (EXIT, 0
-// steps) and goes to the outbox.
+// Initialise n particles at [first, first+n): positions, ids, limits; append
+// the seed as vertex 0 of its line to the vertex log (one atomic per wave); a
+// seed outside the owned bounds of a non-periodic block ends at once (EXIT,
+// 0 steps) and goes to the outbox.
 __global__ void k_seed(const float* xyz, const unsigned long long* ids, unsigned long long auto_id0,
                        const int* max_steps, int default_max, int stride, float t_birth, int blk,
-                       BlockDev B, long long first, long long n, long long vbase0, float4* pos, int4* meta,
-                       int4* meta2, unsigned long long* pid, long long* vbase, float* verts, OutRec* outbox,
-                       unsigned long long* outbox_count) {
+                       BlockDev B, long long first, long long n, float4* pos, int4* meta, int4* meta2,
+                       unsigned long long* pid, VertexLog log, OutRec* outbox, unsigned long long* outbox_count) {
   const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   bool emit = false;
   const long long q = first + i;
@@ -76,13 +75,25 @@ __global__ void k_seed(const float* xyz, const unsigned long long* ids, unsigned
     meta[q] = make_int4(0, m, out ? EXIT : ACTIVE, 1);
     meta2[q] = make_int4(stride, blk, m / stride + 2, 0);
     pid[q] = id;
-    // uniform limits: slots are a fixed stride from vbase0; otherwise the host
-    // has reserved them (prefix over the batch) in vbase[]
-    const long long vb = max_steps ? vbase[q] : vbase0 + i * (long long)(m / stride + 2);
-    if (!max_steps) vbase[q] = vb;
-    float* w = verts + vb * 3;
-    w[0] = x.x; w[1] = x.y; w[2] = x.z;
     emit = out;
+  }
+  // vertex 0 of every new line (the host sized the log for it)
+  const unsigned long long vm = __ballot(i < n);
+  if (vm) {
+    const int lane = __lane_id();
+    unsigned long long b = 0;
+    if (lane == 0) b = atomicAdd(log.count, (unsigned long long)__popcll(vm));
+    b = __shfl(b, 0, 64);
+    if (i < n) {
+      const unsigned long long r = b + __builtin_amdgcn_mbcnt_hi((unsigned)(vm >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)vm, 0u));
+      if (r < (unsigned long long)log.cap) {
+        log.x[r] = x.x;
+        log.y[r] = x.y;
+        log.z[r] = x.z;
+        log.pj[r] = make_uint2((unsigned)q, 0u);
+      }
+    }
+    if (lane == 0) atomicAdd(log.real, (unsigned long long)__popcll(vm));
   }
   const unsigned long long em = __ballot(emit);
   if (em) {
@@ -112,35 +123,69 @@ __global__ void k_seed(const float* xyz, const unsigned long long* ids, unsigned
 
 int launch_seed(const float* xyz, const unsigned long long* ids, unsigned long long auto_id0,
                 const int* max_steps, int default_max, int stride, float t_birth, int blk, const BlockDev& B,
-                long long first, long long n, long long vbase0, float4* pos, int4* meta, int4* meta2,
-                unsigned long long* pid, long long* vbase, float* verts, OutRec* outbox,
+                long long first, long long n, float4* pos, int4* meta, int4* meta2,
+                unsigned long long* pid, const VertexLog& log, OutRec* outbox,
                 unsigned long long* outbox_count, hipStream_t st) {
   if (n <= 0) return 0;
   const long long grid = (n + 255) / 256;
   hipLaunchKernelGGL(k_seed, dim3((unsigned)grid), dim3(256), 0, st, xyz, ids, auto_id0, max_steps, default_max,
-                     stride, t_birth, blk, B, first, n, vbase0, pos, meta, meta2, pid, vbase, verts, outbox,
-                     outbox_count);
+                     stride, t_birth, blk, B, first, n, pos, meta, meta2, pid, log, outbox, outbox_count);
   return 0;
 }
 
-// Copy the recorded vertices of particles idx[0..count) into CSR rows.
-__global__ void k_pack_lines(const long long* idx, long long count, const long long* offsets,
-                             const long long* vbase, const float* verts, float* out) {
-  const long long r = blockIdx.x;  // one workgroup per particle row (grid-stride)
-  for (long long row = r; row < count; row += gridDim.x) {
-    const long long q = idx[row];
-    const long long o = offsets[row], nvert = offsets[row + 1] - o;
-    const float* src = verts + vbase[q] * 3;
-    float* dst = out + o * 3;
-    for (long long e = threadIdx.x; e < nvert * 3; e += blockDim.x) dst[e] = src[e];
+// Scatter log records to CSR rows: record (p, j) of a requested particle
+// (row_of[p] = its row) lands at out[offsets[row] + j].
+__global__ void k_scatter_lines(VertexLog log, long long n_rec, long long n_particles, const int* row_of,
+                                const long long* offsets, float* out) {
+  for (long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x; r < n_rec;
+       r += (long long)gridDim.x * blockDim.x) {
+    const uint2 pj = log.pj[r];
+    if ((long long)pj.x >= n_particles) continue;  // unused tail of a chunk
+    const int row = row_of[pj.x];
+    if (row < 0) continue;
+    const long long o = offsets[row] + pj.y;
+    if (o >= offsets[row + 1]) continue;
+    out[o * 3 + 0] = log.x[r];
+    out[o * 3 + 1] = log.y[r];
+    out[o * 3 + 2] = log.z[r];
   }
 }
 
-int launch_pack_lines(const long long* idx, long long count, const long long* offsets, const long long* vbase,
-                      const float* verts, float* out, hipStream_t st) {
+int launch_scatter_lines(const VertexLog& log, long long n_rec, long long n_particles, const int* row_of,
+                         const long long* offsets, float* out, hipStream_t st) {
+  if (n_rec <= 0) return 0;
+  long long grid = (n_rec + 255) / 256;
+  if (grid > 65536) grid = 65536;
+  hipLaunchKernelGGL(k_scatter_lines, dim3((unsigned)grid), dim3(256), 0, st, log, n_rec, n_particles, row_of,
+                     offsets, out);
+  return 0;
+}
+
+// row_of[idx[r]] = r for the requested rows (row_of was filled with -1).
+__global__ void k_mark_rows(const long long* idx, long long count, int* row_of) {
+  for (long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x; r < count;
+       r += (long long)gridDim.x * blockDim.x)
+    row_of[idx[r]] = (int)r;
+}
+
+int launch_mark_rows(const long long* idx, long long count, int* row_of, hipStream_t st) {
   if (count <= 0) return 0;
-  int grid = (int)(count < 65536 ? count : 65536);
-  hipLaunchKernelGGL(k_pack_lines, dim3(grid), dim3(256), 0, st, idx, count, offsets, vbase, verts, out);
+  long long grid = (count + 255) / 256;
+  if (grid > 65536) grid = 65536;
+  hipLaunchKernelGGL(k_mark_rows, dim3((unsigned)grid), dim3(256), 0, st, idx, count, row_of);
+  return 0;
+}
+
+__global__ void k_fill_u32(unsigned* p, long long n, unsigned v) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+int launch_fill_u32(unsigned* p, long long n, unsigned v, hipStream_t st) {
+  if (n <= 0) return 0;
+  long long grid = (n + 255) / 256;
+  if (grid > 65536) grid = 65536;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)grid), dim3(256), 0, st, p, n, v);
   return 0;
 }
 
