@@ -92,12 +92,179 @@ def cpu_baseline(blk, seeds, h, m, budget_s=12.0):
                 seconds=round(total_t, 2))
 
 
+def surrogate_bench(args):
+    """Learned flow-map form on the ABC field: train on GPU-generated 16-step windows, then
+    advect seeds for 2000 steps with plain RK4, with the surrogate (both residual kinds) and
+    with one RK4 step of 16h per jump (the surrogate's gather budget without the network)."""
+    import torch
+    import fieldgen as fg
+    import oracle
+    import paper_2606_02627_amd as S
+    from paper_2606_02627_amd import surrogate
+
+    h, steps = 0.01, 2000
+    n_train = int(os.environ.get("STREAMI_SURR_TRAIN", 1 << 23))
+    n_inf = int(os.environ.get("STREAMI_SURR_SEEDS", 1 << 22))
+    epochs = int(os.environ.get("STREAMI_SURR_EPOCHS", 12))
+    blk = fg.abc_block(32)
+    ext = 2 * np.pi
+    log(f"training windows: {n_train}")
+    t0 = time.perf_counter()
+    x0, d = surrogate.flow_map_windows(blk, fg.training_starts(5, n_train, ext), h)
+    t_data = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    net, sigma, hist = surrogate.train(x0, d, fg.mlp_init(5), ext, epochs=epochs, batch=8192, lr=2e-3, log=log)
+    t_train = time.perf_counter() - t0
+    del x0, d
+    seeds = fg.uniform_seeds(5, n_inf, (0, 0, 0), (ext,) * 3, sub=21)
+    d_seeds = torch.from_numpy(seeds).cuda()
+    sample = 4096
+    ref = oracle.Field.from_block(blk).trace(seeds[:sample], float(np.float32(h)), steps, keep_verts=False)
+
+    def run(label, hh, m, **kw):
+        f = S.Field([blk], S.F32)
+        best = None
+        for _ in range(max(1, args.steps)):
+            f.clear()
+            f.seed(0, d_seeds, default_max_steps=m, record_stride=16 if m >= 16 else 1)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            st = S.streami_advect(f.h, S.advect_params(hh, **kw))
+            wall = time.perf_counter() - t
+            best = wall if best is None else min(best, wall)
+        L = f.lines(0, 0, sample)
+        f.close()
+        end = L["xyz"][L["offsets"][1:] - 1].astype(np.float64)
+        err = np.abs(end - ref["final_pos"]).max(axis=1) / ext
+        acc = st.surrogate_accepted / max(1, st.surrogate_accepted + st.surrogate_fallback)
+        r = dict(label=label, seconds=best, equiv_steps_per_s=n_inf * steps / best, device_ms=st.device_ms,
+                 acceptance=acc if kw.get("mode") == S.MODE_SURROGATE else None,
+                 endpoint_err_over_extent=dict(median=float(np.median(err)), p90=float(np.quantile(err, 0.9)),
+                                               max=float(err.max()),
+                                               frac_within_2e_3=float((err <= 2e-3).mean())))
+        log(json.dumps(r))
+        return r
+
+    res = [run("plain-rk4", h, steps),
+           run("rk4-16h-per-jump", 16 * h, steps // 16),
+           run("surrogate-kind1-bigstep-residual", h, steps, mode=S.MODE_SURROGATE, mlp=net,
+               residual_tol_cells=1e-3, residual_kind=1),
+           run("surrogate-kind0-commutation-residual", h, steps, mode=S.MODE_SURROGATE, mlp=net,
+               residual_tol_cells=1e-3, residual_kind=0)]
+    S.streami_mlp_destroy(net)
+    plain = res[0]
+    best_sur = max(res[2:], key=lambda r: r["equiv_steps_per_s"])
+    out = {
+        "metric": "RK4 particle-steps/s + HBM GB/s; surrogate vs plain at fixed endpoint error",
+        "value": best_sur["equiv_steps_per_s"], "unit": "equivalent particle-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": 0, "ms_per_step": best_sur["seconds"] * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 MFMA (fp32 accumulate) + f32 RK4", "data": "synthetic",
+        "config": {"workload": "surrogate-abc", "field": "ABC 32^3 periodic f32", "train_windows": n_train,
+                   "epochs": epochs, "seeds": n_inf, "steps": steps, "h": h, "residual_tol_cells": 1e-3},
+        "speedup_vs_plain": best_sur["equiv_steps_per_s"] / plain["equiv_steps_per_s"],
+        "runs": res, "train_seconds": t_train, "data_seconds": t_data,
+        "final_loss": hist[-1]["loss"] if hist else None, "sigma": [float(v) for v in sigma],
+    }
+    print(json.dumps(out), flush=True)
+
+
+def batched_bench(args, unsteady=False):
+    """96 uneven FP16 blocks with uneven seed sets and trajectory lengths in one persistent
+    launch (hipGraph replay, autotuned launch shape); unsteady: 16 time slices and
+    streakline emitters releasing a particle every 10 steps."""
+    import torch
+    import fieldgen as fg
+    import paper_2606_02627_amd as S
+    from paper_2606_02627_amd import autotune
+
+    h = 0.5
+    t0 = time.perf_counter()
+    if unsteady:
+        blocks, emit, elim = fg.batched_blocks(n_blocks=96, fmt=fg.F16, n_slices=16, n_modes=64,
+                                               seed_scale=float(os.environ.get("STREAMI_STREAK_SCALE", 1 / 16)))
+        seeds, limits, births = [], [], []
+        for e, m in zip(emit, elim):
+            pos, tb, lim, _ = fg.streakline_particles(e, m, 10, h)
+            seeds.append(pos), limits.append(lim), births.append(tb)
+        stride = 1 << 20  # a streakline is the emitters' particles' final positions: keep seed + last vertex
+    else:
+        blocks, seeds, limits = fg.batched_blocks(n_blocks=96, fmt=fg.F16)
+        births = None
+        stride = 1
+    n_part = sum(len(x) for x in seeds)
+    log(f"inputs: {len(blocks)} blocks, {n_part} particles, generated in {time.perf_counter() - t0:.1f}s")
+    tuned = autotune.load(blocks, seeds, fg.F16, h)
+    if tuned is None:
+        tuned = autotune.tune(blocks, seeds, limits, fg.F16, h, record_stride=stride, log=log)
+    cfg = {k: tuned[k] for k in ("waves_per_cu", "refill_threshold", "work_order")}
+    f = S.Field(blocks, fg.F16, layout=tuned["layout"])
+    dseeds = [torch.from_numpy(x).cuda() for x in seeds]
+    dlim = [torch.from_numpy(x).cuda() for x in limits]
+    dtb = [torch.from_numpy(x).cuda() for x in births] if births else None
+
+    def one_pass(stats=False):
+        f.clear()
+        for b in range(len(blocks)):
+            f.seed(b, dseeds[b], max_steps=dlim[b], record_stride=stride, t_births=dtb[b] if dtb else None)
+        return S.streami_advect(f.h, S.advect_params(h, use_graph=1, **cfg), want_stats=stats)
+
+    st0 = one_pass(stats=True)
+    for _ in range(max(0, args.warmup - 1)):
+        one_pass()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        one_pass()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t) / args.steps
+    steps_per_pass = int(st0.steps)
+    # baseline: the same work as one launch per block
+    fields = [S.Field([b], fg.F16, layout=tuned["layout"]) for b in blocks]
+
+    def per_block_pass():
+        for k, fb in enumerate(fields):
+            fb.clear()
+            fb.seed(0, dseeds[k], max_steps=dlim[k], record_stride=stride, t_births=dtb[k] if dtb else None)
+            S.streami_advect(fb.h, S.advect_params(h), want_stats=False)
+
+    per_block_pass()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    per_block_pass()
+    torch.cuda.synchronize()
+    wall_pb = time.perf_counter() - t
+    for fb in fields:
+        fb.close()
+    value = steps_per_pass / wall
+    vals = 192 if unsteady else 96
+    alg = steps_per_pass * vals * 2 + int(st0.vertices) * 20
+    out = {
+        "metric": "RK4 particle-steps/s + HBM GB/s; surrogate vs plain at fixed endpoint error",
+        "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f16 storage, f32 math", "data": "synthetic",
+        "config": {"workload": "batched96-f16" + ("-streaklines" if unsteady else ""), "blocks": len(blocks),
+                   "particles": n_part, "particle_steps_per_step": steps_per_pass, "slices": 16 if unsteady else 1,
+                   "tuned": {k: tuned[k] for k in ("layout", "waves_per_cu", "refill_threshold", "work_order")},
+                   "graph": True},
+        "roofline": {"bound": "hbm", "achieved": alg / wall / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": alg / wall / 1e9 / HBM_PEAK_GBS, "traffic": None, "kernel": "k_advect (batched)"},
+        "one_block_per_launch_steps_per_s": steps_per_pass / wall_pb,
+        "batching_speedup": wall_pb / wall,
+        "terminated": list(st0.terminated),
+    }
+    f.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="turb256-f32", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="turb256-f32",
+                    choices=sorted(WORKLOADS) + ["surrogate-abc", "batched96-f16", "batched96-f16-streaklines"])
     ap.add_argument("--layout", type=int, default=0, help="0 auto, 1 linear, 2 brick4")
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--refill", type=int, default=0)
@@ -117,6 +284,10 @@ def main():
     import paper_2606_02627_amd as S
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    if args.workload == "surrogate-abc":
+        return surrogate_bench(args)
+    if args.workload.startswith("batched96"):
+        return batched_bench(args, unsteady=args.workload.endswith("streaklines"))
     dev = torch.device("cuda:0")
     log("building inputs", args.workload)
     t0 = time.perf_counter()

@@ -317,3 +317,74 @@ def int_uniform(config: int, purpose: int, n: int, lo: int, hi: int, sub: int = 
     """n integers uniform in {lo..hi} (inclusive)."""
     u = uniform(stream(config, purpose, sub), n)
     return (lo + np.floor(u * (hi - lo + 1))).astype(np.int64).clip(lo, hi)
+
+
+# ---------------------------------------------------------------------------
+# Learned flow-map surrogate: initial weights and training samples
+# ---------------------------------------------------------------------------
+MLP_WIDTHS = (3, 256, 256, 256, 256, 3)
+
+
+def mlp_init(config: int = 5, widths=MLP_WIDTHS, sub: int = 0):
+    """Initial parameters, U(-1/sqrt(fan_in), 1/sqrt(fan_in)), FP32: list of (W [out, in], b [out])."""
+    params = []
+    for l in range(len(widths) - 1):
+        fi, fo = widths[l], widths[l + 1]
+        r = 1.0 / np.sqrt(fi)
+        w = (uniform(stream(config, P_MLP, sub * 64 + 2 * l), fo * fi) * 2 - 1) * r
+        b = (uniform(stream(config, P_MLP, sub * 64 + 2 * l + 1), fo) * 2 - 1) * r
+        params.append((w.reshape(fo, fi).astype(np.float32), b.astype(np.float32)))
+    return params
+
+
+def training_starts(config: int, n: int, period: float, sub: int = 0) -> np.ndarray:
+    """n FP32 start points uniform in [0, period)^3 for flow-map training windows."""
+    return uniform_seeds(config, n, (0, 0, 0), (period,) * 3, sub=1000 + sub)
+
+
+# ---------------------------------------------------------------------------
+# Batched uneven blocks
+# ---------------------------------------------------------------------------
+def batched_blocks(config: int = 4, n_blocks: int = 96, edge_lo: int = 32, edge_hi: int = 192,
+                   fmt: int = F16, n_slices: int = 1, n_modes: int = 512, h: float = 0.5,
+                   m_lo: int = 100, m_hi: int = 5000, seeds_lo: int = 1024, seeds_hi: int = 65536,
+                   seed_scale: float = 1.0):
+    """Independent turbulence blocks with uneven shapes and seed sets.
+
+    Each axis edge ~ U{edge_lo..edge_hi}; each block its own generator
+    realisation (sub-stream b), normalised per block; seeds per block
+    round(exp(U[ln seeds_lo, ln seeds_hi])) * seed_scale, uniform in the block;
+    per-seed step limits ~ U{m_lo..m_hi}.  With n_slices > 1 the slices are
+    spaced slice_dt = m_hi*h/(n_slices-1) so the longest seeds span them all.
+    Returns (blocks, seeds per block, max steps per block).
+    """
+    edges = int_uniform(config, P_BLOCKSHAPE, n_blocks * 3, edge_lo, edge_hi).reshape(n_blocks, 3)
+    counts = np.round(np.exp(np.log(seeds_lo) + uniform(stream(config, P_NSEEDS), n_blocks)
+                             * (np.log(seeds_hi) - np.log(seeds_lo))) * seed_scale).astype(np.int64)
+    counts = np.maximum(counts, 1)
+    slice_dt = m_hi * h / (n_slices - 1) if n_slices > 1 else 1.0
+    blocks, seeds, limits = [], [], []
+    for b in range(n_blocks):
+        dims = tuple(int(v) for v in edges[b])
+        blk = Block(dims=dims, ghost=1, origin=(0.5, 0.5, 0.5), spacing=(1.0, 1.0, 1.0), lo=(0.0, 0.0, 0.0),
+                    hi=tuple(float(v) for v in dims), boundary=BOUNDARY_BLOCK, rank_grid=(1, 1, 1),
+                    rank_coord=(0, 0, 0), n_slices=n_slices, t0=0.0, slice_dt=slice_dt)
+        blk.values = turbulence_values(config, dims, sub=b, n_slices=n_slices, n_modes=n_modes)
+        blocks.append(blk.quantise(fmt))
+        seeds.append(uniform_seeds(config, int(counts[b]), (0, 0, 0), dims, sub=10 + b))
+        limits.append(int_uniform(config, P_MAXSTEPS, int(counts[b]), m_lo, m_hi, sub=b).astype(np.int32))
+    return blocks, seeds, limits
+
+
+def streakline_particles(emitters: np.ndarray, limits: np.ndarray, every: int, h: float):
+    """Particles released by emitters every `every` steps: emitter e releases at steps
+    0, every, 2*every, ... < limits[e]; the particle born at step b runs to step
+    limits[e] (limit limits[e] - b) from time b*h.  Returned emitter-major,
+    birth-minor: (positions, birth times, step limits, emitter index)."""
+    births = [np.arange(0, int(m), every) for m in limits]
+    emi = np.concatenate([np.full(len(b), e, np.int64) for e, b in enumerate(births)])
+    bsteps = np.concatenate(births)
+    pos = np.ascontiguousarray(emitters[emi], np.float32)
+    tb = (bsteps * h).astype(np.float32)
+    lim = (np.asarray(limits)[emi] - bsteps).astype(np.int32)
+    return pos, tb, lim, emi

@@ -135,6 +135,9 @@ typedef struct {
   int32_t record_stride;     /* keep vertex j when j % stride == 0, and the final vertex; >= 1 */
   int32_t inputs_on_device;  /* 1: xyz/ids/max_steps are device pointers */
   float t_birth;             /* time of step 0 of these particles (unsteady fields) */
+  const float* t_births;     /* per-particle birth times (host or device like xyz) or NULL:
+                                streaklines release particles from the same emitter at
+                                different times (Sec. 3.2) */
 } streami_seed_opts;
 
 /*
@@ -164,6 +167,8 @@ typedef struct {
   int32_t use_graph;        /* 1: capture the launch sequence in a hipGraph and replay it */
   int32_t no_cell_cache;    /* 1: re-gather a cell's corners at every sample (A/B measurement;
                                results are bit-identical either way) */
+  int32_t work_order;       /* 0: spatial order (block, Morton brick) split over per-XCD queues;
+                               1: seed order, one queue (results are bit-identical either way) */
 } streami_advect_params;
 
 typedef struct {
@@ -228,6 +233,33 @@ int streami_clear(streami_field f);
 
 /* Particle counts of a block (for sizing fetch buffers). */
 int streami_block_info(streami_field f, int32_t block, int64_t* n_particles, int64_t* n_vertices);
+
+/* ---------------------------------------------------------------------------
+ * Learned flow-map surrogate (not part of the paper: one of the forms this
+ * library adds).  A multilayer perceptron maps a position to the displacement
+ * of 16 plain RK4 steps:
+ *   xhat = 2 (x mod L)/L - 1;  h0 = xhat;  h_{l+1} = SiLU(W_l h_l + b_l), l = 0..3,
+ *   widths 3 -> 256 -> 256 -> 256 -> 256;  out = sigma * (W_4 h_4 + b_4)   [3].
+ * Weights and activations enter the matrix cores as BF16 with FP32
+ * accumulation; FP32 master weights are updated by Adam (b1 = 0.9,
+ * b2 = 0.999, eps = 1e-8).  Parameter order of every flat array below: for
+ * l = 0..4, W_l (row-major [out x in]) then b_l; 199,171 floats in total.
+ * All xyz/target/out arrays are device pointers (n x 3 FP32).
+ * ------------------------------------------------------------------------- */
+int streami_mlp_create(const float* params, const float* sigma, float period, void* hip_stream,
+                       streami_mlp* out);
+int streami_mlp_destroy(streami_mlp m);
+int streami_mlp_set_params(streami_mlp m, const float* params);  /* host array */
+int streami_mlp_get_params(streami_mlp m, float* params);        /* host array */
+/* Network output for n positions (enqueued on the network's stream). */
+int streami_mlp_forward(streami_mlp m, const float* xyz, int64_t n, float* out);
+/* One training step on `batch` samples: loss = mean(((out - target)/sigma)^2);
+ * backprop; Adam with learning rate lr (lr = 0: gradients only).  loss_out
+ * (host, nullable) receives the batch loss; grads_out (host, nullable,
+ * 199,171 floats) the gradients of this step.  Waits for the stream when
+ * either output is requested. */
+int streami_mlp_train_step(streami_mlp m, const float* xyz, const float* target, int64_t batch, float lr,
+                           float* loss_out, float* grads_out);
 
 /* Thread-local description of the last error. */
 const char* streami_last_error(void);

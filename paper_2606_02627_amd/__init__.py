@@ -51,7 +51,8 @@ class FieldOpts(ctypes.Structure):
 
 class SeedOpts(ctypes.Structure):
     _fields_ = [("default_max_steps", ctypes.c_int32), ("record_stride", ctypes.c_int32),
-                ("inputs_on_device", ctypes.c_int32), ("t_birth", ctypes.c_float)]
+                ("inputs_on_device", ctypes.c_int32), ("t_birth", ctypes.c_float),
+                ("t_births", ctypes.c_void_p)]
 
 
 class AdvectParams(ctypes.Structure):
@@ -60,7 +61,7 @@ class AdvectParams(ctypes.Structure):
                 ("mlp", ctypes.c_void_p), ("residual_tol_cells", ctypes.c_float),
                 ("residual_kind", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
                 ("refill_threshold", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("no_cell_cache", ctypes.c_int32)]
+                ("no_cell_cache", ctypes.c_int32), ("work_order", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -100,6 +101,12 @@ def _load():
         "streami_fetch_outbox": [vp, vp, i64, vp],
         "streami_block_info": [vp, i32, vp, vp],
         "streami_clear": [vp],
+        "streami_mlp_create": [vp, vp, ctypes.c_float, vp, vp],
+        "streami_mlp_destroy": [vp],
+        "streami_mlp_set_params": [vp, vp],
+        "streami_mlp_get_params": [vp, vp],
+        "streami_mlp_forward": [vp, vp, i64, vp],
+        "streami_mlp_train_step": [vp, vp, vp, i64, ctypes.c_float, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -178,16 +185,19 @@ def streami_field_destroy(f):
 
 
 def streami_seed(f, block, xyz, ids=None, max_steps=None, default_max_steps=0, record_stride=1,
-                 t_birth=0.0):
+                 t_birth=0.0, t_births=None):
     px, dx = _addr(xyz)
     pi, di = _addr(ids)
     pm, dm = _addr(max_steps)
+    pt, dt = _addr(t_births)
     on_dev = dx
-    if (ids is not None and di != on_dev) or (max_steps is not None and dm != on_dev):
-        raise ValueError("xyz, ids and max_steps must all be host or all device arrays")
+    if ((ids is not None and di != on_dev) or (max_steps is not None and dm != on_dev)
+            or (t_births is not None and dt != on_dev)):
+        raise ValueError("xyz, ids, max_steps and t_births must all be host or all device arrays")
     n = (xyz.numel() if hasattr(xyz, "numel") else xyz.size) // 3
     opts = SeedOpts(default_max_steps=int(default_max_steps), record_stride=int(record_stride),
-                    inputs_on_device=int(on_dev), t_birth=float(t_birth))
+                    inputs_on_device=int(on_dev), t_birth=float(t_birth),
+                    t_births=None if pt is None else pt.value)
     return _check(_load().streami_seed(f, int(block), px, pi, pm, int(n), ctypes.byref(opts)))
 
 
@@ -233,7 +243,8 @@ def advect_params(h, step_budget=0, eps=1e-6, **kw):
     p.step_budget = int(step_budget)
     p.stagnation_eps = float(eps)
     p.mode = kw.pop("mode", MODE_PLAIN)
-    p.mlp = kw.pop("mlp", None)
+    net = kw.pop("mlp", None)
+    p.mlp = net.value if isinstance(net, ctypes.c_void_p) else net
     for k, v in kw.items():
         setattr(p, k, v)
     return p
@@ -294,3 +305,67 @@ class Field:
             if rc != E_CAPACITY:
                 break
         return np.concatenate(recs)
+
+
+# ---------------------------------------------------------------- surrogate network
+MLP_WIDTHS = (3, 256, 256, 256, 256, 3)
+MLP_N_PARAMS = sum(MLP_WIDTHS[i] * MLP_WIDTHS[i + 1] + MLP_WIDTHS[i + 1] for i in range(5))
+
+
+def flatten_params(params):
+    """[(W, b), ...] -> flat FP32 array in the library's parameter order."""
+    return np.ascontiguousarray(np.concatenate([np.concatenate([np.asarray(W, np.float32).ravel(),
+                                                                np.asarray(b, np.float32).ravel()])
+                                                for W, b in params]), np.float32)
+
+
+def unflatten_params(flat):
+    out, off = [], 0
+    for i in range(5):
+        fi, fo = MLP_WIDTHS[i], MLP_WIDTHS[i + 1]
+        W = flat[off:off + fi * fo].reshape(fo, fi)
+        off += fi * fo
+        b = flat[off:off + fo]
+        off += fo
+        out.append((W, b))
+    return out
+
+
+def streami_mlp_create(params, sigma, period, stream=None):
+    flat = flatten_params(params) if isinstance(params, (list, tuple)) else np.ascontiguousarray(params, np.float32)
+    assert flat.size == MLP_N_PARAMS
+    sig = np.ascontiguousarray(sigma, np.float32)
+    out = ctypes.c_void_p()
+    _check(_load().streami_mlp_create(_addr(flat)[0], _addr(sig)[0], float(period), _stream(stream),
+                                      ctypes.byref(out)))
+    return out
+
+
+def streami_mlp_destroy(m):
+    return _check(_load().streami_mlp_destroy(m))
+
+
+def streami_mlp_get_params(m):
+    flat = np.zeros(MLP_N_PARAMS, np.float32)
+    _check(_load().streami_mlp_get_params(m, _addr(flat)[0]))
+    return flat
+
+
+def streami_mlp_set_params(m, params):
+    flat = flatten_params(params) if isinstance(params, (list, tuple)) else np.ascontiguousarray(params, np.float32)
+    return _check(_load().streami_mlp_set_params(m, _addr(flat)[0]))
+
+
+def streami_mlp_forward(m, xyz, out):
+    n = xyz.numel() // 3
+    return _check(_load().streami_mlp_forward(m, _addr(xyz)[0], int(n), _addr(out)[0]))
+
+
+def streami_mlp_train_step(m, xyz, target, lr, want_loss=True, want_grads=False):
+    n = xyz.numel() // 3
+    loss = ctypes.c_float()
+    grads = np.zeros(MLP_N_PARAMS, np.float32) if want_grads else None
+    _check(_load().streami_mlp_train_step(m, _addr(xyz)[0], _addr(target)[0], int(n), float(lr),
+                                          ctypes.byref(loss) if want_loss else None,
+                                          _addr(grads)[0] if want_grads else None))
+    return (loss.value if want_loss else None), grads

@@ -6,4 +6,8 @@ int launch_advect_f16(const AdvectArgs& a, int layout, bool periodic, int mode, 
                       hipStream_t st) {
   return launch_advect_fmt<FMT_F16>(a, layout, periodic, mode, batched, grid, st);
 }
+int launch_surrogate_f16(const SurrogateArgs& s, int layout, bool periodic, bool pre, int grid,
+                          hipStream_t st) {
+  return launch_surrogate_fmt<FMT_F16>(s, layout, periodic, pre, grid, st);
+}
 }  // namespace streami

@@ -295,19 +295,27 @@ __global__ void __launch_bounds__(256) k_advect(AdvectArgs A) {
   smp.reset();
   bool queue_done = false;  // wave-uniform
   const unsigned long long all = __ballot(1);
+  const long long n_work = A.order ? (long long)*A.n_work : A.n_particles;
+  int q = (int)(blockIdx.x % (unsigned)A.n_queues), tries = 0;
 
   while (true) {
     const unsigned long long dead = __ballot(p < 0);
     if (!queue_done && dead != 0 && (__popcll(dead) >= A.refill || dead == all)) {
       const int cnt = __popcll(dead);
       const int leader = __ffsll((long long)dead) - 1;
+      const long long qlo = n_work * q / A.n_queues, qhi = n_work * (q + 1) / A.n_queues;
       unsigned long long qbase = 0;
-      if (lane == leader) qbase = atomicAdd(&A.ctr[CTR_QUEUE], (unsigned long long)cnt);
+      if (lane == leader) qbase = atomicAdd(&A.qctr[q * QCTR_STRIDE], (unsigned long long)cnt);
       qbase = __shfl(qbase, leader, 64);
-      if (qbase + cnt >= (unsigned long long)A.n_particles) queue_done = true;
+      const long long first = qlo + (long long)qbase;
+      if (first + cnt >= qhi) {  // this range is used up: continue with the next one
+        q = (q + 1 == A.n_queues) ? 0 : q + 1;
+        if (++tries == A.n_queues) queue_done = true;
+      }
       if (p < 0) {
-        const long long my = (long long)(qbase + lanes_below(dead));
-        if (my < A.n_particles) {
+        const long long slot = first + (long long)lanes_below(dead);
+        if (slot < qhi) {
+          const long long my = A.order ? (long long)A.order[slot] : slot;
           const int4 mt = A.meta[my];
           if (mt.z == ACTIVE) {
             p = (int)my;
@@ -432,6 +440,194 @@ __global__ void __launch_bounds__(256) k_advect(AdvectArgs A) {
       atomicAdd(A.log.real, v);
     }
   }
+}
+
+// ---------------------------------------------------------------- surrogate jumps
+// Pre-pass of the commutation residual: xh = one plain RK4 step from x.
+template <int FMT, int LAYOUT, bool PERIODIC>
+__global__ void __launch_bounds__(256) k_sur_pre(SurrogateArgs S) {
+  constexpr unsigned NB = NodeBytes<FMT>::v;
+  const AdvectArgs& A = S.a;
+  const BlockDev B = A.blocks[0];
+  const char* base = reinterpret_cast<const char*>(A.nodes) + (size_t)B.base * NB;
+  Sampler<FMT, LAYOUT, PERIODIC, SM_CACHED> smp;
+  for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < A.n_particles;
+       q += (long long)gridDim.x * blockDim.x) {
+    if (A.meta[q].z != ACTIVE) continue;
+    smp.reset();
+    const float4 ps = A.pos[q];
+    float3 P1 = make_float3(ps.x, ps.y, ps.z), fail;
+    const int4 mt = A.meta[q];
+    const float t = fmaf((float)mt.x, A.h, ps.w);
+    if (rk4_step(smp, B, base, make_float3(ps.x, ps.y, ps.z), t, A.h, A.eps2, P1, fail) != ACTIVE)
+      P1 = make_float3(ps.x, ps.y, ps.z);
+    S.xh[3 * q] = P1.x;
+    S.xh[3 * q + 1] = P1.y;
+    S.xh[3 * q + 2] = P1.z;
+  }
+}
+
+// Accept the network's jump when its residual is within tol, else advance by
+// plain RK4 steps; particles whose step count is not a multiple of the jump,
+// or that have fewer than a jump's steps left, take plain steps to the next
+// multiple.  One vertex per particle per call at most (record strides are
+// multiples of the jump), appended with one atomic per wave.
+template <int FMT, int LAYOUT, bool PERIODIC>
+__global__ void __launch_bounds__(256) k_sur_apply(SurrogateArgs S) {
+  constexpr unsigned NB = NodeBytes<FMT>::v;
+  const AdvectArgs& A = S.a;
+  const BlockDev B = A.blocks[0];
+  const char* base = reinterpret_cast<const char*>(A.nodes) + (size_t)B.base * NB;
+  const int lane = __lane_id();
+  Sampler<FMT, LAYOUT, PERIODIC, SM_CACHED> smp;
+  unsigned my_steps = 0, acc = 0, fb = 0;
+  for (long long q0 = blockIdx.x * (long long)blockDim.x; q0 < A.n_particles; q0 += (long long)gridDim.x * blockDim.x) {
+    const long long q = q0 + threadIdx.x;
+    int term = ACTIVE, dest = -1;
+    bool rec = false, active = false;
+    float3 P = make_float3(0.f, 0.f, 0.f), opos = P;
+    int4 mt = make_int4(0, 0, 0, 0);
+    int stride = 1;
+    float tb = 0.f;
+    if (q < A.n_particles) {
+      mt = A.meta[q];
+      active = mt.z == ACTIVE;
+    }
+    if (active) {
+      smp.reset();
+      const float4 ps = A.pos[q];
+      P = make_float3(ps.x, ps.y, ps.z);
+      opos = P;
+      tb = ps.w;
+      stride = A.meta2[q].x;
+      int n = mt.x;
+      const int m = mt.y;
+      int target = ((n / S.jump) + 1) * S.jump;
+      if (target > m) target = m;
+      bool plain = (n % S.jump) != 0 || m - n < S.jump;
+      if (n >= m) {
+        term = MAX_STEPS;
+      } else if (!plain) {
+        const float3 d = make_float3(S.dhat[3 * q], S.dhat[3 * q + 1], S.dhat[3 * q + 2]);
+        const float3 Y = make_float3(P.x + d.x, P.y + d.y, P.z + d.z);
+        float3 ref, fail;
+        float r = 3.0e38f;
+        const float t = fmaf((float)n, A.h, tb);
+        if (S.kind == 1) {
+          if (rk4_step(smp, B, base, P, t, S.jump * A.h, A.eps2, ref, fail) == ACTIVE)
+            r = fmaxf(fabsf(Y.x - ref.x), fmaxf(fabsf(Y.y - ref.y), fabsf(Y.z - ref.z)));
+        } else {
+          const float3 d2 = make_float3(S.dhat2[3 * q], S.dhat2[3 * q + 1], S.dhat2[3 * q + 2]);
+          const float3 xh = make_float3(S.xh[3 * q], S.xh[3 * q + 1], S.xh[3 * q + 2]);
+          if (rk4_step(smp, B, base, Y, t + S.jump * A.h, A.h, A.eps2, ref, fail) == ACTIVE)
+            r = fmaxf(fabsf(xh.x + d2.x - ref.x), fmaxf(fabsf(xh.y + d2.y - ref.y), fabsf(xh.z + d2.z - ref.z)));
+        }
+        if (r <= S.tol && __builtin_isfinite(Y.x + Y.y + Y.z)) {
+          P = Y;
+          n += S.jump;
+          my_steps += S.jump;
+          ++acc;
+          if (!PERIODIC && !inside(B, P)) {
+            term = EXIT;
+            dest = dest_id(B, P);
+            opos = P;
+          } else if (n == m) {
+            term = MAX_STEPS;
+          }
+          rec = term != ACTIVE || n % stride == 0;
+        } else {
+          plain = true;
+          ++fb;
+        }
+      }
+      if (plain && term == ACTIVE) {
+        smp.reset();
+        while (n < target) {
+          float3 P1, fail;
+          const float t = fmaf((float)n, A.h, tb);
+          const int st = rk4_step(smp, B, base, P, t, A.h, A.eps2, P1, fail);
+          if (st != ACTIVE) {
+            term = st;
+            if (st == HALO_MISS) {
+              dest = dest_id(B, fail);
+              opos = P;
+            }
+            break;
+          }
+          P = P1;
+          ++n;
+          ++my_steps;
+          if (!PERIODIC && !inside(B, P)) {
+            term = EXIT;
+            dest = dest_id(B, P);
+            opos = P;
+            break;
+          }
+        }
+        if (term == ACTIVE && n == m) term = MAX_STEPS;
+        rec = term != ACTIVE || n % stride == 0;
+      }
+      mt.x = n;
+    }
+    // one log record per recording lane (exact reservation, one atomic per wave)
+    const unsigned long long vm = __ballot(rec);
+    if (vm) {
+      unsigned long long b = 0;
+      const int leader = __ffsll((long long)vm) - 1;
+      if (lane == leader) b = atomicAdd(A.log.count, (unsigned long long)__popcll(vm));
+      b = __shfl(b, leader, 64);
+      if (rec) {
+        const unsigned long long r = b + lanes_below(vm);
+        if (r < (unsigned long long)A.log.cap) {
+          A.log.x[r] = P.x;
+          A.log.y[r] = P.y;
+          A.log.z[r] = P.z;
+          A.log.pj[r] = make_uint2((unsigned)q, (unsigned)mt.w);
+        }
+        ++mt.w;
+      }
+      if (lane == leader) atomicAdd(A.log.real, (unsigned long long)__popcll(vm));
+    }
+    const bool emit = term == EXIT || term == HALO_MISS;
+    const unsigned long long em = __ballot(emit);
+    if (em) {
+      const int leader = __ffsll((long long)em) - 1;
+      unsigned long long ob = 0;
+      if (lane == leader) ob = atomicAdd(A.outbox_count, (unsigned long long)__popcll(em));
+      ob = __shfl(ob, leader, 64);
+      if (emit) {
+        OutRec rr;
+        rr.id = A.ids[q];
+        rr.pos[0] = opos.x; rr.pos[1] = opos.y; rr.pos[2] = opos.z;
+        rr.steps = mt.x;
+        rr.dest = dest;
+        rr.code = (short)term;
+        rr.block = 0;
+        A.outbox[ob + lanes_below(em)] = rr;
+      }
+    }
+    if (active) {
+      A.pos[q] = make_float4(P.x, P.y, P.z, tb);
+      A.meta[q] = make_int4(mt.x, mt.y, term, mt.w);
+    }
+  }
+  const unsigned long long s = wave_sum(my_steps), a1 = wave_sum(acc), f1 = wave_sum(fb);
+  if (lane == 0) {
+    if (s) atomicAdd(&A.ctr[CTR_STEPS], s);
+    if (a1) atomicAdd(&A.ctr[CTR_ACCEPT], a1);
+    if (f1) atomicAdd(&A.ctr[CTR_FALLBACK], f1);
+  }
+}
+
+template <int FMT>
+int launch_surrogate_fmt(const SurrogateArgs& s, int layout, bool periodic, bool pre, int grid, hipStream_t st) {
+#define STREAMI_S(LAY, PER)                                                                        if (pre) hipLaunchKernelGGL((k_sur_pre<FMT, LAY, PER>), dim3(grid), dim3(256), 0, st, s);        else hipLaunchKernelGGL((k_sur_apply<FMT, LAY, PER>), dim3(grid), dim3(256), 0, st, s);          return 0;
+  if (layout == LAYOUT_BRICK4) {
+    if (periodic) { STREAMI_S(LAYOUT_BRICK4, true) } else { STREAMI_S(LAYOUT_BRICK4, false) }
+  } else {
+    if (periodic) { STREAMI_S(LAYOUT_LINEAR, true) } else { STREAMI_S(LAYOUT_LINEAR, false) }
+  }
+#undef STREAMI_S
 }
 
 template <int FMT, int LAYOUT, bool PERIODIC, int MODE, bool BATCHED>

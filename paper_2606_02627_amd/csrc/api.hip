@@ -22,16 +22,24 @@ int launch_advect_f16(const AdvectArgs& a, int layout, bool periodic, int mode, 
                       hipStream_t st);
 int launch_advect_bf16(const AdvectArgs& a, int layout, bool periodic, int mode, bool batched, int grid,
                        hipStream_t st);
+int launch_surrogate_f32(const SurrogateArgs& s, int layout, bool periodic, bool pre, int grid, hipStream_t st);
+int launch_surrogate_f16(const SurrogateArgs& s, int layout, bool periodic, bool pre, int grid, hipStream_t st);
+int launch_surrogate_bf16(const SurrogateArgs& s, int layout, bool periodic, bool pre, int grid, hipStream_t st);
+int mlp_forward_rows(streami_mlp m, const float* xyz, int xstride, long long n, float* out, hipStream_t st);
 int launch_ingest(const void* src, void* pool, const BlockDev& B, int fmt, int layout, int nx, int ny, int nz,
                   int n_slices, hipStream_t st);
 int launch_seed(const float* xyz, const unsigned long long* ids, unsigned long long auto_id0, const int* max_steps,
-                int default_max, int stride, float t_birth, int blk, const BlockDev& B, long long first,
+                int default_max, int stride, float t_birth, const float* t_births, int blk, const BlockDev& B,
+                long long first,
                 long long n, float4* pos, int4* meta, int4* meta2, unsigned long long* pid, const VertexLog& log,
                 OutRec* outbox, unsigned long long* outbox_count, hipStream_t st);
 int launch_scatter_lines(const VertexLog& log, long long n_rec, long long n_particles, const int* row_of,
                          const long long* offsets, float* out, hipStream_t st);
 int launch_mark_rows(const long long* idx, long long count, int* row_of, hipStream_t st);
 int launch_fill_u32(unsigned* p, long long n, unsigned v, hipStream_t st);
+int launch_work_order(const float4* pos, const int4* meta, const int4* meta2, const BlockDev* blocks, long long n,
+                      int bits, unsigned n_buckets, unsigned* key, unsigned* hist, unsigned* cursor, int* order,
+                      unsigned* n_work, hipStream_t st);
 int launch_fill_u64(unsigned long long* p, long long n, unsigned long long v, hipStream_t st);
 int launch_gather_meta(const long long* idx, long long count, const int4* meta, const int4* meta2,
                        const unsigned long long* pid, long long* nverts, int* steps, int* codes,
@@ -44,6 +52,17 @@ using namespace streami;
 namespace {
 
 thread_local std::string g_err;
+
+}  // namespace
+
+namespace streami {
+int set_error(int code, const char* msg) {
+  g_err = msg;
+  return code;
+}
+}  // namespace streami
+
+namespace {
 
 int fail(int code, const char* fmt, ...) {
   char buf[512];
@@ -128,6 +147,11 @@ struct streami_field_s {
   long long log_cap = 0;
   long long vert_bound = 0;
   DevBuf d_ctr;        // CTR_N per-call counters, PER_N persistent counters, 6 code counts
+  DevBuf d_qctr;       // per-queue work counters
+  DevBuf d_key, d_order, d_hist, d_cursor, d_nwork;  // spatial work order
+  DevBuf d_dhat, d_dhat2, d_xh;                      // surrogate jumps
+  bool strides_mult16 = true;                        // every seed batch's record stride % 16 == 0
+  int max_m = 0;                                     // largest per-particle step limit seeded
   unsigned long long next_auto_id = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipGraphExec_t graph = nullptr;
@@ -288,6 +312,94 @@ void drop_graph(streami_field_s* f) {
   f->graph = nullptr;
 }
 
+
+int collect_stats(streami_field_s* f, streami_stats* stats) {
+  launch_fill_u64(f->code_counts(), 6, 0, f->stream);
+  launch_count_codes((const int4*)f->d_meta.p, f->n_particles, f->code_counts(), f->stream);
+  unsigned long long h[N_COUNTERS];
+  HIP_TRY(hipMemcpyAsync(h, f->ctr(), sizeof h, hipMemcpyDeviceToHost, f->stream));
+  HIP_TRY(hipStreamSynchronize(f->stream));
+  std::memset(stats, 0, sizeof *stats);
+  stats->steps = (int64_t)h[CTR_STEPS];
+  stats->vertices = (int64_t)h[CTR_VERTS];
+  stats->surrogate_accepted = (int64_t)h[CTR_ACCEPT];
+  stats->surrogate_fallback = (int64_t)h[CTR_FALLBACK];
+  stats->outbox = (int64_t)h[CTR_N + PER_OUTBOX];
+  for (int k = 0; k < 6; ++k) stats->terminated[k] = (int64_t)h[CTR_N + PER_N + k];
+  stats->active = stats->terminated[0];
+  float ms = 0;
+  HIP_TRY(hipEventElapsedTime(&ms, f->ev0, f->ev1));
+  stats->device_ms = ms;
+  if (h[CTR_OVERFLOW]) return fail(STREAMI_E_DEVICE, "vertex log overflow (internal sizing error)");
+  return STREAMI_OK;
+}
+
+// SURROGATE mode: repeated jumps of 16 steps; the network displacement is
+// accepted where its residual is within tolerance, else plain RK4 is used.
+int advect_surrogate(streami_field_s* f, const streami_advect_params* p, streami_stats* stats) {
+  const int J = 16;
+  if (!p->mlp) return fail(STREAMI_E_STATE, "surrogate mode needs a network (params.mlp)");
+  if (f->blocks.size() != 1 || f->unsteady)
+    return fail(STREAMI_E_UNSUPPORTED, "surrogate mode supports one steady block");
+  if (!f->strides_mult16) return fail(STREAMI_E_ARG, "surrogate mode needs record strides that are multiples of 16");
+  if (p->step_budget % J != 0) return fail(STREAMI_E_ARG, "surrogate step_budget must be a multiple of 16");
+  if (p->residual_kind != 0 && p->residual_kind != 1) return fail(STREAMI_E_ARG, "residual_kind must be 0 or 1");
+  if (!(p->residual_tol_cells >= 0)) return fail(STREAMI_E_ARG, "residual_tol_cells must be >= 0");
+  const long long n = f->n_particles;
+  int rc;
+  if ((rc = f->d_dhat.reserve(n * 12, 0, f->stream)) || (rc = f->d_dhat2.reserve(n * 12, 0, f->stream)) ||
+      (rc = f->d_xh.reserve(n * 12, 0, f->stream)))
+    return rc;
+  if ((rc = ensure_log(f, 0))) return rc;  // one record per particle per jump, exactly reserved
+  const HostBlock& hb = f->blocks[0];
+  const double cell = std::min(hb.desc.spacing[0], std::min(hb.desc.spacing[1], hb.desc.spacing[2]));
+  SurrogateArgs s;
+  std::memset(&s, 0, sizeof s);
+  AdvectArgs& a = s.a;
+  a.blocks = (const BlockDev*)f->d_blocks.p;
+  a.n_blocks = 1;
+  a.nodes = f->d_nodes.p;
+  a.pos = (float4*)f->d_pos.p;
+  a.meta = (int4*)f->d_meta.p;
+  a.meta2 = (const int4*)f->d_meta2.p;
+  a.ids = (const unsigned long long*)f->d_ids.p;
+  a.log = f->log();
+  a.outbox = (OutRec*)f->d_outbox.p;
+  a.outbox_count = f->outbox_count();
+  a.ctr = f->ctr();
+  a.n_particles = n;
+  a.h = p->h;
+  a.eps2 = p->stagnation_eps * p->stagnation_eps;
+  s.dhat = (const float*)f->d_dhat.p;
+  s.dhat2 = (const float*)f->d_dhat2.p;
+  s.xh = (float*)f->d_xh.p;
+  s.tol = (float)(p->residual_tol_cells * cell);
+  s.kind = p->residual_kind;
+  s.jump = J;
+  long long jumps = (f->max_m + J - 1) / J + 1;
+  if (p->step_budget > 0) jumps = std::min<long long>(jumps, p->step_budget / J);
+  const int grid = (int)std::min<long long>((n + 255) / 256, 8192);
+  auto launch = [&](bool pre) {
+    if (f->fmt == STREAMI_F32) return launch_surrogate_f32(s, f->layout, f->periodic, pre, grid, f->stream);
+    if (f->fmt == STREAMI_F16) return launch_surrogate_f16(s, f->layout, f->periodic, pre, grid, f->stream);
+    return launch_surrogate_bf16(s, f->layout, f->periodic, pre, grid, f->stream);
+  };
+  HIP_TRY(hipEventRecord(f->ev0, f->stream));
+  launch_fill_u64(a.ctr, CTR_N, 0, f->stream);
+  for (long long j = 0; j < jumps; ++j) {
+    if (s.kind == 0) {
+      launch(true);
+      if ((rc = mlp_forward_rows(p->mlp, s.xh, 3, n, (float*)f->d_dhat2.p, f->stream))) return rc;
+    }
+    if ((rc = mlp_forward_rows(p->mlp, (const float*)f->d_pos.p, 4, n, (float*)f->d_dhat.p, f->stream))) return rc;
+    launch(false);
+    HIP_TRY(hipGetLastError());
+  }
+  HIP_TRY(hipEventRecord(f->ev1, f->stream));
+  if (stats) return collect_stats(f, stats);
+  return STREAMI_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -380,7 +492,8 @@ int streami_field_destroy(streami_field f) {
   (void)hipStreamSynchronize(f->stream);
   drop_graph(f);
   for (DevBuf* b : {&f->d_blocks, &f->d_nodes, &f->d_pos, &f->d_meta, &f->d_meta2, &f->d_ids, &f->d_outbox,
-                    &f->d_logx, &f->d_logy, &f->d_logz, &f->d_logpj, &f->d_ctr})
+                    &f->d_logx, &f->d_logy, &f->d_logz, &f->d_logpj, &f->d_ctr, &f->d_qctr, &f->d_key,
+                    &f->d_order, &f->d_hist, &f->d_cursor, &f->d_nwork, &f->d_dhat, &f->d_dhat2, &f->d_xh})
     b->release();
   if (f->ev0) (void)hipEventDestroy(f->ev0);
   if (f->ev1) (void)hipEventDestroy(f->ev1);
@@ -414,9 +527,11 @@ int streami_seed(streami_field f, int32_t block, const float* xyz, const uint64_
   }
   // every particle may record at most max_steps/stride + 2 vertices
   long long bound = 0;
+  int batch_max = 0;
   for (long long i = 0; i < n; ++i) {
     const int m = max_steps ? ms[i] : opts->default_max_steps;
     bound += m / opts->record_stride + 2;
+    batch_max = std::max(batch_max, m);
   }
   int rc;
   drop_graph(f);
@@ -428,7 +543,8 @@ int streami_seed(streami_field f, int32_t block, const float* xyz, const uint64_
   }
   const long long first = f->n_particles;
   // stage host inputs on the device
-  DevBuf s_xyz, s_ids, s_ms;
+  DevBuf s_xyz, s_ids, s_ms, s_tb;
+  const float* d_tb = opts->t_births;
   const float* d_xyz = xyz;
   const unsigned long long* d_ids = reinterpret_cast<const unsigned long long*>(ids);
   const int* d_ms = max_steps;
@@ -446,15 +562,22 @@ int streami_seed(streami_field f, int32_t block, const float* xyz, const uint64_
       HIP_TRY(hipMemcpyAsync(s_ms.p, ms.data(), n * 4, hipMemcpyHostToDevice, f->stream));
       d_ms = (const int*)s_ms.p;
     }
+    if (opts->t_births) {
+      if ((rc = s_tb.reserve(n * 4, 0, f->stream))) return rc;
+      HIP_TRY(hipMemcpyAsync(s_tb.p, opts->t_births, n * 4, hipMemcpyHostToDevice, f->stream));
+      d_tb = (const float*)s_tb.p;
+    }
   }
   HostBlock& hb = f->blocks[block];
-  launch_seed(d_xyz, d_ids, f->next_auto_id, d_ms, opts->default_max_steps, opts->record_stride, opts->t_birth,
+  launch_seed(d_xyz, d_ids, f->next_auto_id, d_ms, opts->default_max_steps, opts->record_stride, opts->t_birth, d_tb,
               block, hb.dev, first, n, (float4*)f->d_pos.p, (int4*)f->d_meta.p, (int4*)f->d_meta2.p,
               (unsigned long long*)f->d_ids.p, f->log(), (OutRec*)f->d_outbox.p, f->outbox_count(), f->stream);
   HIP_TRY(hipGetLastError());
   if (!dev_in) HIP_TRY(hipStreamSynchronize(f->stream));  // staging buffers are freed on return
   if (!ids) f->next_auto_id += (unsigned long long)n;
   f->n_particles += n;
+  f->max_m = std::max(f->max_m, batch_max);
+  if (opts->record_stride % 16 != 0) f->strides_mult16 = false;
   hb.ranges.push_back({first, n});
   hb.n_particles += n;
   return STREAMI_OK;
@@ -466,12 +589,14 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
   if (!(p->h > 0) || !std::isfinite(p->h)) return fail(STREAMI_E_ARG, "h must be finite and > 0");
   if (p->step_budget < 0) return fail(STREAMI_E_ARG, "step_budget must be >= 0");
   if (!(p->stagnation_eps >= 0)) return fail(STREAMI_E_ARG, "stagnation_eps must be >= 0");
-  if (p->mode == STREAMI_MODE_SURROGATE) return fail(STREAMI_E_UNSUPPORTED, "surrogate mode needs a network");
-  if (p->mode != STREAMI_MODE_PLAIN) return fail(STREAMI_E_ARG, "unknown mode %d", p->mode);
+  if (p->mode != STREAMI_MODE_PLAIN && p->mode != STREAMI_MODE_SURROGATE)
+    return fail(STREAMI_E_ARG, "unknown mode %d", p->mode);
   if (p->waves_per_cu < 0 || p->waves_per_cu > 64) return fail(STREAMI_E_ARG, "waves_per_cu must be in [0,64]");
   if (p->refill_threshold < 0 || p->refill_threshold > 64)
     return fail(STREAMI_E_ARG, "refill_threshold must be in [0,64]");
+  if (p->work_order != 0 && p->work_order != 1) return fail(STREAMI_E_ARG, "work_order must be 0 or 1");
   if (f->n_particles == 0) return fail(STREAMI_E_STATE, "no particles seeded");
+  if (p->mode == STREAMI_MODE_SURROGATE) return advect_surrogate(f, p, stats);
   AdvectArgs a;
   a.blocks = (const BlockDev*)f->d_blocks.p;
   a.n_blocks = (int)f->blocks.size();
@@ -497,6 +622,25 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
     if (rc) return rc;
   }
   a.log = f->log();
+  // spatial work order (bucket sort by block and Morton brick) over per-XCD queues
+  const bool spatial = p->work_order == 0;
+  const int bits = f->blocks.size() == 1 ? 5 : 3;
+  const unsigned n_buckets = (unsigned)f->blocks.size() * (1u << (3 * bits)) + 1;
+  {
+    int rc;
+    if ((rc = f->d_qctr.reserve(sizeof(unsigned long long) * MAX_QUEUES * QCTR_STRIDE, 0, f->stream))) return rc;
+    if (spatial) {
+      if ((rc = f->d_key.reserve(f->n_particles * 4, 0, f->stream)) ||
+          (rc = f->d_order.reserve(f->n_particles * 4, 0, f->stream)) ||
+          (rc = f->d_hist.reserve(n_buckets * 4, 0, f->stream)) ||
+          (rc = f->d_cursor.reserve(n_buckets * 4, 0, f->stream)) || (rc = f->d_nwork.reserve(8, 0, f->stream)))
+        return rc;
+    }
+  }
+  a.order = spatial ? (const int*)f->d_order.p : nullptr;
+  a.n_work = spatial ? (const unsigned*)f->d_nwork.p : nullptr;
+  a.qctr = (unsigned long long*)f->d_qctr.p;
+  a.n_queues = spatial ? MAX_QUEUES : 1;
   const bool batched = f->blocks.size() > 1;
   const int mode = f->unsteady ? 2 : (p->no_cell_cache ? 1 : 0);
   auto launch = [&](hipStream_t st) {
@@ -506,7 +650,7 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
   };
   HIP_TRY(hipEventRecord(f->ev0, f->stream));
   if (p->use_graph) {
-    const int key[6] = {(int)grid, a.refill, a.budget, mode, (int)(p->h * 1e6f), 1};
+    const int key[6] = {(int)grid, a.refill, a.budget, mode, (int)(p->h * 1e6f), spatial ? 1 : 0};
     bool same = f->graph && std::memcmp(key, f->graph_key, sizeof key) == 0 &&
                 std::memcmp(&a, &f->graph_args, sizeof a) == 0;
     if (!same) {
@@ -516,6 +660,12 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
       hipGraph_t g;
       HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
       launch_fill_u64(a.ctr, CTR_N, 0, cs);
+      launch_fill_u64(a.qctr, MAX_QUEUES * QCTR_STRIDE, 0, cs);
+      if (spatial)
+        launch_work_order((const float4*)f->d_pos.p, (const int4*)f->d_meta.p, (const int4*)f->d_meta2.p,
+                          (const BlockDev*)f->d_blocks.p, f->n_particles, bits, n_buckets, (unsigned*)f->d_key.p,
+                          (unsigned*)f->d_hist.p, (unsigned*)f->d_cursor.p, (int*)f->d_order.p,
+                          (unsigned*)f->d_nwork.p, cs);
       launch(cs);
       HIP_TRY(hipStreamEndCapture(cs, &g));
       HIP_TRY(hipGraphInstantiate(&f->graph, g, nullptr, nullptr, 0));
@@ -527,29 +677,17 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
     HIP_TRY(hipGraphLaunch(f->graph, f->stream));
   } else {
     launch_fill_u64(a.ctr, CTR_N, 0, f->stream);
+    launch_fill_u64(a.qctr, MAX_QUEUES * QCTR_STRIDE, 0, f->stream);
+    if (spatial)
+      launch_work_order((const float4*)f->d_pos.p, (const int4*)f->d_meta.p, (const int4*)f->d_meta2.p,
+                        (const BlockDev*)f->d_blocks.p, f->n_particles, bits, n_buckets, (unsigned*)f->d_key.p,
+                        (unsigned*)f->d_hist.p, (unsigned*)f->d_cursor.p, (int*)f->d_order.p,
+                        (unsigned*)f->d_nwork.p, f->stream);
     launch(f->stream);
   }
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipEventRecord(f->ev1, f->stream));
-  if (stats) {
-    launch_fill_u64(f->code_counts(), 6, 0, f->stream);
-    launch_count_codes((const int4*)f->d_meta.p, f->n_particles, f->code_counts(), f->stream);
-    unsigned long long h[N_COUNTERS];
-    HIP_TRY(hipMemcpyAsync(h, f->ctr(), sizeof h, hipMemcpyDeviceToHost, f->stream));
-    HIP_TRY(hipStreamSynchronize(f->stream));
-    std::memset(stats, 0, sizeof *stats);
-    stats->steps = (int64_t)h[CTR_STEPS];
-    stats->vertices = (int64_t)h[CTR_VERTS];
-    stats->surrogate_accepted = (int64_t)h[CTR_ACCEPT];
-    stats->surrogate_fallback = (int64_t)h[CTR_FALLBACK];
-    stats->outbox = (int64_t)h[CTR_N + PER_OUTBOX];
-    for (int k = 0; k < 6; ++k) stats->terminated[k] = (int64_t)h[CTR_N + PER_N + k];
-    if (h[CTR_OVERFLOW]) return fail(STREAMI_E_DEVICE, "vertex log overflow (internal sizing error)");
-    stats->active = stats->terminated[0];
-    float ms = 0;
-    HIP_TRY(hipEventElapsedTime(&ms, f->ev0, f->ev1));
-    stats->device_ms = ms;
-  }
+  if (stats) return collect_stats(f, stats);
   return STREAMI_OK;
 }
 
@@ -558,6 +696,8 @@ int streami_clear(streami_field f) {
   drop_graph(f);
   f->n_particles = 0;
   f->vert_bound = 0;
+  f->max_m = 0;
+  f->strides_mult16 = true;
   f->next_auto_id = 0;
   for (auto& hb : f->blocks) {
     hb.ranges.clear();

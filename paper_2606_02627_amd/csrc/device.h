@@ -85,11 +85,35 @@ struct AdvectArgs {
   unsigned long long* outbox_count;  // persistent across calls
   unsigned long long* ctr;           // per-call counters
   long long n_particles;
+  // work order: particles are claimed in the order of `order` (NULL: index
+  // order), the first *n_work entries only; the order is split into
+  // n_queues contiguous ranges, one per XCD (workgroups are dispatched to the
+  // XCDs round-robin), and a wave that empties its range steals from the next
+  const int* order;
+  const unsigned* n_work;
+  unsigned long long* qctr;  // n_queues counters, QCTR_STRIDE apart
+  int n_queues;
   float h;
   float eps2;               // stagnation_eps^2
   int budget;               // 0 = unlimited
   int refill;               // free lanes that trigger a refill
 };
+
+// One surrogate jump (16 plain steps) for every active particle of a single
+// steady block.  dhat = network displacement at x; for the commutation
+// residual (kind 0) xh = one plain step from x and dhat2 = network at xh.
+struct SurrogateArgs {
+  AdvectArgs a;
+  const float* dhat;    // [n x 3]
+  const float* dhat2;   // [n x 3] (kind 0)
+  float* xh;            // [n x 3] (kind 0; written by the pre-pass)
+  float tol;            // residual tolerance in world units
+  int kind;             // 0 commutation, 1 one big RK4 step
+  int jump;             // steps per jump (16)
+};
+
+constexpr int QCTR_STRIDE = 16;  // one 128-byte line per queue counter
+constexpr int MAX_QUEUES = 8;
 
 // Per-axis offsets of node i within a slice of a block.
 template <int LAYOUT>

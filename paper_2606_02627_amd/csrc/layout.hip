@@ -55,7 +55,7 @@ int launch_ingest(const void* src, void* pool, const BlockDev& B, int fmt, int l
 // seed outside the owned bounds of a non-periodic block ends at once (EXIT,
 // 0 steps) and goes to the outbox.
 __global__ void k_seed(const float* xyz, const unsigned long long* ids, unsigned long long auto_id0,
-                       const int* max_steps, int default_max, int stride, float t_birth, int blk,
+                       const int* max_steps, int default_max, int stride, float t_birth, const float* t_births, int blk,
                        BlockDev B, long long first, long long n, float4* pos, int4* meta, int4* meta2,
                        unsigned long long* pid, VertexLog log, OutRec* outbox, unsigned long long* outbox_count) {
   const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -71,7 +71,7 @@ __global__ void k_seed(const float* xyz, const unsigned long long* ids, unsigned
     if (!B.periodic)
       out = !(x.x >= B.lo[0] && x.x < B.hi[0] && x.y >= B.lo[1] && x.y < B.hi[1] && x.z >= B.lo[2] &&
               x.z < B.hi[2]);
-    pos[q] = make_float4(x.x, x.y, x.z, t_birth);
+    pos[q] = make_float4(x.x, x.y, x.z, t_births ? t_births[i] : t_birth);
     meta[q] = make_int4(0, m, out ? EXIT : ACTIVE, 1);
     meta2[q] = make_int4(stride, blk, m / stride + 2, 0);
     pid[q] = id;
@@ -122,14 +122,15 @@ __global__ void k_seed(const float* xyz, const unsigned long long* ids, unsigned
 }
 
 int launch_seed(const float* xyz, const unsigned long long* ids, unsigned long long auto_id0,
-                const int* max_steps, int default_max, int stride, float t_birth, int blk, const BlockDev& B,
+                const int* max_steps, int default_max, int stride, float t_birth, const float* t_births, int blk,
+                const BlockDev& B,
                 long long first, long long n, float4* pos, int4* meta, int4* meta2,
                 unsigned long long* pid, const VertexLog& log, OutRec* outbox,
                 unsigned long long* outbox_count, hipStream_t st) {
   if (n <= 0) return 0;
   const long long grid = (n + 255) / 256;
   hipLaunchKernelGGL(k_seed, dim3((unsigned)grid), dim3(256), 0, st, xyz, ids, auto_id0, max_steps, default_max,
-                     stride, t_birth, blk, B, first, n, pos, meta, meta2, pid, log, outbox, outbox_count);
+                     stride, t_birth, t_births, blk, B, first, n, pos, meta, meta2, pid, log, outbox, outbox_count);
   return 0;
 }
 
@@ -248,6 +249,96 @@ int launch_count_codes(const int4* meta, long long n, unsigned long long* counts
   if (grid > 2048) grid = 2048;
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL(k_count_codes, dim3(grid), dim3(256), 0, st, meta, n, counts);
+  return 0;
+}
+
+}  // namespace streami
+
+namespace streami {
+
+// ---------------------------------------------------------------- work order
+// Active particles are bucketed by (block, Morton index of a coarse brick of
+// their position) so that lanes of a wave and waves of an XCD work on nearby
+// cells; terminated particles go to the last bucket and are not processed.
+// The order only decides which lane advances which particle, never what is
+// computed, so results do not depend on it.
+
+__device__ __forceinline__ unsigned spread3(unsigned v) {  // 5 bits -> every third bit
+  v &= 0x1f;
+  v = (v | (v << 8)) & 0x0f00f;
+  v = (v | (v << 4)) & 0xc30c3;
+  v = (v | (v << 2)) & 0x249249;
+  return v;
+}
+
+__global__ void k_order_keys(const float4* pos, const int4* meta, const int4* meta2, const BlockDev* blocks,
+                             long long n, int bits, unsigned n_buckets, unsigned* key, unsigned* hist) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    unsigned k = n_buckets - 1;
+    if (meta[i].z == ACTIVE) {
+      const int blk = meta2[i].y;
+      const BlockDev& B = blocks[blk];
+      const float4 p = pos[i];
+      const float side = (float)(1 << bits);
+      const float xs[3] = {p.x, p.y, p.z};
+      unsigned c[3];
+      for (int a = 0; a < 3; ++a) {
+        const float s = fmaf(xs[a], B.scale[a], B.offs[a]) * (side / B.fn[a]);
+        float w = floorf(s);
+        if (B.periodic) w -= side * floorf(w / side);
+        c[a] = (unsigned)__builtin_amdgcn_fmed3f(w, 0.0f, side - 1.0f);
+      }
+      k = (unsigned)blk * (1u << (3 * bits)) + (spread3(c[0]) | (spread3(c[1]) << 1) | (spread3(c[2]) << 2));
+    }
+    key[i] = k;
+    atomicAdd(&hist[k], 1u);
+  }
+}
+
+// Exclusive scan of hist[0..nb) into cursor[], one workgroup of 1024 threads;
+// n_work = number of particles outside the last (terminated) bucket.
+__global__ void __launch_bounds__(1024) k_order_scan(const unsigned* hist, unsigned nb, unsigned* cursor,
+                                                     unsigned* n_work) {
+  __shared__ unsigned part[1024];
+  const unsigned t = threadIdx.x;
+  const unsigned per = (nb + 1023) / 1024;
+  const unsigned b0 = t * per, b1 = min(nb, b0 + per);
+  unsigned s = 0;
+  for (unsigned b = b0; b < b1; ++b) s += hist[b];
+  part[t] = s;
+  __syncthreads();
+  for (unsigned o = 1; o < 1024; o <<= 1) {  // Hillis-Steele inclusive scan
+    const unsigned v = t >= o ? part[t - o] : 0u;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  unsigned run = part[t] - s;  // exclusive prefix of this thread's chunk
+  for (unsigned b = b0; b < b1; ++b) {
+    cursor[b] = run;
+    run += hist[b];
+  }
+  if (t == 1023) *n_work = part[1023] - hist[nb - 1];
+}
+
+__global__ void k_order_scatter(const unsigned* key, long long n, unsigned* cursor, int* order) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const unsigned slot = atomicAdd(&cursor[key[i]], 1u);
+    order[slot] = (int)i;
+  }
+}
+
+int launch_work_order(const float4* pos, const int4* meta, const int4* meta2, const BlockDev* blocks, long long n,
+                      int bits, unsigned n_buckets, unsigned* key, unsigned* hist, unsigned* cursor, int* order,
+                      unsigned* n_work, hipStream_t st) {
+  if (n <= 0) return 0;
+  long long grid = (n + 255) / 256;
+  if (grid > 16384) grid = 16384;
+  launch_fill_u32(hist, n_buckets, 0u, st);
+  hipLaunchKernelGGL(k_order_keys, dim3((unsigned)grid), dim3(256), 0, st, pos, meta, meta2, blocks, n, bits,
+                     n_buckets, key, hist);
+  hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(1024), 0, st, hist, n_buckets, cursor, n_work);
+  hipLaunchKernelGGL(k_order_scatter, dim3((unsigned)grid), dim3(256), 0, st, key, n, cursor, order);
   return 0;
 }
 

@@ -1,0 +1,527 @@
+// Learned flow-map surrogate: a 3 -> 256 -> 256 -> 256 -> 256 -> 3 MLP with
+// SiLU activations, BF16 weights and activations as MFMA operands and FP32
+// accumulation (gfx950 v_mfma_f32_32x32x16_bf16), trained on the GPU with
+// its own forward/backward GEMMs and an Adam kernel (FP32 master weights).
+//
+// Network (FP32 master parameters, l = 0..4):
+//   xhat = 2 (x mod L)/L - 1;  h0 = xhat;  z_l = W_l h_l + b_l;
+//   h_{l+1} = SiLU(z_l) (l < 4);  out = sigma * z_4.
+// Loss: mean of ((out - target)/sigma)^2 over samples and components.
+//
+// Layouts (row-major, padded with zeros so every GEMM dimension is a multiple
+// of 16 along K and 32 along M/N): layer l has in_pad = 16 (l = 0) or 256 and
+// out_pad = 256 or 32 (l = 4).  Activations are kept in BF16 both row-major
+// [B x in_pad] (forward A operand) and transposed [in_pad x B] (weight-gradient
+// B operand), so that every MFMA fragment is a contiguous 16-byte load.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/streami.h"
+
+namespace streami {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+constexpr int NL = 5;
+constexpr int WID[NL + 1] = {3, 256, 256, 256, 256, 3};
+constexpr int IN_PAD[NL] = {16, 256, 256, 256, 256};
+constexpr int OUT_PAD[NL] = {256, 256, 256, 256, 32};
+
+__host__ __device__ inline int n_params_total() {
+  int s = 0;
+  for (int l = 0; l < NL; ++l) s += WID[l] * WID[l + 1] + WID[l + 1];
+  return s;
+}
+
+__device__ __forceinline__ unsigned short f2bf(float f) {  // round to nearest even
+  unsigned u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
+
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float dsilu(float z) {
+  const float s = 1.0f / (1.0f + __expf(-z));
+  return s * (1.0f + z * (1.0f - s));
+}
+
+// C[M x N] (FP32, ldc) = A[M x K] . B[K x N], BF16 operands with K contiguous:
+//   A(i, k) = A[i*lda + k],  B(k, j) = B[j*ldb + k].
+// One wave per 32x32 tile; rows/cols beyond M/N read as zero and are not
+// stored; K is a multiple of 16.  MFMA operand layout (32x32x16): lane l holds
+// row/col (l % 32) and k = 8*(l/32) .. +7; the accumulator register r of lane l
+// holds row 8*(r/4) + 4*(l/32) + r%4 and column l % 32.
+__global__ void __launch_bounds__(256) k_gemm_bf16(const unsigned short* __restrict__ A, int lda,
+                                                   const unsigned short* __restrict__ B, int ldb, float* C, int ldc,
+                                                   int M, int N, int K, int accumulate) {
+  const int lane = __lane_id();
+  const int wave = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  const int tiles_n = (N + 31) / 32;
+  const int tm = wave / tiles_n, tn = wave % tiles_n;
+  if (tm * 32 >= M) return;
+  const int i = tm * 32 + (lane & 31), j = tn * 32 + (lane & 31);
+  const int kh = 8 * (lane >> 5);
+  const bool ai = i < M, bj = j < N;
+  f32x16 acc;
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+  const bf16x8 zero = {};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    const bf16x8 a = ai ? *reinterpret_cast<const bf16x8*>(A + (size_t)i * lda + k0 + kh) : zero;
+    const bf16x8 b = bj ? *reinterpret_cast<const bf16x8*>(B + (size_t)j * ldb + k0 + kh) : zero;
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+  }
+  const int col = tn * 32 + (lane & 31);
+  if (col >= N) return;
+  for (int r = 0; r < 16; ++r) {
+    const int row = tm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    if (row < M) {
+      float* c = C + (size_t)row * ldc + col;
+      *c = accumulate ? *c + acc[r] : acc[r];
+    }
+  }
+}
+
+static void gemm(const unsigned short* A, int lda, const unsigned short* B, int ldb, float* C, int ldc, int M, int N,
+                 int K, bool accumulate, hipStream_t st) {
+  const long long tiles = (long long)((M + 31) / 32) * ((N + 31) / 32);
+  const int grid = (int)((tiles + 3) / 4);
+  hipLaunchKernelGGL(k_gemm_bf16, dim3(grid), dim3(256), 0, st, A, lda, B, ldb, C, ldc, M, N, K, accumulate ? 1 : 0);
+}
+
+// xhat = 2 (x mod L)/L - 1 in columns 0..2 of a [B x 16] BF16 row (zeros
+// elsewhere; rows >= n are zero) and its transpose [16 x Bp].
+__global__ void k_mlp_input(const float* xyz, int xstride, long long n, long long Bp, float period,
+                            unsigned short* H, unsigned short* HT) {
+  for (long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x; r < Bp; r += (long long)gridDim.x * blockDim.x) {
+    for (int c = 0; c < 16; ++c) {
+      float v = 0.0f;
+      if (r < n && c < 3) {
+        const float x = xyz[r * xstride + c];
+        const float w = x - period * floorf(x / period);
+        v = 2.0f * (w / period) - 1.0f;
+      }
+      const unsigned short b = f2bf(v);
+      H[r * 16 + c] = b;
+      HT[(long long)c * Bp + r] = b;
+    }
+  }
+}
+
+// z += b (FP32, in place); h = BF16(SiLU(z)) row-major and transposed.
+__global__ void k_bias_silu(float* Z, const float* bias, long long Bp, int width, unsigned short* H,
+                            unsigned short* HT) {
+  const long long total = Bp * width;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+    const long long r = e / width;
+    const int c = (int)(e - r * width);
+    const float z = Z[e] + bias[c];
+    Z[e] = z;
+    const unsigned short b = f2bf(silu(z));
+    H[e] = b;
+    HT[(long long)c * Bp + r] = b;
+  }
+}
+
+// Output layer: out = sigma * (z + b) for the first n rows; loss terms and
+// dL/dz (BF16, row-major [Bp x 32] and transposed [32 x Bp]).
+__global__ void k_out_loss(const float* Z, const float* bias, long long n, long long Bp, float sx, float sy, float sz,
+                           const float* target, float* out, unsigned short* dZ, unsigned short* dZT, float* loss_acc,
+                           float inv_count) {
+  const float sig[3] = {sx, sy, sz};
+  float part = 0.0f;
+  for (long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x; r < Bp; r += (long long)gridDim.x * blockDim.x) {
+    for (int c = 0; c < 32; ++c) {
+      float g = 0.0f;
+      if (r < n && c < 3) {
+        const float o = sig[c] * (Z[r * 32 + c] + bias[c]);
+        if (out) out[r * 3 + c] = o;
+        if (target) {
+          const float d = (o - target[r * 3 + c]) / sig[c];
+          part += d * d;
+          g = 2.0f * d * inv_count;  // dL/dz = dL/dout * sigma = 2 d / count
+        }
+      }
+      if (dZ) {
+        const unsigned short b = f2bf(g);
+        dZ[r * 32 + c] = b;
+        dZT[(long long)c * Bp + r] = b;
+      }
+    }
+  }
+  if (loss_acc) {
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+    if (__lane_id() == 0) atomicAdd(loss_acc, part);
+  }
+}
+
+// dZ = dH * SiLU'(Z) -> BF16 row-major and transposed.
+__global__ void k_silu_grad(const float* dH, const float* Z, long long Bp, int width, unsigned short* dZ,
+                            unsigned short* dZT) {
+  const long long total = Bp * width;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+    const long long r = e / width;
+    const int c = (int)(e - r * width);
+    const unsigned short b = f2bf(dH[e] * dsilu(Z[e]));
+    dZ[e] = b;
+    dZT[(long long)c * Bp + r] = b;
+  }
+}
+
+// db[c] = sum over rows of dZ[r][c] (dZ^T rows are contiguous).
+__global__ void k_rowsum_bf16(const unsigned short* dZT, long long Bp, int width, float* db) {
+  const int c = blockIdx.x;
+  if (c >= width) return;
+  float s = 0.0f;
+  for (long long r = threadIdx.x; r < Bp; r += blockDim.x) s += bf2f(dZT[(long long)c * Bp + r]);
+  __shared__ float red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) db[c] = red[0];
+}
+
+// Adam on FP32 master parameters; gradients of W come padded [out_pad x in_pad].
+__global__ void k_adam(float* p, float* m, float* v, const float* g, int rows, int cols, int g_ld, float lr, float b1,
+                       float b2, float eps, float c1, float c2) {
+  const long long total = (long long)rows * cols;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+    const long long r = e / cols;
+    const int c = (int)(e - r * cols);
+    const float gr = g[r * g_ld + c];
+    const float mm = b1 * m[e] + (1.0f - b1) * gr;
+    const float vv = b2 * v[e] + (1.0f - b2) * gr * gr;
+    m[e] = mm;
+    v[e] = vv;
+    p[e] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+  }
+}
+
+// BF16 copies of W_l: [out_pad x in_pad] and transposed [in_pad x out_pad].
+__global__ void k_refresh_w(const float* W, int out, int in, int out_pad, int in_pad, unsigned short* Wb,
+                            unsigned short* WTb) {
+  const long long total = (long long)out_pad * in_pad;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+    const int r = (int)(e / in_pad), c = (int)(e - (long long)r * in_pad);
+    const unsigned short b = (r < out && c < in) ? f2bf(W[(long long)r * in + c]) : (unsigned short)0;
+    Wb[e] = b;
+    WTb[(long long)c * out_pad + r] = b;
+  }
+}
+
+static int grid_for(long long n) {
+  long long g = (n + 255) / 256;
+  if (g > 16384) g = 16384;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+}  // namespace streami
+
+using namespace streami;
+
+namespace streami {
+int set_error(int code, const char* msg);  // api.hip: the thread's last-error text
+}
+namespace {
+int mfail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  return streami::set_error(code, buf);
+}
+#define MHIP(expr)                                                                                      \
+  do {                                                                                                  \
+    hipError_t e_ = (expr);                                                                             \
+    if (e_ != hipSuccess) return mfail(STREAMI_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+}  // namespace
+
+struct streami_mlp_s {
+  hipStream_t stream = nullptr;
+  float sigma[3] = {1, 1, 1};
+  float period = 1;
+  // FP32 master parameters and Adam moments, per layer: W [out x in], b [out]
+  float* W[NL] = {};
+  float* b[NL] = {};
+  float* mW[NL] = {};
+  float* vW[NL] = {};
+  float* mb[NL] = {};
+  float* vb[NL] = {};
+  unsigned short* Wb[NL] = {};   // BF16 [out_pad x in_pad]
+  unsigned short* WTb[NL] = {};  // BF16 [in_pad x out_pad]
+  float* gW[NL] = {};            // FP32 [out_pad x in_pad]
+  float* gb[NL] = {};            // FP32 [out_pad]
+  long long t = 0;               // Adam step count
+  // batch workspace (grown on demand)
+  long long cap = 0;
+  unsigned short* H[NL] = {};   // BF16 layer inputs [cap x in_pad]
+  unsigned short* HT[NL] = {};  // transposed [in_pad x cap]
+  float* Z[NL] = {};            // FP32 pre-activations [cap x out_pad]
+  unsigned short* dZ = nullptr;  // BF16 [cap x 256]
+  unsigned short* dZT = nullptr;
+  float* dH = nullptr;           // FP32 [cap x 256]
+  float* loss = nullptr;
+  std::vector<void*> owned;
+};
+
+namespace {
+
+int dalloc(streami_mlp_s* m, void** p, size_t bytes) {
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return mfail(STREAMI_E_NOMEM, "device allocation of %zu bytes failed", bytes);
+  }
+  m->owned.push_back(*p);
+  return STREAMI_OK;
+}
+
+void free_batch(streami_mlp_s* m) {
+  auto drop = [&](void* p) {
+    if (!p) return;
+    for (auto& q : m->owned)
+      if (q == p) q = nullptr;
+    (void)hipFree(p);
+  };
+  for (int l = 0; l < NL; ++l) {
+    drop(m->H[l]);
+    drop(m->HT[l]);
+    drop(m->Z[l]);
+    m->H[l] = m->HT[l] = nullptr;
+    m->Z[l] = nullptr;
+  }
+  drop(m->dZ);
+  drop(m->dZT);
+  drop(m->dH);
+  m->dZ = m->dZT = nullptr;
+  m->dH = nullptr;
+  m->cap = 0;
+}
+
+int ensure_batch(streami_mlp_s* m, long long Bp) {
+  if (Bp <= m->cap) return STREAMI_OK;
+  // the workspace may be in use by kernels on any stream (a field's advection
+  // uses this network on its own stream): wait for the device before freeing
+  MHIP(hipDeviceSynchronize());
+  free_batch(m);
+  int rc;
+  for (int l = 0; l < NL; ++l) {
+    if ((rc = dalloc(m, (void**)&m->H[l], (size_t)Bp * IN_PAD[l] * 2)) ||
+        (rc = dalloc(m, (void**)&m->HT[l], (size_t)Bp * IN_PAD[l] * 2)) ||
+        (rc = dalloc(m, (void**)&m->Z[l], (size_t)Bp * OUT_PAD[l] * 4)))
+      return rc;
+  }
+  if ((rc = dalloc(m, (void**)&m->dZ, (size_t)Bp * 256 * 2)) || (rc = dalloc(m, (void**)&m->dZT, (size_t)Bp * 256 * 2)) ||
+      (rc = dalloc(m, (void**)&m->dH, (size_t)Bp * 256 * 4)))
+    return rc;
+  m->cap = Bp;
+  return STREAMI_OK;
+}
+
+void refresh_bf16(streami_mlp_s* m) {
+  for (int l = 0; l < NL; ++l)
+    hipLaunchKernelGGL(k_refresh_w, dim3(grid_for((long long)OUT_PAD[l] * IN_PAD[l])), dim3(256), 0, m->stream, m->W[l],
+                       WID[l + 1], WID[l], OUT_PAD[l], IN_PAD[l], m->Wb[l], m->WTb[l]);
+}
+
+// Forward over Bp rows (n real); leaves Z/H for backprop; writes out (n x 3) if given.
+void forward(streami_mlp_s* m, const float* xyz, int xstride, long long n, long long Bp, float* out,
+             const float* target, bool want_grad, hipStream_t st) {
+  hipLaunchKernelGGL(k_mlp_input, dim3(grid_for(Bp)), dim3(256), 0, st, xyz, xstride, n, Bp, m->period, m->H[0],
+                     m->HT[0]);
+  for (int l = 0; l < NL; ++l) {
+    gemm(m->H[l], IN_PAD[l], m->Wb[l], IN_PAD[l], m->Z[l], OUT_PAD[l], (int)Bp, OUT_PAD[l], IN_PAD[l], false, st);
+    if (l < NL - 1)
+      hipLaunchKernelGGL(k_bias_silu, dim3(grid_for(Bp * OUT_PAD[l])), dim3(256), 0, st, m->Z[l], m->b[l], Bp,
+                         OUT_PAD[l], m->H[l + 1], m->HT[l + 1]);
+  }
+  const float inv = n > 0 ? 1.0f / (float)(n * 3) : 0.0f;
+  hipLaunchKernelGGL(k_out_loss, dim3(grid_for(Bp)), dim3(256), 0, st, m->Z[NL - 1], m->b[NL - 1], n, Bp, m->sigma[0],
+                     m->sigma[1], m->sigma[2], target, out, want_grad ? m->dZ : nullptr, want_grad ? m->dZT : nullptr,
+                     target ? m->loss : nullptr, inv);
+}
+
+// Backward from dZ of the output layer (already in m->dZ/dZT, width 32).
+void backward(streami_mlp_s* m, long long Bp) {
+  hipStream_t st = m->stream;
+  for (int l = NL - 1; l >= 0; --l) {
+    const int op = OUT_PAD[l], ip = IN_PAD[l];
+    // dW_l [op x ip] = dZ^T [op x Bp] . H_l [Bp x ip]  (K = batch, contiguous in dZ^T and H^T)
+    gemm(m->dZT, (int)Bp, m->HT[l], (int)Bp, m->gW[l], ip, op, ip, (int)Bp, false, st);
+    hipLaunchKernelGGL(k_rowsum_bf16, dim3(op), dim3(256), 0, st, m->dZT, Bp, op, m->gb[l]);
+    if (l > 0) {
+      // dH_l [Bp x ip] = dZ [Bp x op] . W_l [op x ip]   (B(k=out, j=in) = W^T[in][out])
+      gemm(m->dZ, op, m->WTb[l], op, m->dH, ip, (int)Bp, ip, op, false, st);
+      hipLaunchKernelGGL(k_silu_grad, dim3(grid_for(Bp * ip)), dim3(256), 0, st, m->dH, m->Z[l - 1], Bp, ip, m->dZ,
+                         m->dZT);
+    }
+  }
+}
+
+}  // namespace
+
+namespace streami {
+// Network output for n rows of positions spaced xstride floats apart (3 for
+// packed xyz, 4 for the particle float4 array), in chunks of 2^18 rows.
+int mlp_forward_rows(streami_mlp m, const float* xyz, int xstride, long long n, float* out, hipStream_t st) {
+  const long long chunk = 1LL << 18;
+  if (st != m->stream) MHIP(hipStreamSynchronize(m->stream));
+  for (long long s = 0; s < n; s += chunk) {
+    const long long k = std::min<long long>(chunk, n - s);
+    const long long Bp = (k + 31) / 32 * 32;
+    int rc = ensure_batch(m, Bp);
+    if (rc) return rc;
+    forward(m, xyz + (size_t)xstride * s, xstride, k, Bp, out + 3 * s, nullptr, false, st);
+  }
+  MHIP(hipGetLastError());
+  return STREAMI_OK;
+}
+}  // namespace streami
+
+extern "C" {
+
+int streami_mlp_create(const float* params, const float* sigma, float period, void* hip_stream, streami_mlp* out) {
+  if (!out || !params || !sigma) return mfail(STREAMI_E_ARG, "NULL argument");
+  if (!(period > 0)) return mfail(STREAMI_E_ARG, "period must be > 0");
+  for (int c = 0; c < 3; ++c)
+    if (!(sigma[c] > 0)) return mfail(STREAMI_E_ARG, "sigma must be > 0");
+  streami_mlp_s* m = new (std::nothrow) streami_mlp_s();
+  if (!m) return mfail(STREAMI_E_NOMEM, "host allocation failed");
+  m->stream = (hipStream_t)hip_stream;
+  std::memcpy(m->sigma, sigma, sizeof m->sigma);
+  m->period = period;
+  int rc = STREAMI_OK;
+  for (int l = 0; l < NL && !rc; ++l) {
+    const size_t nw = (size_t)WID[l + 1] * WID[l], nb = WID[l + 1];
+    const size_t npad = (size_t)OUT_PAD[l] * IN_PAD[l];
+    if ((rc = dalloc(m, (void**)&m->W[l], nw * 4)) || (rc = dalloc(m, (void**)&m->b[l], nb * 4)) ||
+        (rc = dalloc(m, (void**)&m->mW[l], nw * 4)) || (rc = dalloc(m, (void**)&m->vW[l], nw * 4)) ||
+        (rc = dalloc(m, (void**)&m->mb[l], nb * 4)) || (rc = dalloc(m, (void**)&m->vb[l], nb * 4)) ||
+        (rc = dalloc(m, (void**)&m->Wb[l], npad * 2)) || (rc = dalloc(m, (void**)&m->WTb[l], npad * 2)) ||
+        (rc = dalloc(m, (void**)&m->gW[l], npad * 4)) || (rc = dalloc(m, (void**)&m->gb[l], (size_t)OUT_PAD[l] * 4)))
+      break;
+    (void)hipMemsetAsync(m->mW[l], 0, nw * 4, m->stream);
+    (void)hipMemsetAsync(m->vW[l], 0, nw * 4, m->stream);
+    (void)hipMemsetAsync(m->mb[l], 0, nb * 4, m->stream);
+    (void)hipMemsetAsync(m->vb[l], 0, nb * 4, m->stream);
+  }
+  if (!rc) rc = dalloc(m, (void**)&m->loss, 4);
+  if (rc) {
+    streami_mlp_destroy(m);
+    return rc;
+  }
+  rc = streami_mlp_set_params(m, params);
+  if (rc) {
+    streami_mlp_destroy(m);
+    return rc;
+  }
+  *out = m;
+  return STREAMI_OK;
+}
+
+int streami_mlp_destroy(streami_mlp m) {
+  if (!m) return STREAMI_OK;
+  (void)hipDeviceSynchronize();  // kernels on other streams may still read the weights
+  for (void* p : m->owned)
+    if (p) (void)hipFree(p);
+  delete m;
+  return STREAMI_OK;
+}
+
+int streami_mlp_set_params(streami_mlp m, const float* params) {
+  if (!m || !params) return mfail(STREAMI_E_ARG, "NULL argument");
+  size_t off = 0;
+  for (int l = 0; l < NL; ++l) {
+    const size_t nw = (size_t)WID[l + 1] * WID[l], nb = WID[l + 1];
+    MHIP(hipMemcpyAsync(m->W[l], params + off, nw * 4, hipMemcpyHostToDevice, m->stream));
+    off += nw;
+    MHIP(hipMemcpyAsync(m->b[l], params + off, nb * 4, hipMemcpyHostToDevice, m->stream));
+    off += nb;
+  }
+  refresh_bf16(m);
+  MHIP(hipStreamSynchronize(m->stream));
+  return STREAMI_OK;
+}
+
+int streami_mlp_get_params(streami_mlp m, float* params) {
+  if (!m || !params) return mfail(STREAMI_E_ARG, "NULL argument");
+  size_t off = 0;
+  for (int l = 0; l < NL; ++l) {
+    const size_t nw = (size_t)WID[l + 1] * WID[l], nb = WID[l + 1];
+    MHIP(hipMemcpyAsync(params + off, m->W[l], nw * 4, hipMemcpyDeviceToHost, m->stream));
+    off += nw;
+    MHIP(hipMemcpyAsync(params + off, m->b[l], nb * 4, hipMemcpyDeviceToHost, m->stream));
+    off += nb;
+  }
+  MHIP(hipStreamSynchronize(m->stream));
+  return STREAMI_OK;
+}
+
+int streami_mlp_forward(streami_mlp m, const float* xyz, int64_t n, float* out) {
+  if (!m || (!xyz && n > 0) || (!out && n > 0)) return mfail(STREAMI_E_ARG, "NULL argument");
+  if (n < 0) return mfail(STREAMI_E_ARG, "n must be >= 0");
+  return streami::mlp_forward_rows(m, xyz, 3, n, out, m->stream);
+}
+
+int streami_mlp_train_step(streami_mlp m, const float* xyz, const float* target, int64_t batch, float lr,
+                           float* loss_out, float* grads_out) {
+  if (!m || !xyz || !target) return mfail(STREAMI_E_ARG, "NULL argument");
+  if (batch < 1 || batch > (1LL << 22)) return mfail(STREAMI_E_ARG, "batch must be in [1, 2^22]");
+  if (!(lr >= 0)) return mfail(STREAMI_E_ARG, "lr must be >= 0");
+  const long long Bp = (batch + 31) / 32 * 32;
+  int rc = ensure_batch(m, Bp);
+  if (rc) return rc;
+  MHIP(hipMemsetAsync(m->loss, 0, 4, m->stream));
+  forward(m, xyz, 3, batch, Bp, nullptr, target, true, m->stream);
+  backward(m, Bp);
+  MHIP(hipGetLastError());
+  if (grads_out) {  // gradients of this step, in the parameter order of streami_mlp_set_params
+    size_t off = 0;
+    for (int l = 0; l < NL; ++l) {
+      MHIP(hipMemcpy2DAsync(grads_out + off, (size_t)WID[l] * 4, m->gW[l], (size_t)IN_PAD[l] * 4, (size_t)WID[l] * 4,
+                            WID[l + 1], hipMemcpyDeviceToHost, m->stream));
+      off += (size_t)WID[l + 1] * WID[l];
+      MHIP(hipMemcpyAsync(grads_out + off, m->gb[l], (size_t)WID[l + 1] * 4, hipMemcpyDeviceToHost, m->stream));
+      off += WID[l + 1];
+    }
+  }
+  if (lr > 0) {
+    ++m->t;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float c1 = 1.0f - powf(b1, (float)m->t), c2 = 1.0f - powf(b2, (float)m->t);
+    for (int l = 0; l < NL; ++l) {
+      hipLaunchKernelGGL(k_adam, dim3(grid_for((long long)WID[l + 1] * WID[l])), dim3(256), 0, m->stream, m->W[l],
+                         m->mW[l], m->vW[l], m->gW[l], WID[l + 1], WID[l], IN_PAD[l], lr, b1, b2, eps, c1, c2);
+      hipLaunchKernelGGL(k_adam, dim3(grid_for(WID[l + 1])), dim3(256), 0, m->stream, m->b[l], m->mb[l], m->vb[l],
+                         m->gb[l], 1, WID[l + 1], WID[l + 1], lr, b1, b2, eps, c1, c2);
+    }
+    refresh_bf16(m);
+  }
+  if (loss_out) {
+    float s = 0;
+    MHIP(hipMemcpyAsync(&s, m->loss, 4, hipMemcpyDeviceToHost, m->stream));
+    MHIP(hipStreamSynchronize(m->stream));
+    *loss_out = s / (float)(batch * 3);
+  } else if (grads_out) {
+    MHIP(hipStreamSynchronize(m->stream));
+  }
+  MHIP(hipGetLastError());
+  return STREAMI_OK;
+}
+
+}  // extern "C"

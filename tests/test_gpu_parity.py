@@ -170,7 +170,7 @@ def test_bit_identical_variants(S):
     seeds = fg.uniform_seeds(2, 2500, (0, 0, 0), (32, 32, 32), sub=9)
     base = run(S, [blk], [seeds], 0.5, 300, fg.F32)
     variants = [dict(no_cell_cache=1), dict(layout=2), dict(use_graph=1), dict(chunk=37),
-                dict(waves_per_cu=8, refill_threshold=1)]
+                dict(waves_per_cu=8, refill_threshold=1), dict(work_order=1)]
     for v in variants:
         note("variant", v)
         layout = v.pop("layout", 0)
