@@ -271,6 +271,7 @@ def main():
     ap.add_argument("--no-cell-cache", action="store_true")
     ap.add_argument("--graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--accuracy", action="store_true", help="report endpoint error against the FP64 field")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a plain 1 GiB device copy first (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -396,6 +397,20 @@ def main():
         "fetch_lines_ms_per_65536": fetch_s * 1e3,
         "outbox_records": int(len(ob)),
     }
+    if args.workload.startswith("turb512") or args.accuracy:
+        # error of the stored-format run against the FP64 oracle on the unrounded field
+        import oracle
+        k = 2048
+        Lk = f.lines(0, 0, k)
+        end = Lk["xyz"][Lk["offsets"][1:] - 1].astype(np.float64)
+        acc = oracle.Field.from_block(blk, use_values=True).trace(seeds[:k], h, m, keep_verts=False)
+        same = (acc["code"] == Lk["codes"]) & (acc["steps"] == Lk["steps"])
+        err = np.abs(end - acc["final_pos"]).max(axis=1) / blk.extent
+        out["endpoint_error_vs_fp64"] = {
+            "sample": k, "median": float(np.median(err)), "p90": float(np.quantile(err, 0.9)),
+            "max": float(err.max()), "frac_within_2e-3": float((err <= 2e-3).mean()),
+            "frac_within_1e-4": float((err <= 1e-4).mean()), "same_code_and_steps": float(same.mean())}
+        log(f"endpoint error vs FP64 field: {out['endpoint_error_vs_fp64']}")
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(blk, seeds, h, m)
