@@ -169,6 +169,12 @@ typedef struct {
                                results are bit-identical either way) */
   int32_t work_order;       /* 0: spatial order (block, Morton brick) split over per-XCD queues;
                                1: seed order, one queue (results are bit-identical either way) */
+  int32_t use_t_end;        /* 1: advance in a time window: a particle takes a step only while its
+                               time t_birth + steps*h is < t_end, and stays ACTIVE at t_end (PLAIN
+                               mode).  Successive calls with growing t_end give bit-identical
+                               results to one call without a window; they keep the particles that
+                               are alive at one instant in the same time slices (streaklines) */
+  float t_end;              /* end of the window (with use_t_end); must not be NaN */
 } streami_advect_params;
 
 typedef struct {

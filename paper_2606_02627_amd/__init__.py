@@ -61,7 +61,8 @@ class AdvectParams(ctypes.Structure):
                 ("mlp", ctypes.c_void_p), ("residual_tol_cells", ctypes.c_float),
                 ("residual_kind", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
                 ("refill_threshold", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("no_cell_cache", ctypes.c_int32), ("work_order", ctypes.c_int32)]
+                ("no_cell_cache", ctypes.c_int32), ("work_order", ctypes.c_int32),
+                ("use_t_end", ctypes.c_int32), ("t_end", ctypes.c_float)]
 
 
 class Stats(ctypes.Structure):
@@ -245,6 +246,9 @@ def advect_params(h, step_budget=0, eps=1e-6, **kw):
     p.mode = kw.pop("mode", MODE_PLAIN)
     net = kw.pop("mlp", None)
     p.mlp = net.value if isinstance(net, ctypes.c_void_p) else net
+    t_end = kw.pop("t_end", None)
+    if t_end is not None:
+        p.use_t_end, p.t_end = 1, float(t_end)
     for k, v in kw.items():
         setattr(p, k, v)
     return p

@@ -1,16 +1,18 @@
 """Launch-configuration autotuner for the batched advection launch.
 
-Times the real workload under each candidate (node layout: x-fastest rows or
-4x4x4 bricks; waves per CU; refill threshold; work order) through the C-ABI
-and caches the fastest per (device, dtype, block shapes, seed counts) in a
-JSON file (STREAMI_TUNE_CACHE, default ~/.cache/streami/autotune.json).
-Results are bit-identical under every candidate; only the time differs.
+Times the caller's whole pass (seeding plus every advect call of it) under each
+candidate -- node layout (x-fastest rows or 4x4x4 bricks), waves per CU,
+refill threshold, work order -- through the C-ABI, and caches the fastest per
+(device, dtype, block shapes, caller's signature) in a JSON file
+(STREAMI_TUNE_CACHE, default ~/.cache/streami/autotune.json).  Results are
+bit-identical under every candidate; only the time differs.
 """
 from __future__ import annotations
 
 import hashlib
 import json
 import os
+import time
 
 CANDIDATES = [dict(waves_per_cu=w, refill_threshold=r, work_order=o)
               for w in (16, 24, 32) for r in (1, 16) for o in (0, 1)]
@@ -21,40 +23,42 @@ def _cache_path():
     return os.environ.get("STREAMI_TUNE_CACHE", os.path.expanduser("~/.cache/streami/autotune.json"))
 
 
-def _key(blocks, seeds, fmt, h):
+def _key(blocks, fmt, sig):
     import torch
     dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
-    sig = hashlib.sha1(json.dumps([[list(b.dims), int(b.n_slices)] for b in blocks] + [[len(s) for s in seeds]]
-                                  + [fmt, h]).encode()).hexdigest()[:16]
-    return f"{dev}|{fmt}|{len(blocks)}|{sig}"
+    h = hashlib.sha1(json.dumps([[list(b.dims), int(b.n_slices)] for b in blocks] + [fmt, sig]).encode())
+    return f"{dev}|{fmt}|{len(blocks)}|{h.hexdigest()[:16]}"
 
 
-def load(blocks, seeds, fmt, h):
+def load(blocks, fmt, sig):
+    """The cached configuration for this workload, or None."""
     try:
-        return json.load(open(_cache_path())).get(_key(blocks, seeds, fmt, h))
+        return json.load(open(_cache_path())).get(_key(blocks, fmt, sig))
     except (OSError, ValueError):
         return None
 
 
-def tune(blocks, seeds, limits, fmt, h, record_stride=1, run_fn=None, log=None, repeats=2):
+def tune(blocks, fmt, pass_fn, sig, log=None, repeats=2):
     """Return the fastest configuration {layout, waves_per_cu, refill_threshold, work_order, ms}.
 
-    run_fn(field, params) -> device ms may replace the default seed+advect pass."""
-    from . import Field, streami_advect, advect_params
+    pass_fn(field, cfg) runs one whole pass on `field` (a Field over `blocks` with the
+    candidate's layout) with advect keyword arguments `cfg`; it is timed by wall clock
+    between two device synchronisations.  `sig` (JSON-able) names everything else the
+    pass depends on (seed counts, step, windows) for the cache key.
+    """
+    from . import Field
     import torch
     best = None
     trials = []
     for layout in LAYOUTS:
         f = Field(blocks, fmt, layout=layout)
-        dseeds = [torch.from_numpy(s).cuda() for s in seeds]
-        dlim = [torch.from_numpy(m).cuda() for m in limits]
 
         def one(cfg):
-            f.clear()
-            for b in range(len(blocks)):
-                f.seed(b, dseeds[b], max_steps=dlim[b], record_stride=record_stride)
-            st = streami_advect(f.h, advect_params(h, **cfg))
-            return st.device_ms
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            pass_fn(f, cfg)
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t) * 1e3
 
         one(CANDIDATES[0])  # warm-up
         for cfg in CANDIDATES:
@@ -72,7 +76,7 @@ def tune(blocks, seeds, limits, fmt, h, record_stride=1, run_fn=None, log=None, 
             cache = json.load(open(path))
         except (OSError, ValueError):
             cache = {}
-        cache[_key(blocks, seeds, fmt, h)] = best
+        cache[_key(blocks, fmt, sig)] = best
         json.dump(cache, open(path, "w"), indent=1)
     except OSError:
         pass

@@ -23,11 +23,13 @@
 //    aligned load; 16-bit values are widened in registers, all arithmetic FP32;
 //  * the outbox append is wave-aggregated (one atomic per wave and event).
 #pragma once
+#include <type_traits>
+
 #include "device.h"
 
 namespace streami {
 
-enum SampleMode { SM_CACHED = 0, SM_UNCACHED = 1, SM_UNSTEADY = 2 };
+enum SampleMode { SM_CACHED = 0, SM_UNCACHED = 1, SM_UNSTEADY = 2, SM_UNSTEADY_UNCACHED = 3 };
 
 __device__ __forceinline__ float lerpf(float a, float b, float t) { return fmaf(t, b - a, a); }
 
@@ -130,6 +132,35 @@ __device__ __forceinline__ float3 trilinear(const float3 c[8], float fx, float f
   return v;
 }
 
+// Trilinear interpolant in monomial form: corners c[i] (i = x + 2y + 4z) are
+// turned in place into the coefficients of 1, x, y, xy, z, xz, yz, xyz
+// (three difference stages), so that a sample is 7 fused multiply-adds per
+// component.  The coefficients of a constant field are exactly 0 beyond the
+// first, so constant fields stay exact.
+__device__ __forceinline__ void to_monomial(float3 c[8]) {
+#pragma unroll
+  for (int b = 1; b < 8; b <<= 1)
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (i & b) {
+        c[i].x -= c[i ^ b].x;
+        c[i].y -= c[i ^ b].y;
+        c[i].z -= c[i ^ b].z;
+      }
+}
+__device__ __forceinline__ float mono1(float k0, float k1, float k2, float k3, float k4, float k5, float k6, float k7,
+                                       float fx, float fy, float fz) {
+  const float a0 = fmaf(fz, k4, k0), a1 = fmaf(fz, k6, k2), a2 = fmaf(fz, k5, k1), a3 = fmaf(fz, k7, k3);
+  return fmaf(fx, fmaf(fy, a3, a2), fmaf(fy, a1, a0));
+}
+__device__ __forceinline__ float3 monomial(const float3 k[8], float fx, float fy, float fz) {
+  float3 v;
+  v.x = mono1(k[0].x, k[1].x, k[2].x, k[3].x, k[4].x, k[5].x, k[6].x, k[7].x, fx, fy, fz);
+  v.y = mono1(k[0].y, k[1].y, k[2].y, k[3].y, k[4].y, k[5].y, k[6].y, k[7].y, fx, fy, fz);
+  v.z = mono1(k[0].z, k[1].z, k[2].z, k[3].z, k[4].z, k[5].z, k[6].z, k[7].z, fx, fy, fz);
+  return v;
+}
+
 // sample(): the field value at (x, t); false where the block holds no data
 // for x (Sec. 3.1.1).
 template <int FMT, int LAYOUT, bool PERIODIC, int MODE>
@@ -180,12 +211,16 @@ struct Sampler {
     if (MODE == SM_CACHED) {
       if (ok && o000 != key) {
         gather(B, base, o000, x0, x1, y0, y1, z0, z1, c);
+        to_monomial(c);
         key = o000;
       }
-      v = trilinear(c, fx, fy, fz);
+      v = monomial(c, fx, fy, fz);
     } else if (MODE == SM_UNCACHED) {
-      if (ok) gather(B, base, o000, x0, x1, y0, y1, z0, z1, c);
-      v = trilinear(c, fx, fy, fz);
+      if (ok) {
+        gather(B, base, o000, x0, x1, y0, y1, z0, z1, c);
+        to_monomial(c);
+      }
+      v = monomial(c, fx, fy, fz);
     } else {
       // linear blend of the two slices bracketing t, clamped at the ends
       float3 d[8];
@@ -215,6 +250,137 @@ struct Sampler {
     }
     return ok;
   }
+};
+
+// Unsteady 16-bit nodes: the corners of the two slices that bracket t are
+// cached packed (x|y<<16 per corner, z pairs), 24 VGPRs instead of 48 as
+// FP32, and widened at each sample (key: cell and slice).
+template <int FMT>
+__device__ __forceinline__ float lo16(unsigned w);
+template <>
+__device__ __forceinline__ float lo16<FMT_BF16>(unsigned w) { return __uint_as_float(w << 16); }
+template <>
+__device__ __forceinline__ float lo16<FMT_F16>(unsigned w) {
+  return (float)__builtin_bit_cast(_Float16, (unsigned short)(w & 0xffffu));
+}
+template <int FMT>
+__device__ __forceinline__ float hi16(unsigned w);
+template <>
+__device__ __forceinline__ float hi16<FMT_BF16>(unsigned w) { return __uint_as_float(w & 0xffff0000u); }
+template <>
+__device__ __forceinline__ float hi16<FMT_F16>(unsigned w) {
+  return (float)__builtin_bit_cast(_Float16, (unsigned short)(w >> 16));
+}
+
+template <int FMT, int LAYOUT, bool PERIODIC>
+struct PackedSlicesSampler {
+  static constexpr unsigned NB = 8;
+  static constexpr int NS = 2;
+  unsigned key, skey;
+  unsigned xy[NS][8];  // corner c: x | y << 16
+  unsigned zz[NS][4];  // corners 2i, 2i+1: z | z << 16
+
+  __device__ __forceinline__ void reset() { key = 0xffffffffu; skey = 0xffffffffu; }
+
+  __device__ __forceinline__ void gather(const BlockDev& B, const char* base, unsigned o000, int x0, int x1, int y0,
+                                         int y1, int z0, int z1, unsigned* xyo, unsigned* zzo) {
+    int dx, r10, r01;
+    if (PERIODIC || LAYOUT == LAYOUT_BRICK4) {
+      dx = (int)off_x<LAYOUT, NB>(x1) - (int)off_x<LAYOUT, NB>(x0);
+      r10 = (int)off_y<LAYOUT, NB>(B, y1) - (int)off_y<LAYOUT, NB>(B, y0);
+      r01 = (int)off_z<LAYOUT, NB>(B, z1) - (int)off_z<LAYOUT, NB>(B, z0);
+    } else {
+      dx = (int)NB;
+      r10 = (int)B.ys;
+      r01 = (int)B.zs;
+    }
+    const char* p00 = base + o000;
+    const char* p10 = p00 + r10;
+    const char* p01 = p00 + r01;
+    const char* p11 = p01 + r10;
+    const uint2 w0 = *reinterpret_cast<const uint2*>(p00), w1 = *reinterpret_cast<const uint2*>(p00 + dx);
+    const uint2 w2 = *reinterpret_cast<const uint2*>(p10), w3 = *reinterpret_cast<const uint2*>(p10 + dx);
+    const uint2 w4 = *reinterpret_cast<const uint2*>(p01), w5 = *reinterpret_cast<const uint2*>(p01 + dx);
+    const uint2 w6 = *reinterpret_cast<const uint2*>(p11), w7 = *reinterpret_cast<const uint2*>(p11 + dx);
+    xyo[0] = w0.x; xyo[1] = w1.x; xyo[2] = w2.x; xyo[3] = w3.x;
+    xyo[4] = w4.x; xyo[5] = w5.x; xyo[6] = w6.x; xyo[7] = w7.x;
+    zzo[0] = (w0.y & 0xffffu) | (w1.y << 16);
+    zzo[1] = (w2.y & 0xffffu) | (w3.y << 16);
+    zzo[2] = (w4.y & 0xffffu) | (w5.y << 16);
+    zzo[3] = (w6.y & 0xffffu) | (w7.y << 16);
+  }
+
+  // one component at a time, so only 8 widened values are live at once
+  __device__ __forceinline__ static float tri1(float c0, float c1, float c2, float c3, float c4, float c5,
+                                               float c6, float c7, float fx, float fy, float fz) {
+    return lerpf(lerpf(lerpf(c0, c1, fx), lerpf(c2, c3, fx), fy), lerpf(lerpf(c4, c5, fx), lerpf(c6, c7, fx), fy),
+                 fz);
+  }
+  __device__ __forceinline__ float3 interp(int sl, float fx, float fy, float fz) const {
+    const unsigned* a = xy[sl];
+    const unsigned* b = zz[sl];
+    float3 v;
+    v.x = tri1(lo16<FMT>(a[0]), lo16<FMT>(a[1]), lo16<FMT>(a[2]), lo16<FMT>(a[3]), lo16<FMT>(a[4]),
+               lo16<FMT>(a[5]), lo16<FMT>(a[6]), lo16<FMT>(a[7]), fx, fy, fz);
+    v.y = tri1(hi16<FMT>(a[0]), hi16<FMT>(a[1]), hi16<FMT>(a[2]), hi16<FMT>(a[3]), hi16<FMT>(a[4]),
+               hi16<FMT>(a[5]), hi16<FMT>(a[6]), hi16<FMT>(a[7]), fx, fy, fz);
+    v.z = tri1(lo16<FMT>(b[0]), hi16<FMT>(b[0]), lo16<FMT>(b[1]), hi16<FMT>(b[1]), lo16<FMT>(b[2]),
+               hi16<FMT>(b[2]), lo16<FMT>(b[3]), hi16<FMT>(b[3]), fx, fy, fz);
+    return v;
+  }
+
+  __device__ __forceinline__ bool operator()(const BlockDev& B, const char* base, float3 x, float t,
+                                             float3& v) {
+    bool ok = true;
+    int x0, x1, y0, y1, z0, z1;
+    float fx, fy, fz;
+    locate_axis<PERIODIC>(x.x, B.scale[0], B.offs[0], B.fn[0], B.inv_fn[0], x0, x1, fx, ok);
+    locate_axis<PERIODIC>(x.y, B.scale[1], B.offs[1], B.fn[1], B.inv_fn[1], y0, y1, fy, ok);
+    locate_axis<PERIODIC>(x.z, B.scale[2], B.offs[2], B.fn[2], B.inv_fn[2], z0, z1, fz, ok);
+    const unsigned o000 = off_x<LAYOUT, NB>(x0) + off_y<LAYOUT, NB>(B, y0) + off_z<LAYOUT, NB>(B, z0);
+    int s = 0;
+    float al = 0.0f;
+    if (B.n_slices > 1) {
+      const float u = (t - B.t0) * B.inv_sdt;
+      const float fs = fminf(fmaxf(floorf(u), 0.0f), (float)(B.n_slices - 2));
+      s = (int)fs;
+      al = fminf(fmaxf(u - fs, 0.0f), 1.0f);
+    }
+    if (ok && (o000 != key || (unsigned)s != skey)) {
+      const char* b0 = base + (size_t)s * B.slice_bytes;
+      gather(B, b0, o000, x0, x1, y0, y1, z0, z1, xy[0], zz[0]);
+      if (B.n_slices > 1) gather(B, b0 + B.slice_bytes, o000, x0, x1, y0, y1, z0, z1, xy[1], zz[1]);
+      key = o000;
+      skey = (unsigned)s;
+    }
+    float3 v0 = interp(0, fx, fy, fz);
+    if (B.n_slices > 1) {
+      const float3 v1 = interp(1, fx, fy, fz);
+      v0.x = lerpf(v0.x, v1.x, al);
+      v0.y = lerpf(v0.y, v1.y, al);
+      v0.z = lerpf(v0.z, v1.z, al);
+    }
+    v = v0;
+    return ok;
+  }
+};
+
+// The sampler each (format, mode) uses: the FP32 register cache of the cell's
+// monomial coefficients for steady fields (every format), the packed two-slice
+// cache for unsteady 16-bit fields, or no cache.  FP32 unsteady sampling is
+// uncached (two slices of FP32 corners would not fit the register budget), and
+// SM_UNSTEADY_UNCACHED is that plain form for every format.
+template <int FMT, int LAYOUT, bool PERIODIC, int MODE>
+struct SamplerFor {
+  using type = Sampler<FMT, LAYOUT, PERIODIC, MODE == SM_UNSTEADY_UNCACHED ? SM_UNSTEADY : MODE>;
+};
+template <int LAYOUT, bool PERIODIC>
+struct SamplerFor<FMT_F16, LAYOUT, PERIODIC, SM_UNSTEADY> {
+  using type = PackedSlicesSampler<FMT_F16, LAYOUT, PERIODIC>;
+};
+template <int LAYOUT, bool PERIODIC>
+struct SamplerFor<FMT_BF16, LAYOUT, PERIODIC, SM_UNSTEADY> {
+  using type = PackedSlicesSampler<FMT_BF16, LAYOUT, PERIODIC>;
 };
 
 // One classical RK4 update from (P, t).  Returns ACTIVE when the step was
@@ -258,6 +424,14 @@ __device__ __forceinline__ bool inside(const BlockDev& B, float3 x) {
          x.z < B.hi[2];
 }
 
+// A value every lane holds the same copy of, moved to scalar registers so that
+// addresses built from it use the scalar-base form of the memory instructions.
+__device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v) {
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return ((unsigned long long)hi << 32) | lo;
+}
+
 __device__ __forceinline__ unsigned lanes_below(unsigned long long m) {
   return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
@@ -270,7 +444,7 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 extern __shared__ BlockDev g_lds_blocks[];
 
 template <int FMT, int LAYOUT, bool PERIODIC, int MODE, bool BATCHED>
-__global__ void __launch_bounds__(256) k_advect(AdvectArgs A) {
+__device__ __forceinline__ void advect_body(const AdvectArgs& A) {
   constexpr unsigned NB = NodeBytes<FMT>::v;
   BlockDev B0;
   const char* base0 = nullptr;
@@ -291,7 +465,7 @@ __global__ void __launch_bounds__(256) k_advect(AdvectArgs A) {
   unsigned long long cpos = 0, cend = 0;
   bool log_ok = true;
   unsigned my_steps = 0, my_verts = 0;
-  Sampler<FMT, LAYOUT, PERIODIC, MODE> smp;
+  typename SamplerFor<FMT, LAYOUT, PERIODIC, MODE>::type smp;
   smp.reset();
   bool queue_done = false;  // wave-uniform
   const unsigned long long all = __ballot(1);
@@ -317,9 +491,9 @@ __global__ void __launch_bounds__(256) k_advect(AdvectArgs A) {
         if (slot < qhi) {
           const long long my = A.order ? (long long)A.order[slot] : slot;
           const int4 mt = A.meta[my];
-          if (mt.z == ACTIVE) {
+          const float4 ps = A.pos[my];
+          if (mt.z == ACTIVE && fmaf((float)mt.x, A.h, ps.w) < A.t_end) {
             p = (int)my;
-            const float4 ps = A.pos[my];
             P = make_float3(ps.x, ps.y, ps.z);
             tb = ps.w;
             n = mt.x; m = mt.y; nv = mt.w;
@@ -342,11 +516,13 @@ __global__ void __launch_bounds__(256) k_advect(AdvectArgs A) {
     bool rec = false;  // a vertex (P, index nv) to append this iteration
     if (p >= 0) {
       const BlockDev& B = BATCHED ? g_lds_blocks[blk] : B0;
+      const float t = fmaf((float)n, A.h, tb);
       if (n >= m) {
         term = MAX_STEPS;
+      } else if (!(t < A.t_end)) {
+        left = 0;  // the window ends here: park the particle, still ACTIVE
       } else {
         float3 P1, fail;
-        const float t = fmaf((float)n, A.h, tb);
         const int st = rk4_step(smp, B, lbase, P, t, A.h, A.eps2, P1, fail);
         if (st == ACTIVE) {
           P = P1;
@@ -380,10 +556,10 @@ __global__ void __launch_bounds__(256) k_advect(AdvectArgs A) {
       const unsigned cnt = (unsigned)__popcll(vm);
       if (cpos + cnt > cend) {
         // mark the unused tail of the old chunk (< 64 records) so fetches skip it
-        if (log_ok && cpos + lane < cend) A.log.pj[cpos + lane] = make_uint2(0xffffffffu, 0xffffffffu);
+        if (log_ok && cpos + lane < cend) A.log.v[cpos + lane] = make_float4(0.f, 0.f, 0.f, __uint_as_float(LOG_UNUSED));
         unsigned long long nb = 0;
         if (lane == 0) nb = atomicAdd(A.log.count, (unsigned long long)LOG_CHUNK);
-        nb = __shfl(nb, 0, 64);
+        nb = uniform_u64(__shfl(nb, 0, 64));
         if (nb + LOG_CHUNK > (unsigned long long)A.log.cap) {
           log_ok = false;  // cannot happen when the host sized the log; never write past it
           if (lane == 0) atomicOr(&A.ctr[CTR_OVERFLOW], 1ull);
@@ -392,11 +568,13 @@ __global__ void __launch_bounds__(256) k_advect(AdvectArgs A) {
         cend = nb + LOG_CHUNK;
       }
       if (rec && log_ok) {
-        const unsigned long long r = cpos + lanes_below(vm);
-        A.log.x[r] = P.x;
-        A.log.y[r] = P.y;
-        A.log.z[r] = P.z;
-        A.log.pj[r] = make_uint2((unsigned)p, (unsigned)nv);
+        // wave-uniform chunk base (scalar address) + a 32-bit lane offset
+        const unsigned k = lanes_below(vm);
+        const unsigned long long cu = uniform_u64(cpos);
+        float4* vb = A.log.v + cu;
+        unsigned* jb = A.log.j + cu;
+        vb[k] = make_float4(P.x, P.y, P.z, __uint_as_float((unsigned)p));
+        jb[k] = (unsigned)nv;
       }
       if (rec) {
         ++nv;
@@ -431,7 +609,8 @@ __global__ void __launch_bounds__(256) k_advect(AdvectArgs A) {
   }
   // mark the unused tail of this wave's last chunk
   if (log_ok)
-    for (unsigned long long r = cpos + lane; r < cend; r += 64) A.log.pj[r] = make_uint2(0xffffffffu, 0xffffffffu);
+    for (unsigned long long r = cpos + lane; r < cend; r += 64)
+      A.log.v[r] = make_float4(0.f, 0.f, 0.f, __uint_as_float(LOG_UNUSED));
   const unsigned long long s = wave_sum((unsigned long long)my_steps), v = wave_sum((unsigned long long)my_verts);
   if (lane == 0) {
     if (s) atomicAdd(&A.ctr[CTR_STEPS], s);
@@ -450,7 +629,7 @@ __global__ void __launch_bounds__(256) k_sur_pre(SurrogateArgs S) {
   const AdvectArgs& A = S.a;
   const BlockDev B = A.blocks[0];
   const char* base = reinterpret_cast<const char*>(A.nodes) + (size_t)B.base * NB;
-  Sampler<FMT, LAYOUT, PERIODIC, SM_CACHED> smp;
+  typename SamplerFor<FMT, LAYOUT, PERIODIC, SM_CACHED>::type smp;
   for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < A.n_particles;
        q += (long long)gridDim.x * blockDim.x) {
     if (A.meta[q].z != ACTIVE) continue;
@@ -479,7 +658,7 @@ __global__ void __launch_bounds__(256) k_sur_apply(SurrogateArgs S) {
   const BlockDev B = A.blocks[0];
   const char* base = reinterpret_cast<const char*>(A.nodes) + (size_t)B.base * NB;
   const int lane = __lane_id();
-  Sampler<FMT, LAYOUT, PERIODIC, SM_CACHED> smp;
+  typename SamplerFor<FMT, LAYOUT, PERIODIC, SM_CACHED>::type smp;
   unsigned my_steps = 0, acc = 0, fb = 0;
   for (long long q0 = blockIdx.x * (long long)blockDim.x; q0 < A.n_particles; q0 += (long long)gridDim.x * blockDim.x) {
     const long long q = q0 + threadIdx.x;
@@ -579,10 +758,8 @@ __global__ void __launch_bounds__(256) k_sur_apply(SurrogateArgs S) {
       if (rec) {
         const unsigned long long r = b + lanes_below(vm);
         if (r < (unsigned long long)A.log.cap) {
-          A.log.x[r] = P.x;
-          A.log.y[r] = P.y;
-          A.log.z[r] = P.z;
-          A.log.pj[r] = make_uint2((unsigned)q, (unsigned)mt.w);
+          A.log.v[r] = make_float4(P.x, P.y, P.z, __uint_as_float((unsigned)q));
+          A.log.j[r] = (unsigned)mt.w;
         }
         ++mt.w;
       }
@@ -631,6 +808,11 @@ int launch_surrogate_fmt(const SurrogateArgs& s, int layout, bool periodic, bool
 }
 
 template <int FMT, int LAYOUT, bool PERIODIC, int MODE, bool BATCHED>
+__global__ void __launch_bounds__(256) k_advect(AdvectArgs A) {
+  advect_body<FMT, LAYOUT, PERIODIC, MODE, BATCHED>(A);
+}
+
+template <int FMT, int LAYOUT, bool PERIODIC, int MODE, bool BATCHED>
 static void launch_variant(const AdvectArgs& a, int grid, hipStream_t st) {
   const size_t lds = BATCHED ? sizeof(BlockDev) * (size_t)a.n_blocks : 0;
   hipLaunchKernelGGL((k_advect<FMT, LAYOUT, PERIODIC, MODE, BATCHED>), dim3(grid), dim3(256), lds, st, a);
@@ -646,7 +828,8 @@ int launch_advect_fmt(const AdvectArgs& a, int layout, bool periodic, int mode, 
     if (periodic) return -1;                                                                        \
     if (mode == SM_CACHED) launch_variant<FMT, LAY, false, SM_CACHED, true>(a, grid, st);           \
     else if (mode == SM_UNCACHED) launch_variant<FMT, LAY, false, SM_UNCACHED, true>(a, grid, st);  \
-    else launch_variant<FMT, LAY, false, SM_UNSTEADY, true>(a, grid, st);                          \
+    else if (mode == SM_UNSTEADY) launch_variant<FMT, LAY, false, SM_UNSTEADY, true>(a, grid, st);  \
+    else launch_variant<FMT, LAY, false, SM_UNSTEADY_UNCACHED, true>(a, grid, st);                 \
   } else if (periodic) {                                                                            \
     if (mode == SM_CACHED) launch_variant<FMT, LAY, true, SM_CACHED, false>(a, grid, st);           \
     else if (mode == SM_UNCACHED) launch_variant<FMT, LAY, true, SM_UNCACHED, false>(a, grid, st);  \
@@ -654,9 +837,11 @@ int launch_advect_fmt(const AdvectArgs& a, int layout, bool periodic, int mode, 
   } else {                                                                                          \
     if (mode == SM_CACHED) launch_variant<FMT, LAY, false, SM_CACHED, false>(a, grid, st);          \
     else if (mode == SM_UNCACHED) launch_variant<FMT, LAY, false, SM_UNCACHED, false>(a, grid, st); \
-    else launch_variant<FMT, LAY, false, SM_UNSTEADY, false>(a, grid, st);                         \
+    else if (mode == SM_UNSTEADY) launch_variant<FMT, LAY, false, SM_UNSTEADY, false>(a, grid, st); \
+    else launch_variant<FMT, LAY, false, SM_UNSTEADY_UNCACHED, false>(a, grid, st);                \
   }                                                                                                 \
   return 0;
+  if (FMT == FMT_F32 && mode == SM_UNSTEADY_UNCACHED) mode = SM_UNSTEADY;  // the same sampler
   if (layout == LAYOUT_BRICK4) {
     STREAMI_L(LAYOUT_BRICK4)
   } else {

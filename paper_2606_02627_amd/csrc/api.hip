@@ -38,9 +38,10 @@ int launch_scatter_lines(const VertexLog& log, long long n_rec, long long n_part
 int launch_mark_rows(const long long* idx, long long count, int* row_of, hipStream_t st);
 int launch_fill_u32(unsigned* p, long long n, unsigned v, hipStream_t st);
 int launch_work_order(const float4* pos, const int4* meta, const int4* meta2, const BlockDev* blocks, long long n,
-                      int bits, unsigned n_buckets, unsigned* key, unsigned* hist, unsigned* cursor, int* order,
-                      unsigned* n_work, hipStream_t st);
+                      int bits, unsigned n_buckets, float h, float t_end, unsigned* key, unsigned* hist,
+                      unsigned* cursor, int* order, unsigned* n_work, hipStream_t st);
 int launch_fill_u64(unsigned long long* p, long long n, unsigned long long v, hipStream_t st);
+int launch_seed_bound(const int* ms, long long n, int stride, unsigned long long* out, hipStream_t st);
 int launch_gather_meta(const long long* idx, long long count, const int4* meta, const int4* meta2,
                        const unsigned long long* pid, long long* nverts, int* steps, int* codes,
                        unsigned long long* ids, hipStream_t st);
@@ -143,9 +144,15 @@ struct streami_field_s {
   DevBuf d_pos, d_meta, d_meta2, d_ids, d_outbox;
   // vertex log (see VertexLog): capacity in records, and the sum over all
   // particles of the vertices each may still record at most
-  DevBuf d_logx, d_logy, d_logz, d_logpj;
+  DevBuf d_logv, d_logj;
   long long log_cap = 0;
   long long vert_bound = 0;
+  // host upper bound of the log records still needed (reserved + to come, with
+  // the chunk-tail allowance); valid while no advect ran since it was set
+  bool log_need_known = false;
+  long long log_need_hi = 0;
+  DevBuf d_seedred;                         // k_seed_bound output
+  unsigned long long* h_seedred = nullptr;  // pinned copy of it
   DevBuf d_ctr;        // CTR_N per-call counters, PER_N persistent counters, 6 code counts
   DevBuf d_qctr;       // per-queue work counters
   DevBuf d_key, d_order, d_hist, d_cursor, d_nwork;  // spatial work order
@@ -164,10 +171,8 @@ struct streami_field_s {
   unsigned long long* code_counts() { return persist() + PER_N; }
   VertexLog log() {
     VertexLog l;
-    l.x = (float*)d_logx.p;
-    l.y = (float*)d_logy.p;
-    l.z = (float*)d_logz.p;
-    l.pj = (uint2*)d_logpj.p;
+    l.v = (float4*)d_logv.p;
+    l.j = (unsigned*)d_logj.p;
     l.count = persist() + PER_LOG;
     l.real = persist() + PER_LOG_REAL;
     l.cap = log_cap;
@@ -296,13 +301,13 @@ int ensure_log(streami_field_s* f, long long slack) {
   // the remaining bound plus 1/8 for those tails, plus `slack` for last chunks
   const long long remaining = std::max<long long>(f->vert_bound - (long long)c[PER_LOG_REAL], 0);
   const long long need = (long long)c[PER_LOG] + remaining + remaining / 8 + slack;
+  f->log_need_known = true;
+  f->log_need_hi = need - slack;
   if (need <= f->log_cap) return STREAMI_OK;
   const long long cap = std::max(need, f->log_cap + f->log_cap / 4);
   int rc;
-  if ((rc = f->d_logx.reserve(cap * 4, count * 4, f->stream))) return rc;
-  if ((rc = f->d_logy.reserve(cap * 4, count * 4, f->stream))) return rc;
-  if ((rc = f->d_logz.reserve(cap * 4, count * 4, f->stream))) return rc;
-  if ((rc = f->d_logpj.reserve(cap * 8, count * 8, f->stream))) return rc;
+  if ((rc = f->d_logv.reserve(cap * 16, count * 16, f->stream))) return rc;
+  if ((rc = f->d_logj.reserve(cap * 4, count * 4, f->stream))) return rc;
   f->log_cap = cap;
   return STREAMI_OK;
 }
@@ -370,6 +375,7 @@ int advect_surrogate(streami_field_s* f, const streami_advect_params* p, streami
   a.n_particles = n;
   a.h = p->h;
   a.eps2 = p->stagnation_eps * p->stagnation_eps;
+  a.t_end = INFINITY;
   s.dhat = (const float*)f->d_dhat.p;
   s.dhat2 = (const float*)f->d_dhat2.p;
   s.xh = (float*)f->d_xh.p;
@@ -385,6 +391,7 @@ int advect_surrogate(streami_field_s* f, const streami_advect_params* p, streami
     return launch_surrogate_bf16(s, f->layout, f->periodic, pre, grid, f->stream);
   };
   HIP_TRY(hipEventRecord(f->ev0, f->stream));
+  f->log_need_known = false;  // the launch appends records the host does not count
   launch_fill_u64(a.ctr, CTR_N, 0, f->stream);
   for (long long j = 0; j < jumps; ++j) {
     if (s.kind == 0) {
@@ -492,9 +499,11 @@ int streami_field_destroy(streami_field f) {
   (void)hipStreamSynchronize(f->stream);
   drop_graph(f);
   for (DevBuf* b : {&f->d_blocks, &f->d_nodes, &f->d_pos, &f->d_meta, &f->d_meta2, &f->d_ids, &f->d_outbox,
-                    &f->d_logx, &f->d_logy, &f->d_logz, &f->d_logpj, &f->d_ctr, &f->d_qctr, &f->d_key,
-                    &f->d_order, &f->d_hist, &f->d_cursor, &f->d_nwork, &f->d_dhat, &f->d_dhat2, &f->d_xh})
+                    &f->d_logv, &f->d_logj, &f->d_ctr, &f->d_qctr, &f->d_key,
+                    &f->d_order, &f->d_hist, &f->d_cursor, &f->d_nwork, &f->d_dhat, &f->d_dhat2, &f->d_xh,
+                    &f->d_seedred})
     b->release();
+  if (f->h_seedred) (void)hipHostFree(f->h_seedred);
   if (f->ev0) (void)hipEventDestroy(f->ev0);
   if (f->ev1) (void)hipEventDestroy(f->ev1);
   delete f;
@@ -514,30 +523,41 @@ int streami_seed(streami_field f, int32_t block, const float* xyz, const uint64_
   if (!max_steps && opts->default_max_steps < 0) return fail(STREAMI_E_ARG, "default_max_steps must be >= 0");
   const bool dev_in = opts->inputs_on_device != 0;
   // per-particle limits on the host, to reserve vertex slots
-  std::vector<int32_t> ms;
-  if (max_steps) {
-    ms.resize(n);
-    if (dev_in) {
-      HIP_TRY(hipMemcpy(ms.data(), max_steps, n * 4, hipMemcpyDeviceToHost));
-    } else {
-      std::memcpy(ms.data(), max_steps, n * 4);
-    }
-    for (long long i = 0; i < n; ++i)
-      if (ms[i] < 0) return fail(STREAMI_E_ARG, "max_steps[%lld] < 0", i);
-  }
   // every particle may record at most max_steps/stride + 2 vertices
   long long bound = 0;
   int batch_max = 0;
-  for (long long i = 0; i < n; ++i) {
-    const int m = max_steps ? ms[i] : opts->default_max_steps;
-    bound += m / opts->record_stride + 2;
-    batch_max = std::max(batch_max, m);
-  }
   int rc;
+  if (max_steps && dev_in) {  // reduce on the device; 24 bytes come back
+    if ((rc = f->d_seedred.reserve(32, 0, f->stream))) return rc;
+    if (!f->h_seedred && hipHostMalloc((void**)&f->h_seedred, 32, hipHostMallocDefault) != hipSuccess) {
+      f->h_seedred = nullptr;
+      return fail(STREAMI_E_NOMEM, "pinned host allocation failed");
+    }
+    launch_seed_bound(max_steps, n, opts->record_stride, (unsigned long long*)f->d_seedred.p, f->stream);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(f->h_seedred, f->d_seedred.p, 24, hipMemcpyDeviceToHost, f->stream));
+    HIP_TRY(hipStreamSynchronize(f->stream));
+    if (f->h_seedred[2]) return fail(STREAMI_E_ARG, "max_steps has a negative entry");
+    bound = (long long)f->h_seedred[0];
+    batch_max = (int)f->h_seedred[1];
+  } else {
+    for (long long i = 0; i < n; ++i) {
+      const int m = max_steps ? max_steps[i] : opts->default_max_steps;
+      if (m < 0) return fail(STREAMI_E_ARG, "max_steps[%lld] < 0", i);
+      bound += m / opts->record_stride + 2;
+      batch_max = std::max(batch_max, m);
+    }
+  }
   drop_graph(f);
   if ((rc = ensure_particles(f, f->n_particles + n))) return rc;
+  // Seeding k particles inside the block adds k records and k real vertices
+  // and raises vert_bound by `bound` >= k, so the need grows by at most
+  // bound + bound/8 + 1: while the host bound covers that, no read-back.
+  const long long grow = bound + bound / 8 + 1;
   f->vert_bound += bound;
-  if ((rc = ensure_log(f, 0))) {
+  if (f->log_need_known && f->log_need_hi + grow <= f->log_cap) {
+    f->log_need_hi += grow;
+  } else if ((rc = ensure_log(f, 0))) {
     f->vert_bound -= bound;
     return rc;
   }
@@ -559,7 +579,7 @@ int streami_seed(streami_field f, int32_t block, const float* xyz, const uint64_
     }
     if (max_steps) {
       if ((rc = s_ms.reserve(n * 4, 0, f->stream))) return rc;
-      HIP_TRY(hipMemcpyAsync(s_ms.p, ms.data(), n * 4, hipMemcpyHostToDevice, f->stream));
+      HIP_TRY(hipMemcpyAsync(s_ms.p, max_steps, n * 4, hipMemcpyHostToDevice, f->stream));
       d_ms = (const int*)s_ms.p;
     }
     if (opts->t_births) {
@@ -596,8 +616,14 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
     return fail(STREAMI_E_ARG, "refill_threshold must be in [0,64]");
   if (p->work_order != 0 && p->work_order != 1) return fail(STREAMI_E_ARG, "work_order must be 0 or 1");
   if (f->n_particles == 0) return fail(STREAMI_E_STATE, "no particles seeded");
-  if (p->mode == STREAMI_MODE_SURROGATE) return advect_surrogate(f, p, stats);
+  if (p->use_t_end != 0 && p->use_t_end != 1) return fail(STREAMI_E_ARG, "use_t_end must be 0 or 1");
+  if (p->use_t_end && std::isnan(p->t_end)) return fail(STREAMI_E_ARG, "t_end is NaN");
+  if (p->mode == STREAMI_MODE_SURROGATE) {
+    if (p->use_t_end) return fail(STREAMI_E_UNSUPPORTED, "surrogate mode takes no time window");
+    return advect_surrogate(f, p, stats);
+  }
   AdvectArgs a;
+  std::memset(&a, 0, sizeof a);  // padding too: the graph cache compares the bytes
   a.blocks = (const BlockDev*)f->d_blocks.p;
   a.n_blocks = (int)f->blocks.size();
   a.nodes = f->d_nodes.p;
@@ -613,6 +639,7 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
   a.eps2 = p->stagnation_eps * p->stagnation_eps;
   a.budget = p->step_budget;
   a.refill = p->refill_threshold > 0 ? p->refill_threshold : 16;
+  a.t_end = p->use_t_end ? p->t_end : INFINITY;
   const int wpc = p->waves_per_cu > 0 ? p->waves_per_cu : 32;
   long long grid = (long long)f->n_cu * wpc / 4;
   grid = std::min(grid, (f->n_particles + 255) / 256);
@@ -642,13 +669,14 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
   a.qctr = (unsigned long long*)f->d_qctr.p;
   a.n_queues = spatial ? MAX_QUEUES : 1;
   const bool batched = f->blocks.size() > 1;
-  const int mode = f->unsteady ? 2 : (p->no_cell_cache ? 1 : 0);
+  const int mode = f->unsteady ? (p->no_cell_cache ? 3 : 2) : (p->no_cell_cache ? 1 : 0);
   auto launch = [&](hipStream_t st) {
     if (f->fmt == STREAMI_F32) return launch_advect_f32(a, f->layout, f->periodic, mode, batched, (int)grid, st);
     if (f->fmt == STREAMI_F16) return launch_advect_f16(a, f->layout, f->periodic, mode, batched, (int)grid, st);
     return launch_advect_bf16(a, f->layout, f->periodic, mode, batched, (int)grid, st);
   };
   HIP_TRY(hipEventRecord(f->ev0, f->stream));
+  f->log_need_known = false;  // the launch appends records the host does not count
   if (p->use_graph) {
     const int key[6] = {(int)grid, a.refill, a.budget, mode, (int)(p->h * 1e6f), spatial ? 1 : 0};
     bool same = f->graph && std::memcmp(key, f->graph_key, sizeof key) == 0 &&
@@ -663,7 +691,7 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
       launch_fill_u64(a.qctr, MAX_QUEUES * QCTR_STRIDE, 0, cs);
       if (spatial)
         launch_work_order((const float4*)f->d_pos.p, (const int4*)f->d_meta.p, (const int4*)f->d_meta2.p,
-                          (const BlockDev*)f->d_blocks.p, f->n_particles, bits, n_buckets, (unsigned*)f->d_key.p,
+                          (const BlockDev*)f->d_blocks.p, f->n_particles, bits, n_buckets, a.h, a.t_end, (unsigned*)f->d_key.p,
                           (unsigned*)f->d_hist.p, (unsigned*)f->d_cursor.p, (int*)f->d_order.p,
                           (unsigned*)f->d_nwork.p, cs);
       launch(cs);
@@ -680,7 +708,7 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
     launch_fill_u64(a.qctr, MAX_QUEUES * QCTR_STRIDE, 0, f->stream);
     if (spatial)
       launch_work_order((const float4*)f->d_pos.p, (const int4*)f->d_meta.p, (const int4*)f->d_meta2.p,
-                        (const BlockDev*)f->d_blocks.p, f->n_particles, bits, n_buckets, (unsigned*)f->d_key.p,
+                        (const BlockDev*)f->d_blocks.p, f->n_particles, bits, n_buckets, a.h, a.t_end, (unsigned*)f->d_key.p,
                         (unsigned*)f->d_hist.p, (unsigned*)f->d_cursor.p, (int*)f->d_order.p,
                         (unsigned*)f->d_nwork.p, f->stream);
     launch(f->stream);
@@ -699,6 +727,8 @@ int streami_clear(streami_field f) {
   f->max_m = 0;
   f->strides_mult16 = true;
   f->next_auto_id = 0;
+  f->log_need_known = true;  // the counters below restart at zero
+  f->log_need_hi = 0;
   for (auto& hb : f->blocks) {
     hb.ranges.clear();
     hb.n_particles = 0;

@@ -57,16 +57,16 @@ enum Persist { PER_OUTBOX = 0, PER_LOG = 1, PER_LOG_REAL = 2, PER_N = 4 };
 
 // Vertex log: a wave appends the vertices its lanes produce in one step as a
 // contiguous run (ballot + mbcnt) inside a chunk it reserved with one atomic,
-// so every store is part of a full, coalesced line.  Each record carries the
-// particle index and the vertex's index within that particle's line; fetching
-// scatters records to their CSR rows without sorting.
-constexpr int LOG_CHUNK = 1024;  // records per wave reservation
+// so every store is part of a full, coalesced line.  A record is one 16-byte
+// (x, y, z, particle index) plus the vertex's index within that particle's
+// line in a parallel array: two stores per vertex.  Fetching scatters records
+// to their CSR rows without sorting.
+constexpr int LOG_CHUNK = 1024;      // records per wave reservation
+constexpr unsigned LOG_UNUSED = 0xffffffffu;  // particle index of an unused record
 
 struct VertexLog {
-  float* x;
-  float* y;
-  float* z;
-  uint2* pj;                       // (particle index, vertex index)
+  float4* v;                       // x, y, z, particle index (as bits)
+  unsigned* j;                     // vertex index within its line
   unsigned long long* count;       // records reserved (incl. unused chunk tails)
   unsigned long long* real;        // records written
   long long cap;                   // records the buffers hold
@@ -97,6 +97,7 @@ struct AdvectArgs {
   float eps2;               // stagnation_eps^2
   int budget;               // 0 = unlimited
   int refill;               // free lanes that trigger a refill
+  float t_end;              // a step starts only at t < t_end (+inf: no window)
 };
 
 // One surrogate jump (16 plain steps) for every active particle of a single

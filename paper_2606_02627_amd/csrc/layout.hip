@@ -87,10 +87,8 @@ __global__ void k_seed(const float* xyz, const unsigned long long* ids, unsigned
     if (i < n) {
       const unsigned long long r = b + __builtin_amdgcn_mbcnt_hi((unsigned)(vm >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)vm, 0u));
       if (r < (unsigned long long)log.cap) {
-        log.x[r] = x.x;
-        log.y[r] = x.y;
-        log.z[r] = x.z;
-        log.pj[r] = make_uint2((unsigned)q, 0u);
+        log.v[r] = make_float4(x.x, x.y, x.z, __uint_as_float((unsigned)q));
+        log.j[r] = 0u;
       }
     }
     if (lane == 0) atomicAdd(log.real, (unsigned long long)__popcll(vm));
@@ -140,15 +138,16 @@ __global__ void k_scatter_lines(VertexLog log, long long n_rec, long long n_part
                                 const long long* offsets, float* out) {
   for (long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x; r < n_rec;
        r += (long long)gridDim.x * blockDim.x) {
-    const uint2 pj = log.pj[r];
-    if ((long long)pj.x >= n_particles) continue;  // unused tail of a chunk
-    const int row = row_of[pj.x];
+    const float4 v = log.v[r];
+    const unsigned p = __float_as_uint(v.w);
+    if ((long long)p >= n_particles) continue;  // unused tail of a chunk
+    const int row = row_of[p];
     if (row < 0) continue;
-    const long long o = offsets[row] + pj.y;
+    const long long o = offsets[row] + log.j[r];
     if (o >= offsets[row + 1]) continue;
-    out[o * 3 + 0] = log.x[r];
-    out[o * 3 + 1] = log.y[r];
-    out[o * 3 + 2] = log.z[r];
+    out[o * 3 + 0] = v.x;
+    out[o * 3 + 1] = v.y;
+    out[o * 3 + 2] = v.z;
   }
 }
 
@@ -193,6 +192,43 @@ int launch_fill_u32(unsigned* p, long long n, unsigned v, hipStream_t st) {
 __global__ void k_fill_u64(unsigned long long* p, long long n, unsigned long long v) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     p[i] = v;
+}
+
+int launch_fill_u64(unsigned long long* p, long long n, unsigned long long v, hipStream_t st);
+
+// Vertex bound of a seed batch whose step limits are on the device:
+// out[0] += sum(m / stride + 2), out[1] = max(out[1], m), out[2] |= (any m < 0).
+__global__ void k_seed_bound(const int* ms, long long n, int stride, unsigned long long* out) {
+  unsigned long long s = 0, mx = 0, neg = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const int m = ms[i];
+    if (m < 0) {
+      neg = 1;
+    } else {
+      s += (unsigned long long)(m / stride + 2);
+      mx = mx > (unsigned long long)m ? mx : (unsigned long long)m;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    s += __shfl_xor(s, o, 64);
+    const unsigned long long m2 = __shfl_xor(mx, o, 64);
+    mx = mx > m2 ? mx : m2;
+    neg |= __shfl_xor(neg, o, 64);
+  }
+  if (__lane_id() == 0) {
+    atomicAdd(&out[0], s);
+    atomicMax(&out[1], mx);
+    if (neg) atomicOr(&out[2], neg);
+  }
+}
+
+int launch_seed_bound(const int* ms, long long n, int stride, unsigned long long* out, hipStream_t st) {
+  launch_fill_u64(out, 3, 0, st);
+  long long grid = (n + 255) / 256;
+  if (grid > 1024) grid = 1024;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(k_seed_bound, dim3((unsigned)grid), dim3(256), 0, st, ms, n, stride, out);
+  return 0;
 }
 
 int launch_fill_u64(unsigned long long* p, long long n, unsigned long long v, hipStream_t st) {
@@ -272,13 +308,16 @@ __device__ __forceinline__ unsigned spread3(unsigned v) {  // 5 bits -> every th
 }
 
 __global__ void k_order_keys(const float4* pos, const int4* meta, const int4* meta2, const BlockDev* blocks,
-                             long long n, int bits, unsigned n_buckets, unsigned* key, unsigned* hist) {
+                             long long n, int bits, unsigned n_buckets, float h, float t_end, unsigned* key,
+                             unsigned* hist) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
     unsigned k = n_buckets - 1;
-    if (meta[i].z == ACTIVE) {
+    const int4 mt = meta[i];
+    const float4 p = pos[i];
+    // work = active particles whose next step starts inside the time window
+    if (mt.z == ACTIVE && fmaf((float)mt.x, h, p.w) < t_end) {
       const int blk = meta2[i].y;
       const BlockDev& B = blocks[blk];
-      const float4 p = pos[i];
       const float side = (float)(1 << bits);
       const float xs[3] = {p.x, p.y, p.z};
       unsigned c[3];
@@ -291,12 +330,15 @@ __global__ void k_order_keys(const float4* pos, const int4* meta, const int4* me
       k = (unsigned)blk * (1u << (3 * bits)) + (spread3(c[0]) | (spread3(c[1]) << 1) | (spread3(c[2]) << 2));
     }
     key[i] = k;
-    atomicAdd(&hist[k], 1u);
+    // idle particles (terminated, or outside the window) take no slot: only the
+    // first n_work entries of the order are read, and one shared bucket would
+    // serialise millions of atomics on one address
+    if (k != n_buckets - 1) atomicAdd(&hist[k], 1u);
   }
 }
 
 // Exclusive scan of hist[0..nb) into cursor[], one workgroup of 1024 threads;
-// n_work = number of particles outside the last (terminated) bucket.
+// n_work = number of particles outside the last (idle, never counted) bucket.
 __global__ void __launch_bounds__(1024) k_order_scan(const unsigned* hist, unsigned nb, unsigned* cursor,
                                                      unsigned* n_work) {
   __shared__ unsigned part[1024];
@@ -321,24 +363,26 @@ __global__ void __launch_bounds__(1024) k_order_scan(const unsigned* hist, unsig
   if (t == 1023) *n_work = part[1023] - hist[nb - 1];
 }
 
-__global__ void k_order_scatter(const unsigned* key, long long n, unsigned* cursor, int* order) {
+__global__ void k_order_scatter(const unsigned* key, long long n, unsigned idle, unsigned* cursor, int* order) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    const unsigned slot = atomicAdd(&cursor[key[i]], 1u);
+    const unsigned k = key[i];
+    if (k == idle) continue;
+    const unsigned slot = atomicAdd(&cursor[k], 1u);
     order[slot] = (int)i;
   }
 }
 
 int launch_work_order(const float4* pos, const int4* meta, const int4* meta2, const BlockDev* blocks, long long n,
-                      int bits, unsigned n_buckets, unsigned* key, unsigned* hist, unsigned* cursor, int* order,
-                      unsigned* n_work, hipStream_t st) {
+                      int bits, unsigned n_buckets, float h, float t_end, unsigned* key, unsigned* hist,
+                      unsigned* cursor, int* order, unsigned* n_work, hipStream_t st) {
   if (n <= 0) return 0;
   long long grid = (n + 255) / 256;
   if (grid > 16384) grid = 16384;
   launch_fill_u32(hist, n_buckets, 0u, st);
   hipLaunchKernelGGL(k_order_keys, dim3((unsigned)grid), dim3(256), 0, st, pos, meta, meta2, blocks, n, bits,
-                     n_buckets, key, hist);
+                     n_buckets, h, t_end, key, hist);
   hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(1024), 0, st, hist, n_buckets, cursor, n_work);
-  hipLaunchKernelGGL(k_order_scatter, dim3((unsigned)grid), dim3(256), 0, st, key, n, cursor, order);
+  hipLaunchKernelGGL(k_order_scatter, dim3((unsigned)grid), dim3(256), 0, st, key, n, n_buckets - 1, cursor, order);
   return 0;
 }
 

@@ -90,3 +90,31 @@ def test_calls_on_null_handle_fail_cleanly():
     assert lib.streami_fetch_lines(null, 0, 0, 0, None, None, 0, None, None, None, None) == S.E_ARG
     assert lib.streami_field_destroy(null) == S.OK
     assert b"NULL" in lib.streami_last_error()
+
+
+STRUCTS = [("streami_block_desc", "BlockDesc"), ("streami_field_opts", "FieldOpts"),
+           ("streami_seed_opts", "SeedOpts"), ("streami_advect_params", "AdvectParams"),
+           ("streami_stats", "Stats")]
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets that a C
+    compiler gives the header's struct (gcc on the header itself)."""
+    import subprocess
+    import paper_2606_02627_amd as S
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "streami.h"', "int main(void) {"]
+    for cname, pyname in STRUCTS:
+        lines.append(f'printf("{pyname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in getattr(S, pyname)._fields_:
+            lines.append(f'printf("{pyname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    for line in filter(None, out):
+        pyname, what, val = line.split()
+        cls = getattr(S, pyname)
+        got = ctypes.sizeof(cls) if what == "size" else getattr(cls, what).offset
+        assert got == int(val), (pyname, what, got, val)

@@ -39,8 +39,10 @@ def run(S, blocks, seeds_per_block, h, max_steps, dtype, layout=0, eps=1e-6, str
     for b, sd in enumerate(seeds_per_block):
         ms = max_steps[b] if isinstance(max_steps, list) else max_steps
         if isinstance(ms, np.ndarray):
+            tbs = adv.pop("t_births", None) if b == 0 else None
             f.seed(b, np.ascontiguousarray(sd, np.float32), max_steps=ms.astype(np.int32),
-                   record_stride=stride, t_birth=adv.pop("t_birth", 0.0) if b == 0 else 0.0)
+                   record_stride=stride, t_birth=adv.pop("t_birth", 0.0) if b == 0 else 0.0,
+                   t_births=None if tbs is None else np.ascontiguousarray(tbs, np.float32))
         else:
             f.seed(b, np.ascontiguousarray(sd, np.float32), default_max_steps=int(ms),
                    record_stride=stride)
@@ -180,6 +182,31 @@ def test_bit_identical_variants(S):
         np.testing.assert_array_equal(np.sort(got[2], order="id"), np.sort(base[2], order="id"))
 
 
+@pytest.mark.parametrize("dtype", [fg.BF16, fg.F16])
+@pytest.mark.parametrize("kind", ["steady", "unsteady", "batched"])
+def test_packed_16bit_cache_bit_identical(S, dtype, kind):
+    """16-bit nodes keep their cached corners packed (two per register) and widen them at
+    each sample; the results equal those of re-gathering every sample, bit for bit,
+    for one block, for time-blended slices and for several blocks in one launch."""
+    note("packed 16-bit cache", fg.DTYPE_NAMES[dtype], kind)
+    if kind == "batched":
+        blocks = [fg.turbulence_block(4, dims=d, fmt=dtype, sub=b, rank_grid=(1, 1, 1), rank_coord=(0, 0, 0),
+                                      n_slices=3, slice_dt=50.0)
+                  for b, d in enumerate([(20, 28, 16), (32, 12, 24), (16, 16, 30)])]
+    else:
+        ns = 4 if kind == "unsteady" else 1
+        blocks = [fg.turbulence_block(2, edge=28, fmt=dtype, rank_grid=(3, 3, 3), rank_coord=(1, 1, 1),
+                                      n_slices=ns, slice_dt=40.0)]
+    seeds = [fg.uniform_seeds(2, 1300 + 100 * b, (0, 0, 0), blk.dims, sub=20 + b) for b, blk in enumerate(blocks)]
+    base = run(S, blocks, seeds, 0.5, 300, dtype)
+    got = run(S, blocks, seeds, 0.5, 300, dtype, no_cell_cache=1)
+    assert got[3].steps == base[3].steps > 0
+    for b in range(len(blocks)):
+        for k in ("offsets", "xyz", "steps", "codes", "ids"):
+            np.testing.assert_array_equal(got[1][b][k], base[1][b][k])
+    np.testing.assert_array_equal(np.sort(got[2], order=["block", "id"]), np.sort(base[2], order=["block", "id"]))
+
+
 def test_graph_replays(S):
     """A captured launch replayed on a fresh particle set each time matches eager runs."""
     note("graph replays")
@@ -304,6 +331,108 @@ def test_unsteady_parity(S):
     dev, same = parity.global_compare(lines[0], ref, len(seeds))
     sens = parity.boundary_sensitive(ref, lines[0], dev, blk.lo, blk.hi, field=F)
     np.testing.assert_array_equal(lines[0]["codes"][~sens], ref["code"][~sens])
+
+
+def test_device_inputs_match_host_inputs(S):
+    """Seeds, ids, step limits and birth times given as device tensors (step limits reduced
+    on the device to size the log) give the same lines and outbox as host arrays, over
+    several seed calls into several blocks; a negative device step limit is rejected."""
+    import torch
+    note("device seed inputs")
+    blocks = [fg.turbulence_block(4, dims=d, fmt=fg.F16, sub=b, rank_grid=(1, 1, 1), rank_coord=(0, 0, 0))
+              for b, d in enumerate([(20, 24, 16), (16, 28, 20)])]
+    rng = np.random.default_rng(41)
+    calls = []
+    for c in range(5):
+        b = c % 2
+        n = int(rng.integers(1, 900))
+        calls.append((b, fg.uniform_seeds(4, n, (0, 0, 0), blocks[b].dims, sub=50 + c),
+                      rng.integers(0, 300, size=n).astype(np.int32), 3 if c == 3 else 1))
+    outs = []
+    for on_dev in (False, True):
+        f = S.Field(blocks, fg.F16)
+        for b, sd, ms, stride in calls:
+            if on_dev:
+                f.seed(b, torch.from_numpy(sd).cuda(), max_steps=torch.from_numpy(ms).cuda(), record_stride=stride)
+            else:
+                f.seed(b, sd, max_steps=ms, record_stride=stride)
+        f.advect(0.5)
+        outs.append(([f.lines(b) for b in range(2)], np.sort(f.outbox(), order=["block", "id"])))
+        if on_dev:
+            bad = torch.tensor([5, -1, 7], dtype=torch.int32, device="cuda")
+            with pytest.raises(S.StreamiError, match="negative"):
+                f.seed(0, torch.zeros(3, 3, device="cuda"), max_steps=bad)
+        f.close()
+    for b in range(2):
+        for k in ("offsets", "xyz", "steps", "codes", "ids"):
+            np.testing.assert_array_equal(outs[1][0][b][k], outs[0][0][b][k])
+    np.testing.assert_array_equal(outs[1][1], outs[0][1])
+
+
+def _streak_inputs():
+    blk = fg.turbulence_block(6, edge=24, fmt=fg.F16, n_slices=4, slice_dt=40.0,
+                              rank_grid=(1, 1, 1), rank_coord=(0, 0, 0), sub=1)
+    emitters = fg.uniform_seeds(6, 60, (0, 0, 0), (24, 24, 24), sub=31)
+    limits = np.random.default_rng(31).integers(40, 240, size=60)
+    pos, tb, lim, _ = fg.streakline_particles(emitters, limits, 10, 0.5)
+    return blk, pos, tb, lim
+
+
+def test_streaklines_parity(S):
+    """Streakline particles (60 emitters, one particle every 10 steps, each with its own
+    birth time) in a 4-slice FP16 block: local check at each vertex's own time against the
+    oracle, discrete results exact away from the boundary."""
+    note("streaklines")
+    blk, pos, tb, lim = _streak_inputs()
+    f = S.Field([blk], fg.F16)
+    f.seed(0, pos, max_steps=lim, t_births=tb)
+    f.advect(0.5)
+    L = f.lines(0)
+    f.close()
+    F = orc_field(blk)
+    ratio, npairs = parity.local_check(F, L, 0.5, 24.0, t_birth=tb)
+    assert ratio <= 1.0 and npairs > 0.5 * lim.sum(), (ratio, npairs)
+    ref = F.trace(pos, 0.5, lim, t_birth=tb)
+    dev, same = parity.global_compare(L, ref, len(pos))
+    sens = parity.boundary_sensitive(ref, L, dev, blk.lo, blk.hi, field=F)
+    assert (~sens).mean() > 0.8
+    np.testing.assert_array_equal(L["codes"][~sens], ref["code"][~sens])
+    np.testing.assert_array_equal(L["steps"][~sens], ref["steps"][~sens])
+
+
+@pytest.mark.parametrize("work_order", [0, 1])
+def test_time_windows_bit_identical(S, work_order):
+    """Advancing the streakline particles in time windows (t_end = 18.5, 37, ...) gives the
+    lines, steps, codes and outbox of one unbounded call, bit for bit; after the first
+    window every particle still ACTIVE stands at its first step time >= t_end."""
+    note("time windows, work order", work_order)
+    blk, pos, tb, lim = _streak_inputs()
+    h = 0.5
+    base = run(S, [blk], [pos], h, [lim], fg.F16, t_births=tb, work_order=work_order)
+    f = S.Field([blk], fg.F16)
+    f.seed(0, pos, max_steps=lim, t_births=tb)
+    W = 37 * h
+    t_end = W
+    st = f.advect(h, t_end=t_end, work_order=work_order)
+    L1 = f.lines(0)
+    act = L1["codes"] == S.ACTIVE
+    assert act.any() and (~act).any()
+    n = L1["steps"][act].astype(np.float64)
+    t_next = tb[act].astype(np.float64) + n * h  # exact: multiples of 0.5
+    assert (t_next >= t_end).all()
+    assert ((n == 0) | (t_next - h < t_end)).all()
+    for _ in range(100):
+        if st.active == 0:
+            break
+        t_end += W
+        st = f.advect(h, t_end=t_end, work_order=work_order)
+    assert st.active == 0
+    got = f.lines(0)
+    ob = f.outbox()
+    f.close()
+    for k in ("offsets", "xyz", "steps", "codes", "ids"):
+        np.testing.assert_array_equal(got[k], base[1][0][k])
+    np.testing.assert_array_equal(np.sort(ob, order="id"), np.sort(base[2], order="id"))
 
 
 # ---------------------------------------------------------------- full size (config 2)
