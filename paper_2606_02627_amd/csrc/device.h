@@ -61,7 +61,9 @@ enum Persist { PER_OUTBOX = 0, PER_LOG = 1, PER_LOG_REAL = 2, PER_N = 4 };
 // (x, y, z, particle index) plus the vertex's index within that particle's
 // line in a parallel array: two stores per vertex.  Fetching scatters records
 // to their CSR rows without sorting.
-constexpr int LOG_CHUNK = 1024;      // records per wave reservation
+// Records per wave reservation.  Every wave reserves from one counter, so the
+// chunk is large: at 1024 records the contended atomic cost a third of a pass.
+constexpr int LOG_CHUNK = 8192;
 constexpr unsigned LOG_UNUSED = 0xffffffffu;  // particle index of an unused record
 
 struct VertexLog {
