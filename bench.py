@@ -28,6 +28,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak, published
+# one network evaluation: 2 * (3*256 + 3*256*256 + 256*3) multiply-adds
+MLP_FLOPS_PER_EVAL = 2 * (3 * 256 + 3 * 256 * 256 + 256 * 3)
 
 
 def log(*a):
@@ -151,6 +154,22 @@ def surrogate_bench(args):
                residual_tol_cells=1e-3, residual_kind=1),
            run("surrogate-kind0-commutation-residual", h, steps, mode=S.MODE_SURROGATE, mlp=net,
                residual_tol_cells=1e-3, residual_kind=0)]
+    # the fused network kernel alone (k_mlp_infer), on the surrogate's input size
+    outn = torch.empty_like(d_seeds)
+    S.streami_mlp_forward(net, d_seeds, outn)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record()
+    for _ in range(reps):
+        S.streami_mlp_forward(net, d_seeds, outn)
+    e1.record()
+    torch.cuda.synchronize()
+    mlp_ms = e0.elapsed_time(e1) / reps
+    flops = n_inf * MLP_FLOPS_PER_EVAL
+    roof = {"bound": "mfma", "achieved": flops / mlp_ms / 1e9, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": flops / mlp_ms / 1e9 / MFMA_BF16_PEAK_TFLOPS, "traffic": None, "kernel": "k_mlp_infer",
+            "flops_per_eval": MLP_FLOPS_PER_EVAL, "evals_per_launch": n_inf, "mean_launch_ms": mlp_ms}
+    log(f"k_mlp_infer: {mlp_ms:.3f} ms for {n_inf} evaluations, {roof['achieved']:.1f} TFLOP/s")
     S.streami_mlp_destroy(net)
     plain = res[0]
     best_sur = max(res[2:], key=lambda r: r["equiv_steps_per_s"])
@@ -162,6 +181,7 @@ def surrogate_bench(args):
         "dtype": "bf16 MFMA (fp32 accumulate) + f32 RK4", "data": "synthetic",
         "config": {"workload": "surrogate-abc", "field": "ABC 32^3 periodic f32", "train_windows": n_train,
                    "epochs": epochs, "seeds": n_inf, "steps": steps, "h": h, "residual_tol_cells": 1e-3},
+        "roofline": roof,
         "speedup_vs_plain": best_sur["equiv_steps_per_s"] / plain["equiv_steps_per_s"],
         "runs": res, "train_seconds": t_train, "data_seconds": t_data,
         "final_loss": hist[-1]["loss"] if hist else None, "sigma": [float(v) for v in sigma],

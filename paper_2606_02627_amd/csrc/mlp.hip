@@ -222,6 +222,122 @@ __global__ void k_refresh_w(const float* W, int out, int in, int out_pad, int in
   }
 }
 
+// ---------------------------------------------------------------- fused inference
+// MFMA fragment order of the weights, built from the FP32 masters whenever
+// they change: layer l, output tile t (32 rows), k-step s, lane L, slot j
+// (8 BF16 = 16 bytes per lane) holds W_l[32 t + L % 32][kmap(l, s, L / 32, j)]:
+//   kmap(0, 0, hi, j) = 8 hi + j                    (the padded 3-vector input)
+//   kmap(l, s, hi, j) = 32 (s/2) + 16 (s%2) + 8 (j/4) + 4 hi + j%4   (l >= 1).
+// The second line is the order in which a layer's accumulators sit in a lane:
+// register r = 8q + j of output tile t holds feature 32t + 8(r/4) + 4hi + r%4
+// of the lane's particle, which is slot j of k-step 2t + q.  With the input
+// dimension of every later layer permuted the same way, a layer's outputs are
+// the next layer's B operand in place, with no exchange between lanes.
+constexpr int FR_TILES[NL] = {8, 8, 8, 8, 1};
+constexpr int FR_KSTEPS[NL] = {1, 16, 16, 16, 16};
+constexpr int FR_OFF[NL + 1] = {0, 512, 8704, 16896, 25088, 26112};  // 16-byte units
+
+__host__ __device__ constexpr int frag_k(int l, int s, int hi, int j) {
+  return l == 0 ? 8 * hi + j : 32 * (s / 2) + 16 * (s % 2) + 8 * (j / 4) + 4 * hi + j % 4;
+}
+
+struct FragArgs {
+  const float* W[NL];
+};
+
+__global__ void k_frag_w(FragArgs a, unsigned short* frag) {
+  const int total = FR_OFF[NL] * 8;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    const int u = e >> 3, j = e & 7;
+    int l = 0;
+    while (u >= FR_OFF[l + 1]) ++l;
+    const int r = u - FR_OFF[l];
+    const int L = r & 63, ts = r >> 6, s = ts % FR_KSTEPS[l], t = ts / FR_KSTEPS[l];
+    const int row = 32 * t + (L & 31), k = frag_k(l, s, L >> 5, j);
+    frag[e] = (row < WID[l + 1] && k < WID[l]) ? f2bf(a.W[l][row * WID[l] + k]) : (unsigned short)0;
+  }
+}
+
+typedef __attribute__((__vector_size__(8 * sizeof(float)))) float f32x8;
+
+__device__ __forceinline__ float silu_fast(float z) {
+  return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+}
+
+struct InferArgs {
+  const uint4* frag;
+  const float* b[NL];
+  const float* xyz;
+  int xstride;
+  long long n;
+  float period;
+  float sigma[3];
+  float* out;
+};
+
+// One workgroup = 4 waves = 128 particles; each layer's weight fragments
+// (<= 128 KB) and biases are staged in LDS and shared by the 4 waves; each
+// wave keeps its 32 particles' activations in registers as the B operand and
+// the 8 output tiles' accumulators (128 registers) as independent MFMA chains.
+constexpr int INFER_WAVES = 4;
+__global__ void __launch_bounds__(64 * INFER_WAVES) k_mlp_infer(InferArgs a) {
+  __shared__ uint4 wl[8192];
+  __shared__ float bl[256];
+  const int tid = threadIdx.x, lane = tid & 63, hi = lane >> 5;
+  const long long p = (long long)blockIdx.x * (32 * INFER_WAVES) + (tid >> 6) * 32 + (lane & 31);
+  const bool live = p < a.n;
+  bf16x8 B[16];
+  {
+    f32x8 x = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (live && hi == 0)
+      for (int c = 0; c < 3; ++c) {
+        const float v = a.xyz[p * a.xstride + c];
+        const float w = v - a.period * floorf(v / a.period);
+        x[c] = 2.0f * (w / a.period) - 1.0f;
+      }
+    B[0] = __builtin_convertvector(x, bf16x8);
+    const bf16x8 zero = {};
+#pragma unroll
+    for (int s = 1; s < 16; ++s) B[s] = zero;  // layer 0 reads B[0] only
+  }
+  f32x16 acc[8];
+#pragma unroll
+  for (int l = 0; l < NL; ++l) {
+    const int tiles = FR_TILES[l], ks = FR_KSTEPS[l];
+    __syncthreads();  // every wave is done with the previous layer's LDS
+    for (int i = tid; i < tiles * ks * 64; i += 64 * INFER_WAVES) wl[i] = a.frag[FR_OFF[l] + i];
+    for (int i = tid; i < 256; i += 64 * INFER_WAVES) bl[i] = i < WID[l + 1] ? a.b[l][i] : 0.0f;
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < tiles; ++t)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[t][r] = 0.0f;
+#pragma unroll
+    for (int s = 0; s < ks; ++s)
+#pragma unroll
+      for (int t = 0; t < tiles; ++t) {
+        const uint4 w = wl[(t * ks + s) * 64 + lane];
+        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, w), B[s], acc[t], 0, 0, 0);
+      }
+    if (l < NL - 1) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          f32x8 h;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int r = 8 * q + j;
+            h[j] = silu_fast(acc[t][r] + bl[32 * t + 8 * (r / 4) + 4 * hi + r % 4]);
+          }
+          B[2 * t + q] = __builtin_convertvector(h, bf16x8);
+        }
+    } else if (live && hi == 0) {
+      for (int c = 0; c < 3; ++c) a.out[p * 3 + c] = a.sigma[c] * (acc[0][c] + bl[c]);
+    }
+  }
+}
+
 static int grid_for(long long n) {
   long long g = (n + 255) / 256;
   if (g > 16384) g = 16384;
@@ -267,6 +383,7 @@ struct streami_mlp_s {
   unsigned short* WTb[NL] = {};  // BF16 [in_pad x out_pad]
   float* gW[NL] = {};            // FP32 [out_pad x in_pad]
   float* gb[NL] = {};            // FP32 [out_pad]
+  unsigned short* frag = nullptr;  // BF16 weights in MFMA fragment order (fused inference)
   long long t = 0;               // Adam step count
   // batch workspace (grown on demand)
   long long cap = 0;
@@ -337,6 +454,9 @@ void refresh_bf16(streami_mlp_s* m) {
   for (int l = 0; l < NL; ++l)
     hipLaunchKernelGGL(k_refresh_w, dim3(grid_for((long long)OUT_PAD[l] * IN_PAD[l])), dim3(256), 0, m->stream, m->W[l],
                        WID[l + 1], WID[l], OUT_PAD[l], IN_PAD[l], m->Wb[l], m->WTb[l]);
+  FragArgs fa;
+  for (int l = 0; l < NL; ++l) fa.W[l] = m->W[l];
+  hipLaunchKernelGGL(k_frag_w, dim3(grid_for((long long)FR_OFF[NL] * 8)), dim3(256), 0, m->stream, fa, m->frag);
 }
 
 // Forward over Bp rows (n real); leaves Z/H for backprop; writes out (n x 3) if given.
@@ -377,17 +497,23 @@ void backward(streami_mlp_s* m, long long Bp) {
 
 namespace streami {
 // Network output for n rows of positions spaced xstride floats apart (3 for
-// packed xyz, 4 for the particle float4 array), in chunks of 2^18 rows.
+// packed xyz, 4 for the particle float4 array): one fused launch, no workspace.
 int mlp_forward_rows(streami_mlp m, const float* xyz, int xstride, long long n, float* out, hipStream_t st) {
-  const long long chunk = 1LL << 18;
+  if (n <= 0) return STREAMI_OK;
   if (st != m->stream) MHIP(hipStreamSynchronize(m->stream));
-  for (long long s = 0; s < n; s += chunk) {
-    const long long k = std::min<long long>(chunk, n - s);
-    const long long Bp = (k + 31) / 32 * 32;
-    int rc = ensure_batch(m, Bp);
-    if (rc) return rc;
-    forward(m, xyz + (size_t)xstride * s, xstride, k, Bp, out + 3 * s, nullptr, false, st);
-  }
+  InferArgs a;
+  a.frag = reinterpret_cast<const uint4*>(m->frag);
+  for (int l = 0; l < NL; ++l) a.b[l] = m->b[l];
+  a.xyz = xyz;
+  a.xstride = xstride;
+  a.n = n;
+  a.period = m->period;
+  for (int c = 0; c < 3; ++c) a.sigma[c] = m->sigma[c];
+  a.out = out;
+  const long long per = 32 * INFER_WAVES;
+  const long long grid = (n + per - 1) / per;
+  if (grid > 0x7fffffffLL) return mfail(STREAMI_E_ARG, "too many rows for one launch");
+  hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)grid), dim3(64 * INFER_WAVES), 0, st, a);
   MHIP(hipGetLastError());
   return STREAMI_OK;
 }
@@ -421,6 +547,7 @@ int streami_mlp_create(const float* params, const float* sigma, float period, vo
     (void)hipMemsetAsync(m->vb[l], 0, nb * 4, m->stream);
   }
   if (!rc) rc = dalloc(m, (void**)&m->loss, 4);
+  if (!rc) rc = dalloc(m, (void**)&m->frag, (size_t)FR_OFF[NL] * 16);
   if (rc) {
     streami_mlp_destroy(m);
     return rc;
