@@ -162,8 +162,8 @@ typedef struct {
   streami_mlp mlp;          /* trained network for SURROGATE mode, else NULL */
   float residual_tol_cells; /* SURROGATE: accept a jump when its residual <= tol (cells) */
   int32_t residual_kind;    /* SURROGATE: 0 commutation residual, 1 one big RK4 step */
-  int32_t waves_per_cu;     /* launch shape; 0 = library default / tuned value */
-  int32_t refill_threshold; /* free lanes that trigger a work-queue refill; 0 = default */
+  int32_t waves_per_cu;     /* launch shape; 0 = library default (16 up to 2^21 particles, else 32) */
+  int32_t refill_threshold; /* free lanes that trigger a work-queue refill; 0 = default (1) */
   int32_t use_graph;        /* 1: capture the launch sequence in a hipGraph and replay it */
   int32_t no_cell_cache;    /* 1: re-gather a cell's corners at every sample (A/B measurement;
                                results are bit-identical either way) */

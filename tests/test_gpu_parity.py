@@ -469,3 +469,75 @@ def test_turbulence_256_full_size_sampled(S):
     out = np.maximum(np.maximum(-ob["pos"], ob["pos"] - 256), 0).max(axis=1)
     assert out.max() <= 0.5 + 1e-4
     assert (ob["dest"] >= 0).all() and (ob["dest"] != 1 + 4 * (1 + 4 * 1)).all()
+
+
+@pytest.mark.parametrize("dtype", [fg.BF16, fg.F16])
+def test_turbulence_512_16bit_full_size_sampled(S, dtype):
+    """The 16-bit workload and launch as benchmarked: 512^3 block + ghost stored in BF16/FP16,
+    4M seeds in 64 Gaussian blobs, h=0.5, up to 4000 steps, every 8th vertex kept.  Sampled
+    outputs (4 x 512 particles from 4 blobs) against the oracle on the same stored nodes; the
+    per-step rule on 512 blob seeds recorded at stride 1; counts and invariants on all."""
+    note("turbulence 512^3 x 4M full size", fg.DTYPE_NAMES[dtype])
+    blk = fg.turbulence_block(3, edge=512, fmt=dtype)
+    seeds = fg.blob_seeds(3, 64, 65536, 512.0, 24.0, 8.0)
+    f = S.Field([blk], dtype)
+    f.seed(0, seeds, default_max_steps=4000, record_stride=8)
+    st = f.advect(0.5)
+    F = orc_field(blk)
+    for b in (0, 21, 42, 63):
+        first, count = b * 65536 + 1000, 512
+        L = f.lines(0, first, count)
+        ref = F.trace(seeds[first:first + count], 0.5, 4000, stride=8)
+        dev, same = parity.global_compare(L, ref, count)
+        sens = parity.boundary_sensitive(ref, L, dev, blk.lo, blk.hi, field=F)
+        # chaotic 4000-step lines: FP32 vs FP64 deviation grows, and with it the margin of
+        # boundary sensitivity; the exact comparison must still cover a quarter of the sample
+        assert (~sens).mean() >= 0.25, (~sens).mean()
+        np.testing.assert_array_equal(L["codes"][~sens], ref["code"][~sens])
+        np.testing.assert_array_equal(L["steps"][~sens], ref["steps"][~sens])
+        note(f"blob {b}: {(dev <= 2e-3 * 512).mean():.3f} within 2e-3 extent, sensitive {sens.mean():.3f}")
+    assert st.active == 0 and sum(st.terminated) == len(seeds)
+    ob = f.outbox(cap=len(seeds))
+    assert len(ob) == st.terminated[S.EXIT] + st.terminated[S.HALO_MISS] and st.terminated[S.HALO_MISS] == 0
+    assert len(np.unique(ob["id"])) == len(ob)
+    f.close()
+    # the per-step rule needs consecutive vertices: a stride-1 run of 512 blob seeds
+    g = S.Field([blk], dtype)
+    sub = seeds[7 * 65536:7 * 65536 + 512]
+    g.seed(0, sub, default_max_steps=4000)
+    g.advect(0.5)
+    ratio, npairs = parity.local_check(F, g.lines(0), 0.5, 512.0)
+    assert ratio <= 1.0 and npairs > 512 * 100, (ratio, npairs)
+    g.close()
+
+
+def test_batched96_full_size_sampled(S):
+    """The batched workload and launch as benchmarked: 96 FP16 blocks of uneven shape, 1.33M
+    seeds with per-seed limits, one graph-captured persistent launch.  Sampled outputs (256
+    particles of each of 6 blocks) against the oracle run on that block alone; counts and
+    invariants on all."""
+    import torch
+    note("batched 96 blocks full size")
+    blocks, seeds, limits = fg.batched_blocks(n_blocks=96, fmt=fg.F16)
+    f = S.Field(blocks, fg.F16)
+    for b in range(96):
+        f.seed(b, torch.from_numpy(seeds[b]).cuda(), max_steps=torch.from_numpy(limits[b]).cuda())
+    st = f.advect(0.5, use_graph=1)
+    n = sum(len(s) for s in seeds)
+    assert st.active == 0 and sum(st.terminated) == n
+    for b in (0, 17, 35, 52, 70, 95):
+        k = min(256, len(seeds[b]))
+        L = f.lines(b, 0, k)
+        F = orc_field(blocks[b])
+        ratio, _ = parity.local_check(F, L, 0.5, blocks[b].extent)
+        assert ratio <= 1.0, (b, ratio)
+        ref = F.trace(seeds[b][:k], 0.5, limits[b][:k])
+        dev, same = parity.global_compare(L, ref, k)
+        sens = parity.boundary_sensitive(ref, L, dev, blocks[b].lo, blocks[b].hi, field=F)
+        np.testing.assert_array_equal(L["codes"][~sens], ref["code"][~sens])
+        np.testing.assert_array_equal(L["steps"][~sens], ref["steps"][~sens])
+    ob = f.outbox(cap=n)
+    assert len(ob) == st.terminated[S.EXIT] + st.terminated[S.HALO_MISS]
+    assert set(np.unique(ob["block"])) <= set(range(96))
+    assert len(np.unique(ob["id"])) == len(ob)
+    f.close()
