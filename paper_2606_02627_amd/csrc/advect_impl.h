@@ -114,7 +114,8 @@ __device__ __forceinline__ void locate_axis(float x, float scale, float offs, fl
     i1 = (w + 1.0f >= fn) ? 0 : i0 + 1;
   } else {
     ok = ok && (s == __builtin_amdgcn_fmed3f(s, 0.0f, fn - 1.0f));
-    const float fl = fmaxf(fminf(floorf(s), fn - 2.0f), 0.0f);
+    // fn >= 2 (validated), so the clamp to [0, fn-2] is one med3
+    const float fl = __builtin_amdgcn_fmed3f(floorf(s), 0.0f, fn - 2.0f);
     f = s - fl;
     i0 = (int)fl;
     i1 = i0 + 1;
