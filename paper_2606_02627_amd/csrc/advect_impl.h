@@ -11,17 +11,20 @@
 // gfx950 design (measured: the kernel is VALU-issue bound once the field is
 // cached, so the per-step instruction count is what matters):
 //  * one lane per particle, persistent grid; a wave refills its free lanes
-//    from a global work counter with one atomic per refill (ballot + mbcnt),
-//    so long and short trajectories share waves without idling;
-//  * each lane keeps the 8 corner vectors of the cell it sampled last in
-//    registers; a particle moves ~0.1-0.3 cells per step, so most of the four
-//    samples of a step re-use them and only a cell change issues the gather;
+//    from per-XCD work queues over a spatially sorted order, with one atomic
+//    per refill (ballot + mbcnt), so long and short trajectories share waves;
+//  * each lane keeps the cell it sampled last in registers -- for steady
+//    fields its trilinear coefficients in monomial form, for unsteady 16-bit
+//    fields the packed corners of the two bracketing slices; a particle moves
+//    ~0.1-0.3 cells per step, so most samples re-use them and only a cell
+//    change issues the gather;
 //  * addresses are 32-bit byte offsets from a per-block base (uniform for a
 //    single block), the byte offset of the cell's first corner doubles as the
-//    cache key, and cell location is branch-free (med3 domain test);
+//    cache key, and cell location is branch-free (med3 domain test and clamp);
 //  * nodes are FP32 (12 B) or FP16/BF16 padded to 8 B, so a node is one
 //    aligned load; 16-bit values are widened in registers, all arithmetic FP32;
-//  * the outbox append is wave-aggregated (one atomic per wave and event).
+//  * vertices go to a log in wave-aggregated runs inside 8192-record chunks,
+//    outbox records with one atomic per wave and event.
 #pragma once
 #include <type_traits>
 

@@ -293,9 +293,10 @@ int launch_count_codes(const int4* meta, long long n, unsigned long long* counts
 namespace streami {
 
 // ---------------------------------------------------------------- work order
-// Active particles are bucketed by (block, Morton index of a coarse brick of
-// their position) so that lanes of a wave and waves of an XCD work on nearby
-// cells; terminated particles go to the last bucket and are not processed.
+// Active particles whose next step lies inside the time window are bucketed by
+// (block, Morton index of a coarse brick of their position) so that lanes of a
+// wave and waves of an XCD work on nearby cells; the others (terminated, or
+// waiting for a later window) get the last key and no slot in the order.
 // The order only decides which lane advances which particle, never what is
 // computed, so results do not depend on it.
 
