@@ -47,11 +47,21 @@ WORKLOADS = {
 }
 
 
+def code_text(src: str) -> str:
+    """Source text without comments and whitespace: what the compiler sees of it."""
+    import re
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    return re.sub(r"\s+", "", src)
+
+
 def kernel_source_hash() -> str:
+    """Hash of the advection kernel's code (comments and whitespace ignored): a traffic
+    measurement stays attached to the kernel it was taken on."""
     h = hashlib.sha1()
     for f in ("advect_impl.h", "device.h"):
-        with open(os.path.join(ROOT, "paper_2606_02627_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2606_02627_amd", "csrc", f)) as fh:
+            h.update(code_text(fh.read()).encode())
     return h.hexdigest()[:12]
 
 
