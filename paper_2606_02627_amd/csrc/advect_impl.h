@@ -427,7 +427,10 @@ __device__ __forceinline__ int rk4_step(S& smp, const BlockDev& B, const char* b
   return ACTIVE;
 }
 
-// destinationID(): flat macrocell id of x, -1 outside the macrocell grid.
+// destinationID(): flat macrocell id of x, -1 outside the macrocell grid.  The
+// advection kernel passes the block descriptor in memory (LDS or global), not
+// its register copy: the rank-grid fields are read only at an exit, and keeping
+// them in scalar registers for the whole loop would spill others.
 __device__ __forceinline__ int dest_id(const BlockDev& B, float3 x) {
   int r0 = B.rcoord[0] + (int)floorf((x.x - B.lo[0]) * B.inv_ext[0]);
   int r1 = B.rcoord[1] + (int)floorf((x.y - B.lo[1]) * B.inv_ext[1]);
@@ -462,6 +465,10 @@ extern __shared__ BlockDev g_lds_blocks[];
 
 template <int FMT, int LAYOUT, bool PERIODIC, int MODE, bool BATCHED>
 __device__ __forceinline__ void advect_body(const AdvectArgs& A) {
+  // The log and outbox counters are addressed from A.ctr (they follow the
+  // per-call counters), and the rank-grid fields are read from memory at an
+  // exit: every 64-bit pointer or field kept in scalar registers for the whole
+  // loop spills others, and each spill reload is a VALU instruction.
   constexpr unsigned NB = NodeBytes<FMT>::v;
   BlockDev B0;
   const char* base0 = nullptr;
@@ -509,7 +516,7 @@ __device__ __forceinline__ void advect_body(const AdvectArgs& A) {
           const long long my = A.order ? (long long)A.order[slot] : slot;
           const int4 mt = A.meta[my];
           const float4 ps = A.pos[my];
-          if (mt.z == ACTIVE && fmaf((float)mt.x, A.h, ps.w) < A.t_end) {
+          if (mt.z == ACTIVE && (!A.windowed || fmaf((float)mt.x, A.h, ps.w) < A.t_end)) {
             p = (int)my;
             P = make_float3(ps.x, ps.y, ps.z);
             tb = ps.w;
@@ -527,16 +534,17 @@ __device__ __forceinline__ void advect_body(const AdvectArgs& A) {
     }
     if (queue_done && __ballot(p < 0) == all) break;
 
+    // an outbox record takes P: the new position after an exit, the unchanged
+    // one after a halo miss
     int term = ACTIVE;
     int dest = -1;
-    float3 opos = P;
     bool rec = false;  // a vertex (P, index nv) to append this iteration
     if (p >= 0) {
       const BlockDev& B = BATCHED ? g_lds_blocks[blk] : B0;
       const float t = fmaf((float)n, A.h, tb);
       if (n >= m) {
         term = MAX_STEPS;
-      } else if (!(t < A.t_end)) {
+      } else if (A.windowed && !(t < A.t_end)) {
         left = 0;  // the window ends here: park the particle, still ACTIVE
       } else {
         float3 P1, fail;
@@ -552,17 +560,13 @@ __device__ __forceinline__ void advect_body(const AdvectArgs& A) {
           rec = out || n == m || on_stride;
           if (out) {
             term = EXIT;
-            dest = dest_id(B, P);
-            opos = P;
+            dest = dest_id(BATCHED ? g_lds_blocks[blk] : A.blocks[0], P);
           } else if (n == m) {
             term = MAX_STEPS;
           }
         } else {
           term = st;
-          if (st == HALO_MISS) {
-            dest = dest_id(B, fail);
-            opos = P;
-          }
+          if (st == HALO_MISS) dest = dest_id(BATCHED ? g_lds_blocks[blk] : A.blocks[0], fail);
           rec = until_rec != stride;  // the final vertex is always kept
         }
       }
@@ -575,7 +579,7 @@ __device__ __forceinline__ void advect_body(const AdvectArgs& A) {
         // mark the unused tail of the old chunk (< 64 records) so fetches skip it
         if (log_ok && cpos + lane < cend) A.log.v[cpos + lane] = make_float4(0.f, 0.f, 0.f, __uint_as_float(LOG_UNUSED));
         unsigned long long nb = 0;
-        if (lane == 0) nb = atomicAdd(A.log.count, (unsigned long long)LOG_CHUNK);
+        if (lane == 0) nb = atomicAdd(A.ctr + CTR_N + PER_LOG, (unsigned long long)LOG_CHUNK);
         nb = uniform_u64(__shfl(nb, 0, 64));
         if (nb + LOG_CHUNK > (unsigned long long)A.log.cap) {
           log_ok = false;  // cannot happen when the host sized the log; never write past it
@@ -605,12 +609,12 @@ __device__ __forceinline__ void advect_body(const AdvectArgs& A) {
     if (em != 0) {
       const int leader = __ffsll((long long)em) - 1;
       unsigned long long obase = 0;
-      if (lane == leader) obase = atomicAdd(A.outbox_count, (unsigned long long)__popcll(em));
+      if (lane == leader) obase = atomicAdd(A.ctr + CTR_N + PER_OUTBOX, (unsigned long long)__popcll(em));
       obase = __shfl(obase, leader, 64);
       if (emit) {
         OutRec r;
         r.id = A.ids[p];
-        r.pos[0] = opos.x; r.pos[1] = opos.y; r.pos[2] = opos.z;
+        r.pos[0] = P.x; r.pos[1] = P.y; r.pos[2] = P.z;
         r.steps = n;
         r.dest = dest;
         r.code = (short)term;
@@ -633,7 +637,7 @@ __device__ __forceinline__ void advect_body(const AdvectArgs& A) {
     if (s) atomicAdd(&A.ctr[CTR_STEPS], s);
     if (v) {
       atomicAdd(&A.ctr[CTR_VERTS], v);
-      atomicAdd(A.log.real, v);
+      atomicAdd(A.ctr + CTR_N + PER_LOG_REAL, v);
     }
   }
 }

@@ -642,6 +642,7 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
   // faster than at 16; 16 waves/CU suit ~4 particles per lane (1M seeds),
   // 32 waves/CU suit larger sets (4M seeds: 16 waves/CU is 9% slower)
   a.refill = p->refill_threshold > 0 ? p->refill_threshold : 1;
+  a.windowed = p->use_t_end;
   a.t_end = p->use_t_end ? p->t_end : INFINITY;
   const int wpc = p->waves_per_cu > 0 ? p->waves_per_cu : (f->n_particles <= (1LL << 21) ? 16 : 32);
   long long grid = (long long)f->n_cu * wpc / 4;

@@ -99,7 +99,8 @@ struct AdvectArgs {
   float eps2;               // stagnation_eps^2
   int budget;               // 0 = unlimited
   int refill;               // free lanes that trigger a refill
-  float t_end;              // a step starts only at t < t_end (+inf: no window)
+  float t_end;              // with `windowed`, a step starts only at t < t_end
+  int windowed;             // 0: no time window (the time is then only the sampler's)
 };
 
 // One surrogate jump (16 plain steps) for every active particle of a single
