@@ -428,6 +428,8 @@ int streami_field_create(const streami_block_desc* blocks, int32_t n_blocks, int
   for (int i = 0; i < n_blocks; ++i) {
     int rc = validate_desc(blocks[i], i);
     if (rc) return rc;
+    // the addressing limits depend only on the shapes: refuse before any device work
+    if ((rc = check_geometry(make_dev(blocks[i], layout, dtype, 0), i))) return rc;
   }
   streami_field_s* f = new (std::nothrow) streami_field_s();
   if (!f) return fail(STREAMI_E_NOMEM, "host allocation failed");
@@ -446,7 +448,6 @@ int streami_field_create(const streami_block_desc* blocks, int32_t n_blocks, int
     HostBlock& hb = f->blocks[i];
     hb.desc = blocks[i];
     hb.dev = make_dev(blocks[i], layout, dtype, base);
-    if (int rc0 = check_geometry(hb.dev, i)) return cleanup(rc0);
     hb.nx = hb.dev.nst[0];
     hb.ny = hb.dev.nst[1];
     hb.nz = hb.dev.nst[2];

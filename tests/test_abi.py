@@ -118,3 +118,29 @@ def test_binding_structs_match_the_header_layout(tmp_path):
         cls = getattr(S, pyname)
         got = ctypes.sizeof(cls) if what == "size" else getattr(cls, what).offset
         assert got == int(val), (pyname, what, got, val)
+
+
+@pytest.mark.parametrize("dims,dtype,msg", [
+    ((600, 600, 600), "f32", "2 GiB"),      # 602^3 nodes x 12 B: one slice > 2 GiB
+    ((1500, 1500, 2), "f32", "16 MiB"),     # a z plane of 1502^2 x 12 B > 16 MiB
+    ((1600, 1600, 2), "f16", "16 MiB"),     # 1602^2 x 8 B (16-bit nodes padded to 8 B)
+])
+def test_field_create_rejects_shapes_beyond_the_addressing_limits(dims, dtype, msg):
+    """The kernels address a slice with 32-bit byte offsets and 24-bit row/plane products;
+    shapes beyond that are refused before any device work."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("checked before device work; on a GPU machine a missed check would ingest")
+    import paper_2606_02627_amd as S
+    d = _desc(dims=dims)
+    fmt = {"f32": S.F32, "f16": S.F16}[dtype]
+    with pytest.raises(S.StreamiError) as e:
+        S.streami_field_create([d], fmt)
+    assert e.value.code == S.E_UNSUPPORTED and msg in str(e.value)
+
+
+def test_field_create_rejects_too_many_blocks():
+    import paper_2606_02627_amd as S
+    with pytest.raises(S.StreamiError) as e:
+        S.streami_field_create([_desc()] * 449, S.F32)
+    assert e.value.code == S.E_UNSUPPORTED and "448" in str(e.value)

@@ -541,3 +541,33 @@ def test_batched96_full_size_sampled(S):
     assert set(np.unique(ob["block"])) <= set(range(96))
     assert len(np.unique(ob["id"])) == len(ob)
     f.close()
+
+
+def test_argument_errors_on_a_live_handle(S):
+    """Errors are reported as codes with a message and leave the handle usable: advect before
+    seeding, a NaN window end, an out-of-range launch shape, a window in surrogate mode,
+    negative step limits; an empty seed batch is a no-op."""
+    note("argument errors")
+    blk = fg.turbulence_block(2, edge=16, rank_grid=(1, 1, 1), rank_coord=(0, 0, 0))
+    f = S.Field([blk], fg.F32)
+    with pytest.raises(S.StreamiError) as e:
+        f.advect(0.5)
+    assert e.value.code == S.E_STATE
+    f.seed(0, np.zeros((0, 3), np.float32), default_max_steps=10)
+    with pytest.raises(S.StreamiError) as e:
+        f.seed(0, np.ones((2, 3), np.float32), max_steps=np.array([3, -1], np.int32))
+    assert e.value.code == S.E_ARG and "max_steps" in str(e.value)
+    seeds = fg.uniform_seeds(2, 300, (0, 0, 0), (16, 16, 16))
+    f.seed(0, seeds, default_max_steps=50)
+    for kw, code in ((dict(t_end=float("nan")), S.E_ARG), (dict(waves_per_cu=65), S.E_ARG),
+                     (dict(refill_threshold=-1), S.E_ARG), (dict(work_order=2), S.E_ARG),
+                     (dict(mode=S.MODE_SURROGATE, t_end=1.0), S.E_UNSUPPORTED)):
+        with pytest.raises(S.StreamiError) as e:
+            f.advect(0.5, **kw)
+        assert e.value.code == code, (kw, e.value)
+    with pytest.raises(S.StreamiError) as e:
+        f.advect(float("inf"))
+    assert e.value.code == S.E_ARG
+    st = f.advect(0.5)  # still usable after every refusal
+    assert st.active == 0 and st.steps == int(f.lines(0)["steps"].sum()) > 0
+    f.close()

@@ -115,3 +115,37 @@ def test_trained_surrogate_endpoint_error_and_acceptance(S, trained):
         note(f"kind {kind}: acceptance {acc:.3f}, endpoint error / extent median {np.median(err):.2e} "
              f"p90 {np.quantile(err, 0.9):.2e} max {err.max():.2e}")
         assert np.isfinite(err).all()
+
+
+def test_full_size_properties(S, trained):
+    """The surrogate workload's size and launch: 2^22 ABC seeds, 2000 steps (125 jumps), every
+    16th vertex kept.  Tolerance 0 reproduces plain RK4 exactly (step and termination counts of
+    all particles, the lines of a sampled range); an infinite tolerance takes every jump, and the
+    sampled range ends at the network displacement applied 125 times."""
+    import torch
+    from paper_2606_02627_amd import surrogate
+    blk, net = trained[0], trained[4]
+    n, first, count = 1 << 22, 777, 4096
+    note("surrogate full size")
+    d_seeds = torch.from_numpy(fg.uniform_seeds(5, n, (0, 0, 0), (2 * np.pi,) * 3, sub=21)).cuda()
+
+    def run(**kw):
+        f = S.Field([blk], S.F32)
+        f.seed(0, d_seeds, default_max_steps=2000, record_stride=16)
+        st = f.advect(H, **kw)
+        L = f.lines(0, first, count)
+        f.close()
+        return st, L
+
+    st_p, Lp = run()
+    st_0, L0 = run(mode=S.MODE_SURROGATE, mlp=net, residual_tol_cells=0.0, residual_kind=1)
+    assert st_0.surrogate_accepted == 0 and st_0.steps == st_p.steps == n * 2000
+    assert list(st_0.terminated) == list(st_p.terminated)
+    for k in ("offsets", "xyz", "steps", "codes", "ids"):
+        np.testing.assert_array_equal(L0[k], Lp[k])
+    st_i, Li = run(mode=S.MODE_SURROGATE, mlp=net, residual_tol_cells=3e38, residual_kind=1)
+    assert st_i.surrogate_accepted == n * 125 and st_i.surrogate_fallback == 0
+    x = d_seeds[first:first + count].clone()
+    for _ in range(125):
+        x = x + surrogate.predict(net, x)
+    np.testing.assert_array_equal(Li["xyz"][Li["offsets"][1:] - 1], x.cpu().numpy())
