@@ -121,8 +121,12 @@ typedef struct {
  * caller keeps ownership of `nodes`); the copy is complete when this returns.
  * hip_stream: the hipStream_t all later work of this handle is enqueued on
  * (NULL = the default stream).  opts may be NULL.
- * Errors: E_ARG for an invalid descriptor (the message names the field),
- * E_NOMEM, E_DEVICE.  *out is set only on success.
+ * Errors: E_ARG for an invalid descriptor (the message names the field);
+ * E_UNSUPPORTED for more than 448 blocks, a PERIODIC block in a handle with
+ * several blocks or time slices, or a block whose time slice exceeds 2 GiB or
+ * whose z plane of nodes exceeds 16 MiB (the kernels use 32-bit offsets;
+ * split such a block); E_NOMEM, E_DEVICE.  *out is set only
+ * on success.
  */
 int streami_field_create(const streami_block_desc* blocks, int32_t n_blocks, int32_t dtype,
                          const streami_field_opts* opts, void* hip_stream, streami_field* out);
@@ -143,12 +147,14 @@ typedef struct {
 /*
  * Append n particles to block `block`.  xyz: n*3 FP32 positions; ids: n
  * unique ids or NULL (then ids continue a per-handle counter from 0);
- * max_steps: n per-particle limits or NULL.  Each particle reserves
- * max_steps/record_stride + 2 vertices of 12 bytes in the handle's line
- * buffer.  The seed position is vertex 0; a seed outside the block's owned
- * bounds (BLOCK boundary) terminates at once with code EXIT and 0 steps and
- * goes to the outbox.  Particles of a block keep their seed order for
- * streami_fetch_lines().  Errors: E_ARG, E_NOMEM, E_DEVICE.
+ * max_steps: n per-particle limits (>= 0) or NULL.  Each particle reserves
+ * room for max_steps/record_stride + 2 vertex records (20 bytes each) in the
+ * handle's vertex log.  The seed position is vertex 0; a seed outside the
+ * block's owned bounds (BLOCK boundary) terminates at once with code EXIT and
+ * 0 steps and goes to the outbox.  Particles of a block keep their seed order
+ * for streami_fetch_lines().  Step limits on the device are reduced on the
+ * device (24 bytes come back); host limits are read directly.
+ * Errors: E_ARG (bad block, opts or a negative limit), E_NOMEM, E_DEVICE.
  */
 int streami_seed(streami_field f, int32_t block, const float* xyz, const uint64_t* ids,
                  const int32_t* max_steps, int64_t n, const streami_seed_opts* opts);
@@ -171,9 +177,9 @@ typedef struct {
                                1: seed order, one queue (results are bit-identical either way) */
   int32_t use_t_end;        /* 1: advance in a time window: a particle takes a step only while its
                                time t_birth + steps*h is < t_end, and stays ACTIVE at t_end (PLAIN
-                               mode).  Successive calls with growing t_end give bit-identical
-                               results to one call without a window; they keep the particles that
-                               are alive at one instant in the same time slices (streaklines) */
+                               mode).  Successive calls with growing t_end bring every particle to
+                               a common time and give bit-identical results to one call without a
+                               window */
   float t_end;              /* end of the window (with use_t_end); must not be NaN */
 } streami_advect_params;
 
@@ -195,7 +201,9 @@ typedef struct {
  * NULL, in which case it waits and fills *stats.  A call with a budget that
  * is resumed by further calls produces bit-identical lines, step counts and
  * codes to a single unbudgeted call.  Errors: E_ARG (bad params), E_STATE
- * (no particles, or SURROGATE without a network), E_DEVICE.
+ * (no particles, or SURROGATE without a network), E_UNSUPPORTED (SURROGATE
+ * with a time window, several blocks or time slices), E_NOMEM (vertex log
+ * growth), E_DEVICE.
  */
 int streami_advect(streami_field f, const streami_advect_params* p, streami_stats* stats);
 
