@@ -28,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+LAYOUT_NAMES = {1: "linear", 2: "brick4", 3: "cell"}
 MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak, published
 # one network evaluation: 2 * (3*256 + 3*256*256 + 256*3) multiply-adds
 MLP_FLOPS_PER_EVAL = 2 * (3 * 256 + 3 * 256 * 256 + 256 * 3)
@@ -322,7 +323,7 @@ def main():
                     choices=sorted(WORKLOADS) + ["surrogate-abc", "batched96-f16", "batched96-f16-streaklines"])
     ap.add_argument("--window-steps", type=int, default=0,
                     help="streaklines: advance in global-time windows of this many steps (0: one launch)")
-    ap.add_argument("--layout", type=int, default=0, help="0 auto, 1 linear, 2 brick4")
+    ap.add_argument("--layout", type=int, default=0, help="0 auto, 1 linear, 2 brick4, 3 cell records (FP32)")
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--refill", type=int, default=0)
     ap.add_argument("--no-cell-cache", action="store_true")
@@ -366,6 +367,8 @@ def main():
     f = S.Field([blk], fmt, layout=args.layout)
     torch.cuda.synchronize()
     ingest_s = time.perf_counter() - t0
+    layout, field_bytes = S.streami_field_info(f.h)
+    log(f"layout {LAYOUT_NAMES[layout]} ({field_bytes / 1e9:.2f} GB stored)")
     d_seeds = torch.from_numpy(seeds).to(dev)
     torch.cuda.synchronize()
 
@@ -423,7 +426,7 @@ def main():
     if os.path.exists(tfile):
         try:
             tj = json.load(open(tfile))
-            if tj.get("kernel_hash") == kernel_source_hash() and tj.get("layout", 0) == args.layout:
+            if tj.get("kernel_hash") == kernel_source_hash() and tj.get("layout", 0) == layout:
                 traffic = tj.get("hbm_bytes_per_launch")
         except Exception:
             traffic = None
@@ -443,7 +446,8 @@ def main():
         "config": {"workload": args.workload, "field": f"{WORKLOADS[args.workload][0]}^3 + ghost",
                    "seeds": len(seeds), "max_steps": m, "h": h, "record_stride": stride,
                    "particle_steps_per_step": steps_per_pass, "vertices_per_step": verts_per_pass,
-                   "layout": args.layout, "waves_per_cu": args.waves_per_cu,
+                   "layout": LAYOUT_NAMES[layout] + (" (auto)" if args.layout == 0 else ""),
+                   "field_bytes": field_bytes, "waves_per_cu": args.waves_per_cu,
                    "cell_cache": not args.no_cell_cache, "graph": args.graph},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

@@ -72,6 +72,11 @@ extern "C" {
 #define STREAMI_LAYOUT_AUTO 0
 #define STREAMI_LAYOUT_LINEAR 1 /* x-fastest node rows */
 #define STREAMI_LAYOUT_BRICK4 2 /* 4x4x4-node bricks, bricks in x-fastest order */
+/* FP32 only: one 96-byte record per cell with the monomial coefficients of its
+ * trilinear interpolant (the sample arithmetic of Sec. 3.1.1 moved to ingest);
+ * 8x the bytes of LINEAR, and results bit-identical to LINEAR for steady
+ * fields. */
+#define STREAMI_LAYOUT_CELL 3
 
 /* ---- advection modes ---- */
 #define STREAMI_MODE_PLAIN 0
@@ -111,7 +116,8 @@ typedef struct {
 } streami_block_desc;
 
 typedef struct {
-  int32_t layout; /* STREAMI_LAYOUT_*; AUTO picks the library default */
+  int32_t layout; /* STREAMI_LAYOUT_*; AUTO: CELL when dtype is F32, every block
+                     has one slice and fits CELL's limits (below), else LINEAR */
 } streami_field_opts;
 
 /*
@@ -123,10 +129,11 @@ typedef struct {
  * (NULL = the default stream).  opts may be NULL.
  * Errors: E_ARG for an invalid descriptor (the message names the field);
  * E_UNSUPPORTED for more than 448 blocks, a PERIODIC block in a handle with
- * several blocks or time slices, or a block whose time slice exceeds 2 GiB or
- * whose z plane of nodes exceeds 16 MiB (the kernels use 32-bit offsets;
- * split such a block); E_NOMEM, E_DEVICE.  *out is set only
- * on success.
+ * several blocks or time slices, the CELL layout with a 16-bit dtype, or a
+ * block whose time slice exceeds 2 GiB or whose z plane of nodes (CELL: of
+ * cell records) exceeds 16 MiB in the chosen layout (the kernels use 32-bit
+ * offsets; split such a block); E_NOMEM, E_DEVICE.  *out is set only on
+ * success.
  */
 int streami_field_create(const streami_block_desc* blocks, int32_t n_blocks, int32_t dtype,
                          const streami_field_opts* opts, void* hip_stream, streami_field* out);
@@ -168,7 +175,8 @@ typedef struct {
   streami_mlp mlp;          /* trained network for SURROGATE mode, else NULL */
   float residual_tol_cells; /* SURROGATE: accept a jump when its residual <= tol (cells) */
   int32_t residual_kind;    /* SURROGATE: 0 commutation residual, 1 one big RK4 step */
-  int32_t waves_per_cu;     /* launch shape; 0 = library default (16 up to 2^21 particles, else 32) */
+  int32_t waves_per_cu;     /* launch shape; 0 = library default (32 for the CELL layout or more
+                               than 2^21 particles, else 16) */
   int32_t refill_threshold; /* free lanes that trigger a work-queue refill; 0 = default (1) */
   int32_t use_graph;        /* 1: capture the launch sequence in a hipGraph and replay it */
   int32_t no_cell_cache;    /* 1: re-gather a cell's corners at every sample (A/B measurement;
@@ -247,6 +255,11 @@ int streami_clear(streami_field f);
 
 /* Particle counts of a block (for sizing fetch buffers). */
 int streami_block_info(streami_field f, int32_t block, int64_t* n_particles, int64_t* n_vertices);
+
+/* The storage the handle chose: *layout (nullable) receives the STREAMI_LAYOUT_*
+ * in use (never AUTO) and *field_bytes (nullable) the device bytes of the
+ * stored field, all blocks and slices.  E_ARG for a NULL handle. */
+int streami_field_info(streami_field f, int32_t* layout, int64_t* field_bytes);
 
 /* ---------------------------------------------------------------------------
  * Learned flow-map surrogate (not part of the paper: one of the forms this

@@ -25,7 +25,7 @@ OK, E_ARG, E_NOMEM, E_DEVICE, E_STATE, E_CAPACITY, E_UNSUPPORTED = range(7)
 F32, F16, BF16 = 0, 1, 2
 BOUNDARY_BLOCK, BOUNDARY_PERIODIC = 0, 1
 ACTIVE, MAX_STEPS, EXIT, STAGNANT, HALO_MISS, NONFINITE = range(6)
-LAYOUT_AUTO, LAYOUT_LINEAR, LAYOUT_BRICK4 = 0, 1, 2
+LAYOUT_AUTO, LAYOUT_LINEAR, LAYOUT_BRICK4, LAYOUT_CELL = 0, 1, 2, 3
 MODE_PLAIN, MODE_SURROGATE = 0, 1
 
 
@@ -101,6 +101,7 @@ def _load():
         "streami_fetch_lines": [vp, i32, i64, i64, vp, vp, i64, vp, vp, vp, vp],
         "streami_fetch_outbox": [vp, vp, i64, vp],
         "streami_block_info": [vp, i32, vp, vp],
+        "streami_field_info": [vp, vp, vp],
         "streami_clear": [vp],
         "streami_mlp_create": [vp, vp, ctypes.c_float, vp, vp],
         "streami_mlp_destroy": [vp],
@@ -230,6 +231,13 @@ def streami_fetch_outbox(f, out, cap):
 
 def streami_clear(f):
     return _check(_load().streami_clear(f))
+
+
+def streami_field_info(f):
+    """(layout in use, device bytes of the stored field)."""
+    lay, nb = ctypes.c_int32(), ctypes.c_int64()
+    _check(_load().streami_field_info(f, ctypes.byref(lay), ctypes.byref(nb)))
+    return lay.value, nb.value
 
 
 def streami_block_info(f, block):

@@ -1,7 +1,8 @@
 """Launch-configuration autotuner for the batched advection launch.
 
 Times the caller's whole pass (seeding plus every advect call of it) under each
-candidate -- node layout (x-fastest rows or 4x4x4 bricks), waves per CU,
+candidate -- node layout (x-fastest rows, 4x4x4 bricks, and for steady FP32
+fields per-cell coefficient records), waves per CU,
 refill threshold, work order -- through the C-ABI, and caches the fastest per
 (device, dtype, block shapes, caller's signature) in a JSON file
 (STREAMI_TUNE_CACHE, default ~/.cache/streami/autotune.json).  Results are
@@ -16,7 +17,11 @@ import time
 
 CANDIDATES = [dict(waves_per_cu=w, refill_threshold=r, work_order=o)
               for w in (16, 24, 32) for r in (1, 16) for o in (0, 1)]
-LAYOUTS = (1, 2)
+
+
+def _layouts(blocks, fmt):
+    steady_f32 = fmt == 0 and all(int(b.n_slices) == 1 for b in blocks)
+    return (1, 2, 3) if steady_f32 else (1, 2)
 
 
 def _cache_path():
@@ -50,7 +55,7 @@ def tune(blocks, fmt, pass_fn, sig, log=None, repeats=2):
     import torch
     best = None
     trials = []
-    for layout in LAYOUTS:
+    for layout in _layouts(blocks, fmt):
         f = Field(blocks, fmt, layout=layout)
 
         def one(cfg):

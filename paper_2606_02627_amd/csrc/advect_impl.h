@@ -79,10 +79,12 @@ __device__ __forceinline__ float3 load_node<FMT_BF16>(const char* p) {
                      __uint_as_float(w.y << 16));
 }
 
-// Byte offsets of node index i/j/k within one slice of a block.
+// Byte offsets of node index i/j/k within one slice of a block (CELL: of the
+// record of the cell whose lowest corner is node i/j/k).
 template <int LAYOUT, unsigned NB>
 __device__ __forceinline__ unsigned off_x(int i) {
   if (LAYOUT == LAYOUT_BRICK4) return __umul24((unsigned)(((i >> 2) << 6) + (i & 3)), NB);
+  if (LAYOUT == LAYOUT_CELL) return __umul24((unsigned)i, 96u);
   return __umul24((unsigned)i, NB);
 }
 template <int LAYOUT, unsigned NB>
@@ -136,22 +138,8 @@ __device__ __forceinline__ float3 trilinear(const float3 c[8], float fx, float f
   return v;
 }
 
-// Trilinear interpolant in monomial form: corners c[i] (i = x + 2y + 4z) are
-// turned in place into the coefficients of 1, x, y, xy, z, xz, yz, xyz
-// (three difference stages), so that a sample is 7 fused multiply-adds per
-// component.  The coefficients of a constant field are exactly 0 beyond the
-// first, so constant fields stay exact.
-__device__ __forceinline__ void to_monomial(float3 c[8]) {
-#pragma unroll
-  for (int b = 1; b < 8; b <<= 1)
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-      if (i & b) {
-        c[i].x -= c[i ^ b].x;
-        c[i].y -= c[i ^ b].y;
-        c[i].z -= c[i ^ b].z;
-      }
-}
+// A sample from monomial coefficients (to_monomial): 7 fused multiply-adds
+// per component.
 __device__ __forceinline__ float mono1(float k0, float k1, float k2, float k3, float k4, float k5, float k6, float k7,
                                        float fx, float fy, float fz) {
   const float a0 = fmaf(fz, k4, k0), a1 = fmaf(fz, k6, k2), a2 = fmaf(fz, k5, k1), a3 = fmaf(fz, k7, k3);
@@ -177,6 +165,20 @@ struct Sampler {
 
   __device__ __forceinline__ void gather(const BlockDev& B, const char* base, unsigned o000, int x0, int x1,
                                          int y0, int y1, int z0, int z1, float3 d[8]) {
+    if constexpr (LAYOUT == LAYOUT_CELL) {
+      // the record already holds the coefficients (periodic wrap included)
+      const float4* q = reinterpret_cast<const float4*>(base + o000);
+      const float4 a = q[0], b = q[1], c = q[2], e = q[3], g = q[4], k = q[5];
+      d[0] = make_float3(a.x, a.y, a.z);
+      d[1] = make_float3(a.w, b.x, b.y);
+      d[2] = make_float3(b.z, b.w, c.x);
+      d[3] = make_float3(c.y, c.z, c.w);
+      d[4] = make_float3(e.x, e.y, e.z);
+      d[5] = make_float3(e.w, g.x, g.y);
+      d[6] = make_float3(g.z, g.w, k.x);
+      d[7] = make_float3(k.y, k.z, k.w);
+      return;
+    }
     // signed deltas: a periodic wrap steps back to index 0 (a slice is < 2 GiB,
     // so every byte offset and delta fits in int)
     int dx, r10, r01;
@@ -219,14 +221,14 @@ struct Sampler {
     if (MODE == SM_CACHED) {
       if (ok && o000 != key) {
         gather(B, base, o000, x0, x1, y0, y1, z0, z1, c);
-        to_monomial(c);
+        if (LAYOUT != LAYOUT_CELL) to_monomial(c);
         key = o000;
       }
       v = monomial(c, fx, fy, fz);
     } else if (MODE == SM_UNCACHED) {
       if (ok) {
         gather(B, base, o000, x0, x1, y0, y1, z0, z1, c);
-        to_monomial(c);
+        if (LAYOUT != LAYOUT_CELL) to_monomial(c);
       }
       v = monomial(c, fx, fy, fz);
     } else {
@@ -243,10 +245,10 @@ struct Sampler {
         }
         const char* b0 = base + (size_t)s * B.slice_bytes;
         gather(B, b0, o000, x0, x1, y0, y1, z0, z1, d);
-        float3 v0 = trilinear(d, fx, fy, fz);
+        float3 v0 = LAYOUT == LAYOUT_CELL ? monomial(d, fx, fy, fz) : trilinear(d, fx, fy, fz);
         if (B.n_slices > 1) {
           gather(B, b0 + B.slice_bytes, o000, x0, x1, y0, y1, z0, z1, d);
-          const float3 v1 = trilinear(d, fx, fy, fz);
+          const float3 v1 = LAYOUT == LAYOUT_CELL ? monomial(d, fx, fy, fz) : trilinear(d, fx, fy, fz);
           v0.x = lerpf(v0.x, v1.x, al);
           v0.y = lerpf(v0.y, v1.y, al);
           v0.z = lerpf(v0.z, v1.z, al);
@@ -811,6 +813,13 @@ __global__ void __launch_bounds__(256) k_sur_apply(SurrogateArgs S) {
 template <int FMT>
 int launch_surrogate_fmt(const SurrogateArgs& s, int layout, bool periodic, bool pre, int grid, hipStream_t st) {
 #define STREAMI_S(LAY, PER)                                                                        if (pre) hipLaunchKernelGGL((k_sur_pre<FMT, LAY, PER>), dim3(grid), dim3(256), 0, st, s);        else hipLaunchKernelGGL((k_sur_apply<FMT, LAY, PER>), dim3(grid), dim3(256), 0, st, s);          return 0;
+  if constexpr (FMT == FMT_F32) {
+    if (layout == LAYOUT_CELL) {
+      if (periodic) { STREAMI_S(LAYOUT_CELL, true) } else { STREAMI_S(LAYOUT_CELL, false) }
+    }
+  } else {
+    if (layout == LAYOUT_CELL) return -1;
+  }
   if (layout == LAYOUT_BRICK4) {
     if (periodic) { STREAMI_S(LAYOUT_BRICK4, true) } else { STREAMI_S(LAYOUT_BRICK4, false) }
   } else {
@@ -854,6 +863,11 @@ int launch_advect_fmt(const AdvectArgs& a, int layout, bool periodic, int mode, 
   }                                                                                                 \
   return 0;
   if (FMT == FMT_F32 && mode == SM_UNSTEADY_UNCACHED) mode = SM_UNSTEADY;  // the same sampler
+  if constexpr (FMT == FMT_F32) {
+    if (layout == LAYOUT_CELL) { STREAMI_L(LAYOUT_CELL) }
+  } else {
+    if (layout == LAYOUT_CELL) return -1;
+  }
   if (layout == LAYOUT_BRICK4) {
     STREAMI_L(LAYOUT_BRICK4)
   } else {

@@ -232,6 +232,11 @@ BlockDev make_dev(const streami_block_desc& d, int layout, int fmt, long long ba
     B.nb[a] = (B.nst[a] + 3) / 4;
     slice *= layout == LAYOUT_BRICK4 ? (long long)B.nb[a] * 4 : B.nst[a];
   }
+  // cell layout: one record per cell (a periodic axis wraps, so it has as many
+  // cells as nodes), counted as 8 pool units of 12 bytes
+  long long cells[3];
+  for (int a = 0; a < 3; ++a) cells[a] = per ? B.nst[a] : B.nst[a] - 1;
+  if (layout == LAYOUT_CELL) slice = cells[0] * cells[1] * cells[2] * 8;
   // periodic blocks: origin shift folded into the position before sampling is
   // not needed when origin = 0; otherwise keep s = (x - origin)/spacing exact
   if (per)
@@ -247,6 +252,9 @@ BlockDev make_dev(const streami_block_desc& d, int layout, int fmt, long long ba
   if (layout == LAYOUT_BRICK4) {
     ys = (long long)B.nb[0] * 64 * nb;
     zs = (long long)B.nb[0] * B.nb[1] * 64 * nb;
+  } else if (layout == LAYOUT_CELL) {
+    ys = cells[0] * 96;
+    zs = cells[0] * cells[1] * 96;
   } else {
     ys = (long long)B.nst[0] * nb;
     zs = (long long)B.nst[0] * B.nst[1] * nb;
@@ -263,6 +271,9 @@ BlockDev make_dev(const streami_block_desc& d, int layout, int fmt, long long ba
 
 // The kernels address a slice with 32-bit byte offsets and 24-bit row/plane
 // multiplies: a slice must stay below 2 GiB and a z plane below 16 MiB.
+bool check_geometry_quiet(const BlockDev& B) {
+  return B.ys < (1u << 24) && B.zs < (1u << 24) && (long long)B.slice_bytes < (1LL << 31);
+}
 int check_geometry(const BlockDev& B, int i) {
   if (B.ys >= (1u << 24) || B.zs >= (1u << 24))
     return fail(STREAMI_E_UNSUPPORTED, "blocks[%d]: a z plane of nodes exceeds 16 MiB", i);
@@ -422,12 +433,26 @@ int streami_field_create(const streami_block_desc* blocks, int32_t n_blocks, int
   if (dtype != STREAMI_F32 && dtype != STREAMI_F16 && dtype != STREAMI_BF16)
     return fail(STREAMI_E_ARG, "dtype must be STREAMI_F32, STREAMI_F16 or STREAMI_BF16");
   int layout = opts ? opts->layout : STREAMI_LAYOUT_AUTO;
-  if (layout == STREAMI_LAYOUT_AUTO) layout = STREAMI_LAYOUT_LINEAR;
-  if (layout != STREAMI_LAYOUT_LINEAR && layout != STREAMI_LAYOUT_BRICK4)
+  if (layout != STREAMI_LAYOUT_AUTO && layout != STREAMI_LAYOUT_LINEAR && layout != STREAMI_LAYOUT_BRICK4 &&
+      layout != STREAMI_LAYOUT_CELL)
     return fail(STREAMI_E_ARG, "unknown layout %d", layout);
+  if (layout == STREAMI_LAYOUT_CELL && dtype != STREAMI_F32)
+    return fail(STREAMI_E_UNSUPPORTED, "the cell layout stores FP32 coefficients: dtype must be STREAMI_F32");
   for (int i = 0; i < n_blocks; ++i) {
     int rc = validate_desc(blocks[i], i);
     if (rc) return rc;
+  }
+  if (layout == STREAMI_LAYOUT_AUTO) {
+    // steady FP32 blocks whose cell records fit the kernels' 32-bit addressing
+    // take the cell layout (fewer instructions per cell-cache miss, 8x the
+    // bytes); everything else x-fastest rows
+    bool cell = dtype == STREAMI_F32;
+    for (int i = 0; i < n_blocks && cell; ++i)
+      cell = blocks[i].n_slices == 1 && check_geometry_quiet(make_dev(blocks[i], LAYOUT_CELL, dtype, 0));
+    layout = cell ? STREAMI_LAYOUT_CELL : STREAMI_LAYOUT_LINEAR;
+  }
+  for (int i = 0; i < n_blocks; ++i) {
+    int rc;
     // the addressing limits depend only on the shapes: refuse before any device work
     if ((rc = check_geometry(make_dev(blocks[i], layout, dtype, 0), i))) return rc;
   }
@@ -640,12 +665,14 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
   a.eps2 = p->stagnation_eps * p->stagnation_eps;
   a.budget = p->step_budget;
   // defaults measured on MI355X: refilling at the first free lane is 3-6%
-  // faster than at 16; 16 waves/CU suit ~4 particles per lane (1M seeds),
-  // 32 waves/CU suit larger sets (4M seeds: 16 waves/CU is 9% slower)
+  // faster than at 16; with node rows 16 waves/CU suit ~4 particles per lane
+  // (1M seeds) and 32 suit larger sets (4M seeds: 16 waves/CU is 9% slower);
+  // cell records (wider loads per miss) want 32 already at 1M seeds (5% faster)
   a.refill = p->refill_threshold > 0 ? p->refill_threshold : 1;
   a.windowed = p->use_t_end;
   a.t_end = p->use_t_end ? p->t_end : INFINITY;
-  const int wpc = p->waves_per_cu > 0 ? p->waves_per_cu : (f->n_particles <= (1LL << 21) ? 16 : 32);
+  const int wpc = p->waves_per_cu > 0 ? p->waves_per_cu
+                                      : (f->layout != LAYOUT_CELL && f->n_particles <= (1LL << 21) ? 16 : 32);
   long long grid = (long long)f->n_cu * wpc / 4;
   grid = std::min(grid, (f->n_particles + 255) / 256);
   grid = std::max(grid, 1LL);
@@ -740,6 +767,13 @@ int streami_clear(streami_field f) {
   }
   launch_fill_u64(f->persist(), PER_N, 0, f->stream);
   HIP_TRY(hipGetLastError());
+  return STREAMI_OK;
+}
+
+int streami_field_info(streami_field f, int32_t* layout, int64_t* field_bytes) {
+  if (!f) return fail(STREAMI_E_ARG, "field handle is NULL");
+  if (layout) *layout = f->layout;
+  if (field_bytes) *field_bytes = (int64_t)f->d_nodes.bytes;
   return STREAMI_OK;
 }
 

@@ -6,7 +6,12 @@
 namespace streami {
 
 enum Fmt { FMT_F32 = 0, FMT_F16 = 1, FMT_BF16 = 2 };
-enum Layout { LAYOUT_LINEAR = 1, LAYOUT_BRICK4 = 2 };
+// LINEAR: x-fastest node rows.  BRICK4: 4x4x4-node bricks.  CELL (FP32 only):
+// one 96-byte record per cell holding its trilinear interpolant's monomial
+// coefficients, so a cell-cache miss is six aligned 16-byte loads and no
+// arithmetic (8x the node bytes; `base` and `slice_nodes` then count 12-byte
+// units, 8 per cell).
+enum Layout { LAYOUT_LINEAR = 1, LAYOUT_BRICK4 = 2, LAYOUT_CELL = 3 };
 enum Code { ACTIVE = 0, MAX_STEPS = 1, EXIT = 2, STAGNANT = 3, HALO_MISS = 4, NONFINITE = 5 };
 
 // One block as the kernels see it.  Storage coordinate along an axis:
@@ -27,9 +32,9 @@ struct alignas(16) BlockDev {
   int nb[3];         // bricks per axis (brick layout)
   int pad0;
   long long base;    // node index of slice 0 of this block in the node pool
-  long long slice_nodes;
+  long long slice_nodes;  // pool units per slice (nodes; CELL: 8 per cell)
   // byte-offset geometry used by the advection kernel (all < 2^32)
-  unsigned ys, zs;       // linear: bytes per y row / z plane; brick4: bytes per brick row / plane
+  unsigned ys, zs;       // linear: bytes per y row / z plane; brick4: per brick row / plane; cell: per cell row / plane
   unsigned slice_bytes;  // bytes per time slice
   unsigned pad1;
   float fn[3];           // stored nodes per axis as float
@@ -115,6 +120,23 @@ struct SurrogateArgs {
   int kind;             // 0 commutation, 1 one big RK4 step
   int jump;             // steps per jump (16)
 };
+
+// Trilinear interpolant in monomial form: corners c[i] (i = x + 2y + 4z) are
+// turned in place into the coefficients of 1, x, y, xy, z, xz, yz, xyz
+// (three FP32 difference stages, always in this order, so the cell layout's
+// stored coefficients equal those computed from gathered corners bit for bit).
+// The coefficients of a constant field are exactly 0 beyond the first.
+__device__ __forceinline__ void to_monomial(float3 c[8]) {
+#pragma unroll
+  for (int b = 1; b < 8; b <<= 1)
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (i & b) {
+        c[i].x -= c[i ^ b].x;
+        c[i].y -= c[i ^ b].y;
+        c[i].z -= c[i ^ b].z;
+      }
+}
 
 constexpr int QCTR_STRIDE = 16;  // one 128-byte line per queue counter
 constexpr int MAX_QUEUES = 8;

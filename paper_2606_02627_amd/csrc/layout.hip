@@ -1,6 +1,7 @@
 // Field ingest (node re-layout), particle seeding, line packing and small fill
 // kernels.  Ingest copies the caller's x-fastest node array into the library's
-// node pool in the handle's layout; 16-bit nodes are padded to 8 bytes so a
+// node pool in the handle's layout (or, for the cell layout, computes each
+// cell's interpolation coefficients); 16-bit nodes are padded to 8 bytes so a
 // node is one aligned 64-bit load in the advection kernel.
 #include "device.h"
 
@@ -34,6 +35,45 @@ __global__ void k_ingest(const void* src, void* pool, BlockDev B, int nx, int ny
   }
 }
 
+// Cell layout (FP32): the record of cell (i, j, k) of slice s holds the
+// monomial coefficients of the trilinear interpolant over its 8 corner nodes
+// (corner index a + 2b + 4c for node (i+a, j+b, k+c), wrapped on a periodic
+// block), 24 floats in corner-major, xyz-minor order.
+__global__ void k_ingest_cell(const float* src, float4* pool, BlockDev B, int nx, int ny, int nz, int n_slices) {
+  const int per = B.periodic;
+  const int cx = per ? nx : nx - 1, cy = per ? ny : ny - 1, cz = per ? nz : nz - 1;
+  const long long per_slice = (long long)cx * cy * cz;
+  const long long total = per_slice * n_slices;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
+       t += (long long)gridDim.x * blockDim.x) {
+    const long long s = t / per_slice;
+    long long r = t - s * per_slice;
+    const int k = (int)(r / ((long long)cx * cy));
+    const long long rk = r - (long long)k * cx * cy;
+    const int j = (int)(rk / cx);
+    const int i = (int)(rk - (long long)j * cx);
+    float3 c[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      int ii = i + (q & 1), jj = j + ((q >> 1) & 1), kk = k + (q >> 2);
+      if (ii == nx) ii = 0;
+      if (jj == ny) jj = 0;
+      if (kk == nz) kk = 0;
+      const float* a = src + 3 * (((s * nz + kk) * ny + jj) * (long long)nx + ii);
+      c[q] = make_float3(a[0], a[1], a[2]);
+    }
+    to_monomial(c);
+    // B.base and B.slice_nodes count 12-byte units: 8 per 96-byte record
+    float4* o = pool + (B.base + s * B.slice_nodes) * 3 / 4 + r * 6;
+    o[0] = make_float4(c[0].x, c[0].y, c[0].z, c[1].x);
+    o[1] = make_float4(c[1].y, c[1].z, c[2].x, c[2].y);
+    o[2] = make_float4(c[2].z, c[3].x, c[3].y, c[3].z);
+    o[3] = make_float4(c[4].x, c[4].y, c[4].z, c[5].x);
+    o[4] = make_float4(c[5].y, c[5].z, c[6].x, c[6].y);
+    o[5] = make_float4(c[6].z, c[7].x, c[7].y, c[7].z);
+  }
+}
+
 int launch_ingest(const void* src, void* pool, const BlockDev& B, int fmt, int layout, int nx, int ny,
                   int nz, int n_slices, hipStream_t st) {
   const long long total = (long long)nx * ny * nz * n_slices;
@@ -41,7 +81,11 @@ int launch_ingest(const void* src, void* pool, const BlockDev& B, int fmt, int l
   if (grid > 65536) grid = 65536;
   if (grid < 1) grid = 1;
 #define STREAMI_INGEST(F, L) hipLaunchKernelGGL((k_ingest<F, L>), dim3(grid), dim3(256), 0, st, src, pool, B, nx, ny, nz, n_slices)
-  if (layout == LAYOUT_BRICK4) {
+  if (layout == LAYOUT_CELL) {
+    if (fmt != FMT_F32) return -1;
+    hipLaunchKernelGGL(k_ingest_cell, dim3(grid), dim3(256), 0, st, reinterpret_cast<const float*>(src),
+                       reinterpret_cast<float4*>(pool), B, nx, ny, nz, n_slices);
+  } else if (layout == LAYOUT_BRICK4) {
     if (fmt == FMT_F32) STREAMI_INGEST(FMT_F32, LAYOUT_BRICK4); else STREAMI_INGEST(FMT_F16, LAYOUT_BRICK4);
   } else {
     if (fmt == FMT_F32) STREAMI_INGEST(FMT_F32, LAYOUT_LINEAR); else STREAMI_INGEST(FMT_F16, LAYOUT_LINEAR);

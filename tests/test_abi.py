@@ -120,14 +120,17 @@ def test_binding_structs_match_the_header_layout(tmp_path):
         assert got == int(val), (pyname, what, got, val)
 
 
-@pytest.mark.parametrize("dims,dtype,msg", [
-    ((600, 600, 600), "f32", "2 GiB"),      # 602^3 nodes x 12 B: one slice > 2 GiB
-    ((1500, 1500, 2), "f32", "16 MiB"),     # a z plane of 1502^2 x 12 B > 16 MiB
-    ((1600, 1600, 2), "f16", "16 MiB"),     # 1602^2 x 8 B (16-bit nodes padded to 8 B)
+@pytest.mark.parametrize("dims,dtype,layout,msg", [
+    ((600, 600, 600), "f32", 0, "2 GiB"),   # 602^3 nodes x 12 B: one slice > 2 GiB
+    ((1500, 1500, 2), "f32", 0, "16 MiB"),  # a z plane of 1502^2 x 12 B > 16 MiB
+    ((1600, 1600, 2), "f16", 0, "16 MiB"),  # 1602^2 x 8 B (16-bit nodes padded to 8 B)
+    ((300, 300, 300), "f32", 3, "2 GiB"),   # 301^3 cell records x 96 B > 2 GiB
+    ((450, 450, 2), "f32", 3, "16 MiB"),    # a z plane of 451^2 cell records x 96 B > 16 MiB
 ])
-def test_field_create_rejects_shapes_beyond_the_addressing_limits(dims, dtype, msg):
+def test_field_create_rejects_shapes_beyond_the_addressing_limits(dims, dtype, layout, msg):
     """The kernels address a slice with 32-bit byte offsets and 24-bit row/plane products;
-    shapes beyond that are refused before any device work."""
+    shapes beyond that are refused before any device work (the automatic layout falls
+    back from cell records to node rows first)."""
     import torch
     if torch.cuda.is_available():
         pytest.skip("checked before device work; on a GPU machine a missed check would ingest")
@@ -135,8 +138,17 @@ def test_field_create_rejects_shapes_beyond_the_addressing_limits(dims, dtype, m
     d = _desc(dims=dims)
     fmt = {"f32": S.F32, "f16": S.F16}[dtype]
     with pytest.raises(S.StreamiError) as e:
-        S.streami_field_create([d], fmt)
+        S.streami_field_create([d], fmt, layout=layout)
     assert e.value.code == S.E_UNSUPPORTED and msg in str(e.value)
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_cell_layout_needs_fp32(dtype):
+    """Cell records hold FP32 coefficients: a 16-bit field cannot use them."""
+    import paper_2606_02627_amd as S
+    with pytest.raises(S.StreamiError) as e:
+        S.streami_field_create([_desc()], {"f16": S.F16, "bf16": S.BF16}[dtype], layout=S.LAYOUT_CELL)
+    assert e.value.code == S.E_UNSUPPORTED and "FP32" in str(e.value)
 
 
 def test_field_create_rejects_too_many_blocks():

@@ -74,7 +74,7 @@ def test_uniform_flow_bit_exact(S):
                                hi=(9, 9, 9), rank_grid=(3, 3, 3), rank_coord=(1, 1, 1))
     rng = np.random.default_rng(1)
     seeds = (rng.integers(0, 9 * 64, size=(777, 3)) / 64.0).astype(np.float32)
-    for layout in (S.LAYOUT_LINEAR, S.LAYOUT_BRICK4):
+    for layout in (S.LAYOUT_LINEAR, S.LAYOUT_BRICK4, S.LAYOUT_CELL):
         f, lines, ob, st = run(S, [blk], [seeds], 0.5, 1000, fg.F32, layout=layout)
         segs = parity.split_lines(lines[0])
         for i, s in enumerate(segs):
@@ -134,8 +134,8 @@ def test_abc_periodic_full(S):
 
 
 # ---------------------------------------------------------------- turbulence blocks
-@pytest.mark.parametrize("dtype", [fg.F32, fg.BF16, fg.F16])
-@pytest.mark.parametrize("layout", [1, 2])
+@pytest.mark.parametrize("dtype,layout", [(fg.F32, 1), (fg.F32, 2), (fg.F32, 3), (fg.BF16, 1), (fg.BF16, 2),
+                                          (fg.F16, 1), (fg.F16, 2)])
 def test_turbulence_block_parity(S, dtype, layout):
     """A 40^3 turbulence block (+ghost), 3000 seeds (ragged vs 256-lane workgroups), h=0.5,
     up to 400 steps: local check on every vertex, discrete results exact away from the
@@ -165,13 +165,14 @@ def test_turbulence_block_parity(S, dtype, layout):
 
 
 def test_bit_identical_variants(S):
-    """Cell cache on/off, brick/linear layout, hipGraph replay and chunked resume all give
-    bit-identical lines, steps, codes and outbox contents."""
+    """Cell cache on/off, node rows / bricks / cell records, hipGraph replay and chunked
+    resume all give bit-identical lines, steps, codes and outbox contents."""
     note("variants")
     blk = fg.turbulence_block(2, edge=32, rank_grid=(3, 3, 3), rank_coord=(1, 1, 1))
     seeds = fg.uniform_seeds(2, 2500, (0, 0, 0), (32, 32, 32), sub=9)
     base = run(S, [blk], [seeds], 0.5, 300, fg.F32)
-    variants = [dict(no_cell_cache=1), dict(layout=2), dict(use_graph=1), dict(chunk=37),
+    variants = [dict(no_cell_cache=1), dict(layout=1), dict(layout=2), dict(layout=3),
+                dict(layout=3, no_cell_cache=1), dict(use_graph=1), dict(chunk=37),
                 dict(waves_per_cu=8, refill_threshold=1), dict(work_order=1)]
     for v in variants:
         note("variant", v)
@@ -331,6 +332,64 @@ def test_unsteady_parity(S):
     dev, same = parity.global_compare(lines[0], ref, len(seeds))
     sens = parity.boundary_sensitive(ref, lines[0], dev, blk.lo, blk.hi, field=F)
     np.testing.assert_array_equal(lines[0]["codes"][~sens], ref["code"][~sens])
+
+
+def test_cell_records_periodic_batched_unsteady(S):
+    """Cell records (FP32 interpolant coefficients per cell) on the other paths: the
+    periodic ABC block (records wrap across the domain) and several blocks in one launch
+    give lines bit-identical to node rows; time-blended slices match the oracle."""
+    note("cell records: periodic")
+    blk = fg.abc_block(32)
+    seeds = fg.uniform_seeds(1, 700, (0, 0, 0), (2 * np.pi,) * 3, sub=3)
+    a = run(S, [blk], [seeds], 0.01, 150, fg.F32, layout=S.LAYOUT_LINEAR)
+    b = run(S, [blk], [seeds], 0.01, 150, fg.F32, layout=S.LAYOUT_CELL)
+    for k in ("offsets", "xyz", "steps", "codes", "ids"):
+        np.testing.assert_array_equal(a[1][0][k], b[1][0][k])
+    note("cell records: batched")
+    rng = np.random.default_rng(11)
+    blocks, seeds, ms = [], [], []
+    for i in range(5):
+        dims = tuple(int(v) for v in rng.integers(10, 30, size=3))
+        blocks.append(fg.turbulence_block(4, dims=dims, sub=i, rank_grid=(1, 1, 1), rank_coord=(0, 0, 0)))
+        n = int(rng.integers(40, 600))
+        seeds.append(fg.uniform_seeds(4, n, (0, 0, 0), dims, sub=200 + i))
+        ms.append(rng.integers(10, 250, size=n).astype(np.int32))
+    a = run(S, blocks, seeds, 0.5, ms, fg.F32, layout=S.LAYOUT_LINEAR)
+    b = run(S, blocks, seeds, 0.5, ms, fg.F32, layout=S.LAYOUT_CELL)
+    for i in range(5):
+        for k in ("offsets", "xyz", "steps", "codes", "ids"):
+            np.testing.assert_array_equal(a[1][i][k], b[1][i][k])
+    np.testing.assert_array_equal(np.sort(a[2], order="id"), np.sort(b[2], order="id"))
+    note("cell records: unsteady")
+    blk = fg.turbulence_block(6, edge=24, n_slices=4, slice_dt=40.0, rank_grid=(1, 1, 1), rank_coord=(0, 0, 0))
+    seeds = fg.uniform_seeds(6, 1500, (0, 0, 0), (24, 24, 24))
+    f, lines, ob, st = run(S, [blk], [seeds], 0.5, 300, fg.F32, layout=S.LAYOUT_CELL)
+    F = orc_field(blk)
+    ratio, _ = parity.local_check(F, lines[0], 0.5, 24.0, t_birth=0.0)
+    assert ratio <= 1.0, ratio
+    ref = F.trace(seeds, 0.5, 300)
+    dev, same = parity.global_compare(lines[0], ref, len(seeds))
+    sens = parity.boundary_sensitive(ref, lines[0], dev, blk.lo, blk.hi, field=F)
+    np.testing.assert_array_equal(lines[0]["codes"][~sens], ref["code"][~sens])
+    np.testing.assert_array_equal(lines[0]["steps"][~sens], ref["steps"][~sens])
+
+
+def test_automatic_layout_choice(S):
+    """AUTO stores a steady FP32 block as cell records (96 B per cell), and 16-bit or
+    time-sliced fields as node rows (12 B per FP32 node, 8 B per padded 16-bit node)."""
+    note("automatic layout")
+    blk = fg.turbulence_block(2, dims=(10, 12, 14))
+    f = S.Field([blk], fg.F32)
+    assert S.streami_field_info(f.h) == (S.LAYOUT_CELL, 11 * 13 * 15 * 96)
+    f.close()
+    blk16 = fg.turbulence_block(2, dims=(10, 12, 14), fmt=fg.F16)
+    f = S.Field([blk16], fg.F16)
+    assert S.streami_field_info(f.h) == (S.LAYOUT_LINEAR, 12 * 14 * 16 * 8)
+    f.close()
+    blkt = fg.turbulence_block(2, dims=(10, 12, 14), n_slices=3, slice_dt=5.0)
+    f = S.Field([blkt], fg.F32)
+    assert S.streami_field_info(f.h) == (S.LAYOUT_LINEAR, 3 * 12 * 14 * 16 * 12)
+    f.close()
 
 
 def test_device_inputs_match_host_inputs(S):
