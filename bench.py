@@ -422,14 +422,19 @@ def main():
     mean_adv_s = float(np.mean(adv_ms)) / 1e3
     achieved = alg_bytes / mean_adv_s / 1e9
     traffic = None
+    counters = None
     tfile = os.path.join(ROOT, "profiles", f"traffic_advect_{args.workload}.json")
     if os.path.exists(tfile):
         try:
             tj = json.load(open(tfile))
             if tj.get("kernel_hash") == kernel_source_hash() and tj.get("layout", 0) == layout:
                 traffic = tj.get("hbm_bytes_per_launch")
+                if "valu_issue" in tj:
+                    # what bounds the kernel, from the same profiled revision's counters
+                    counters = {"valu_issue_frac": tj["valu_issue"], "l2_hit_rate": tj.get("l2_hit"),
+                                "source": os.path.relpath(tfile, ROOT)}
         except Exception:
-            traffic = None
+            traffic = counters = None
     out = {
         "metric": "RK4 particle-steps/s + HBM GB/s; surrogate vs plain at fixed endpoint error",
         "value": value,
@@ -452,7 +457,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_advect", "alg_bytes_per_launch": alg_bytes,
-                     "mean_launch_ms": mean_adv_s * 1e3, "kernel_hash": kernel_source_hash()},
+                     "mean_launch_ms": mean_adv_s * 1e3, "kernel_hash": kernel_source_hash(),
+                     "counters": counters},
         "advect_only_steps_per_s": steps_per_pass / mean_adv_s,
         "ingest_ms": ingest_s * 1e3,
         "fetch_lines_ms_per_65536": fetch_s * 1e3,
