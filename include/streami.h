@@ -200,6 +200,8 @@ typedef struct {
   int64_t surrogate_fallback;  /* jumps rejected and redone with plain RK4 */
   int64_t terminated[6];       /* particles per termination code after the call */
   double device_ms;            /* device time of the advect kernels of this call */
+  int64_t gathers;             /* PLAIN mode: cells fetched from memory in this call (one per
+                                  time slice blended), i.e. the lanes' cell-cache misses */
 } streami_stats;
 
 /*

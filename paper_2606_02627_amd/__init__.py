@@ -69,7 +69,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("active", ctypes.c_int64), ("steps", ctypes.c_int64),
                 ("vertices", ctypes.c_int64), ("outbox", ctypes.c_int64),
                 ("surrogate_accepted", ctypes.c_int64), ("surrogate_fallback", ctypes.c_int64),
-                ("terminated", ctypes.c_int64 * 6), ("device_ms", ctypes.c_double)]
+                ("terminated", ctypes.c_int64 * 6), ("device_ms", ctypes.c_double),
+                ("gathers", ctypes.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "terminated"}
@@ -109,6 +110,7 @@ def _load():
         "streami_mlp_get_params": [vp, vp],
         "streami_mlp_forward": [vp, vp, i64, vp],
         "streami_mlp_train_step": [vp, vp, vp, i64, ctypes.c_float, vp, vp],
+        "streami_probe_gather": [vp, i64, i32, i32, i32, i32, vp, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -231,6 +233,18 @@ def streami_fetch_outbox(f, out, cap):
 
 def streami_clear(f):
     return _check(_load().streami_clear(f))
+
+
+def streami_probe_gather(buf, record_bytes, loads_per_lane, in_flight=4, waves_per_cu=16, stream=None):
+    """Random record gathers over a device tensor: (ms of the timed launch, records read)."""
+    ptr, dev = _addr(buf)
+    if not dev:
+        raise ValueError("the probe reads device memory")
+    ms, n = ctypes.c_float(), ctypes.c_int64()
+    _check(_load().streami_probe_gather(ptr, buf.numel() * buf.element_size(), int(record_bytes),
+                                        int(loads_per_lane), int(in_flight), int(waves_per_cu), _stream(stream),
+                                        ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
 
 
 def streami_field_info(f):

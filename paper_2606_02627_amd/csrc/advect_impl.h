@@ -159,6 +159,7 @@ template <int FMT, int LAYOUT, bool PERIODIC, int MODE>
 struct Sampler {
   static constexpr unsigned NB = NodeBytes<FMT>::v;
   unsigned key;
+  unsigned gathers = 0;  // cell-cache refills of this lane (a time-sliced refill reads two slices)
   float3 c[8];
 
   __device__ __forceinline__ void reset() { key = 0xffffffffu; }
@@ -223,18 +224,21 @@ struct Sampler {
         gather(B, base, o000, x0, x1, y0, y1, z0, z1, c);
         if (LAYOUT != LAYOUT_CELL) to_monomial(c);
         key = o000;
+        ++gathers;
       }
       v = monomial(c, fx, fy, fz);
     } else if (MODE == SM_UNCACHED) {
       if (ok) {
         gather(B, base, o000, x0, x1, y0, y1, z0, z1, c);
         if (LAYOUT != LAYOUT_CELL) to_monomial(c);
+        ++gathers;
       }
       v = monomial(c, fx, fy, fz);
     } else {
       // linear blend of the two slices bracketing t, clamped at the ends
       float3 d[8];
       if (ok) {
+        ++gathers;
         int s = 0;
         float al = 0.0f;
         if (B.n_slices > 1) {
@@ -287,6 +291,7 @@ struct PackedSlicesSampler {
   static constexpr unsigned NB = 8;
   static constexpr int NS = 2;
   unsigned key, skey;
+  unsigned gathers = 0;  // cell-cache refills of this lane (a time-sliced refill reads two slices)
   unsigned xy[NS][8];  // corner c: x | y << 16
   unsigned zz[NS][4];  // corners 2i, 2i+1: z | z << 16
 
@@ -356,7 +361,9 @@ struct PackedSlicesSampler {
       s = (int)fs;
       al = fminf(fmaxf(u - fs, 0.0f), 1.0f);
     }
-    if (ok && (o000 != key || (unsigned)s != skey)) {
+    const bool refill = ok && (o000 != key || (unsigned)s != skey);
+    gathers += refill ? 1u : 0u;  // counted outside the branch: inside it costs 17 registers here
+    if (refill) {
       const char* b0 = base + (size_t)s * B.slice_bytes;
       gather(B, b0, o000, x0, x1, y0, y1, z0, z1, xy[0], zz[0]);
       if (B.n_slices > 1) gather(B, b0 + B.slice_bytes, o000, x0, x1, y0, y1, z0, z1, xy[1], zz[1]);
@@ -626,8 +633,10 @@ __device__ __forceinline__ void advect_body(const AdvectArgs& A) {
     for (unsigned long long r = cpos + lane; r < cend; r += 64)
       A.log.v[r] = make_float4(0.f, 0.f, 0.f, __uint_as_float(LOG_UNUSED));
   const unsigned long long s = wave_sum((unsigned long long)my_steps), v = wave_sum((unsigned long long)my_verts);
+  const unsigned long long g = wave_sum((unsigned long long)smp.gathers);
   if (lane == 0) {
     if (s) atomicAdd(&A.ctr[CTR_STEPS], s);
+    if (g) atomicAdd(&A.ctr[CTR_GATHERS], g);
     if (v) {
       atomicAdd(&A.ctr[CTR_VERTS], v);
       atomicAdd(A.ctr + CTR_N + PER_LOG_REAL, v);

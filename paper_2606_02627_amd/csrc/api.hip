@@ -346,6 +346,7 @@ int collect_stats(streami_field_s* f, streami_stats* stats) {
   float ms = 0;
   HIP_TRY(hipEventElapsedTime(&ms, f->ev0, f->ev1));
   stats->device_ms = ms;
+  stats->gathers = (int64_t)h[CTR_GATHERS];
   if (h[CTR_OVERFLOW]) return fail(STREAMI_E_DEVICE, "vertex log overflow (internal sizing error)");
   return STREAMI_OK;
 }

@@ -54,7 +54,8 @@ static_assert(sizeof(OutRec) == 32, "outbox record must be 32 bytes");
 
 // Per-call counters (zeroed by a fill kernel before each advect launch).
 enum Counter {
-  CTR_QUEUE = 0, CTR_STEPS = 1, CTR_VERTS = 2, CTR_ACCEPT = 3, CTR_FALLBACK = 4, CTR_OVERFLOW = 5, CTR_N = 8
+  CTR_QUEUE = 0, CTR_STEPS = 1, CTR_VERTS = 2, CTR_ACCEPT = 3, CTR_FALLBACK = 4, CTR_OVERFLOW = 5,
+  CTR_GATHERS = 6, CTR_N = 8
 };
 
 // Persistent counters (survive across advect calls; reset by streami_clear).

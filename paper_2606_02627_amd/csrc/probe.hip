@@ -1,0 +1,130 @@
+// Memory-level probe behind streami_probe_gather (include/streami_probe.h):
+// random record gathers over a buffer of a chosen footprint, to measure the
+// gather rate each level of the memory hierarchy sustains (L2 for a few
+// hundred KB, the Infinity Cache for ~200 MB, HBM beyond).  It is measurement
+// support for the advection kernel's gather roofline, not part of the method.
+#include <hip/hip_runtime.h>
+
+#include "../../include/streami.h"
+#include "../../include/streami_probe.h"
+
+namespace streami {
+int set_error(int code, const char* msg);
+}
+
+namespace {
+
+// 32-bit integer mix (xorshift-multiply, "lowbias32" constants by C. Wellons):
+// a counter-based stream of record indices, cheap next to a memory access.
+__device__ __forceinline__ unsigned mix32(unsigned x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+// Each lane reads `per_lane` records of R16 x 16 bytes at record-aligned
+// offsets r * R16 * 16, r uniform in [0, n_recs) (n_recs < 2^32), and writes
+// the XOR of everything it read to sink[lane] so no load can be dropped.
+// U records are in flight per lane at a time (per_lane is a multiple of U).
+template <int R16, int U>
+__global__ void __launch_bounds__(256) k_probe_gather(const uint4* __restrict__ buf, unsigned n_recs, int per_lane,
+                                                      unsigned seed, unsigned* __restrict__ sink) {
+  const unsigned tid = blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned acc = 0;
+  const unsigned ctr = mix32(tid ^ seed);
+  for (int i = 0; i < per_lane; i += U) {
+    uint4 v[U][R16];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const unsigned r = __umulhi(mix32(ctr + (unsigned)(i + u) * 0x9e3779b9u), n_recs);
+      const uint4* q = buf + (size_t)r * R16;
+#pragma unroll
+      for (int k = 0; k < R16; ++k) v[u][k] = q[k];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < R16; ++k) acc ^= v[u][k].x ^ v[u][k].y ^ v[u][k].z ^ v[u][k].w;
+  }
+  sink[tid] = acc;
+}
+
+int perr(int code, const char* msg) { return streami::set_error(code, msg); }
+
+template <int R16>
+void launch_probe(int in_flight, unsigned grid, hipStream_t st, const uint4* b, unsigned nr, int per_lane,
+                  unsigned seed, unsigned* sink) {
+  if (in_flight == 1)
+    hipLaunchKernelGGL((k_probe_gather<R16, 1>), dim3(grid), dim3(256), 0, st, b, nr, per_lane, seed, sink);
+  else if (in_flight == 2)
+    hipLaunchKernelGGL((k_probe_gather<R16, 2>), dim3(grid), dim3(256), 0, st, b, nr, per_lane, seed, sink);
+  else if (in_flight == 4)
+    hipLaunchKernelGGL((k_probe_gather<R16, 4>), dim3(grid), dim3(256), 0, st, b, nr, per_lane, seed, sink);
+  else
+    hipLaunchKernelGGL((k_probe_gather<R16, 8>), dim3(grid), dim3(256), 0, st, b, nr, per_lane, seed, sink);
+}
+
+}  // namespace
+
+extern "C" int streami_probe_gather(const void* buf, int64_t bytes, int32_t record_bytes, int32_t loads_per_lane,
+                                    int32_t in_flight, int32_t waves_per_cu, void* hip_stream, float* ms,
+                                    int64_t* records_read) {
+  if (!buf || !ms) return perr(STREAMI_E_ARG, "buf and ms must not be NULL");
+  if (record_bytes != 16 && record_bytes != 96 && record_bytes != 128)
+    return perr(STREAMI_E_ARG, "record_bytes must be 16, 96 or 128");
+  if (in_flight != 1 && in_flight != 2 && in_flight != 4 && in_flight != 8)
+    return perr(STREAMI_E_ARG, "in_flight must be 1, 2, 4 or 8");
+  if (loads_per_lane < in_flight || loads_per_lane % in_flight != 0 || loads_per_lane > (1 << 20))
+    return perr(STREAMI_E_ARG, "loads_per_lane must be a multiple of in_flight in [in_flight, 2^20]");
+  if (waves_per_cu < 1 || waves_per_cu > 64) return perr(STREAMI_E_ARG, "waves_per_cu must be in [1, 64]");
+  const long long n_recs = bytes / record_bytes;
+  if (bytes < 0 || n_recs < 1 || n_recs >= (1LL << 32))
+    return perr(STREAMI_E_ARG, "bytes must hold 1 to 2^32-1 records");
+  hipStream_t st = (hipStream_t)hip_stream;
+  int dev = 0, n_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return perr(STREAMI_E_DEVICE, "no HIP device");
+  const unsigned grid = (unsigned)n_cu * (unsigned)waves_per_cu / 4;
+  const size_t lanes = (size_t)grid * 256;
+  unsigned* sink = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipMalloc(&sink, lanes * sizeof(unsigned)) != hipSuccess) {
+    (void)hipGetLastError();
+    return perr(STREAMI_E_NOMEM, "probe sink allocation failed");
+  }
+  int rc = STREAMI_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    rc = perr(STREAMI_E_DEVICE, "event creation failed");
+  } else {
+    const uint4* b = reinterpret_cast<const uint4*>(buf);
+    const unsigned nr = (unsigned)n_recs;
+    // one untimed launch (caches and TLB warm), then the timed one
+    for (int rep = 0; rep < 2 && rc == STREAMI_OK; ++rep) {
+      if (rep == 1) (void)hipEventRecord(e0, st);
+      const unsigned seed = 0x5eed0000u + (unsigned)rep;
+      if (record_bytes == 16)
+        launch_probe<1>(in_flight, grid, st, b, nr, loads_per_lane, seed, sink);
+      else if (record_bytes == 96)
+        launch_probe<6>(in_flight, grid, st, b, nr, loads_per_lane, seed, sink);
+      else
+        launch_probe<8>(in_flight, grid, st, b, nr, loads_per_lane, seed, sink);
+      if (hipGetLastError() != hipSuccess) rc = perr(STREAMI_E_DEVICE, "probe launch failed");
+      if (rep == 1) (void)hipEventRecord(e1, st);
+    }
+    if (rc == STREAMI_OK) {
+      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+        rc = perr(STREAMI_E_DEVICE, "probe timing failed");
+      else if (records_read)
+        *records_read = (int64_t)lanes * loads_per_lane;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(sink);
+  return rc;
+}

@@ -92,6 +92,24 @@ def test_calls_on_null_handle_fail_cleanly():
     assert b"NULL" in lib.streami_last_error()
 
 
+def test_probe_rejects_invalid_arguments_before_device_work():
+    """The memory probe validates everything before it touches HIP (the buffer pointer below
+    is never dereferenced)."""
+    import paper_2606_02627_amd as S
+    lib = S._load()
+    ms = ctypes.c_float()
+    fake = ctypes.c_void_p(1 << 20)
+    probe = lambda *a: lib.streami_probe_gather(*a, None, ctypes.byref(ms), None)
+    assert probe(None, 1 << 20, 16, 64, 4, 16) == S.E_ARG
+    assert probe(fake, 1 << 20, 24, 64, 4, 16) == S.E_ARG
+    assert probe(fake, 1 << 20, 16, 64, 3, 16) == S.E_ARG
+    assert probe(fake, 1 << 20, 16, 63, 4, 16) == S.E_ARG
+    assert probe(fake, 1 << 20, 16, 64, 4, 0) == S.E_ARG
+    assert probe(fake, 8, 16, 64, 4, 16) == S.E_ARG
+    assert probe(fake, 1 << 40, 16, 64, 4, 16) == S.E_ARG
+    assert b"record" in lib.streami_last_error()
+
+
 STRUCTS = [("streami_block_desc", "BlockDesc"), ("streami_field_opts", "FieldOpts"),
            ("streami_seed_opts", "SeedOpts"), ("streami_advect_params", "AdvectParams"),
            ("streami_stats", "Stats")]

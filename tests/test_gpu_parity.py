@@ -93,6 +93,52 @@ def test_uniform_flow_bit_exact(S):
         np.testing.assert_array_equal(srt["steps"], ref["steps"])
 
 
+def test_gather_counts(S):
+    """streami_stats.gathers counts the lanes' cell-cache misses: on a dyadic uniform flow the
+    stage points are exact, so the count equals the number of cell changes along each
+    particle's sample sequence (k1, k2, k3, k4 of every step), the same for node rows and cell
+    records; without the cache every sample is a gather."""
+    note("gather counts")
+    c = (0.375, -0.25, 0.125)
+    blk = fg.closed_form_block(lambda x, y, z: (0 * x + c[0], 0 * x + c[1], 0 * x + c[2]),
+                               (9, 9, 9), ghost=1, origin=(0.5, 0.5, 0.5), lo=(0, 0, 0),
+                               hi=(9, 9, 9), rank_grid=(3, 3, 3), rank_coord=(1, 1, 1))
+    rng = np.random.default_rng(3)
+    seeds = (rng.integers(0, 9 * 64, size=(301, 3)) / 64.0).astype(np.float32)
+    h, cv = 0.5, np.array(c)
+    expect, total_steps = 0, 0
+    for p0 in seeds.astype(np.float64):
+        key, p = None, p0.copy()
+        while True:
+            for q in (p, p + 0.5 * h * cv, p + 0.5 * h * cv, p + h * cv):
+                cell = tuple(int(min(max(np.floor(v + 0.5), 0), 9)) for v in q)
+                if cell != key:
+                    expect, key = expect + 1, cell
+            p = p + h * cv
+            total_steps += 1
+            if ((p < 0) | (p >= 9)).any():
+                break
+    for layout in (S.LAYOUT_LINEAR, S.LAYOUT_CELL):
+        f, lines, ob, st = run(S, [blk], [seeds], h, 1000, fg.F32, layout=layout)
+        assert st.steps == total_steps and st.gathers == expect, (layout, st.steps, st.gathers, expect)
+        f, lines, ob, st = run(S, [blk], [seeds], h, 1000, fg.F32, layout=layout, no_cell_cache=1)
+        assert st.gathers == 4 * total_steps, (layout, st.gathers)
+
+
+def test_memory_probe_reads_what_it_reports(S):
+    """The memory probe (random record reads over a device buffer) runs for every record size
+    and reports lanes x loads records and a positive time."""
+    import torch
+    buf = torch.zeros(1 << 20, dtype=torch.uint8, device="cuda")
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    for rec in (16, 96, 128):
+        ms, n = S.streami_probe_gather(buf, rec, 8, 2, 4)  # 4 waves per CU: one workgroup per CU
+        assert ms > 0 and n == n_cu * 256 * 8, (rec, ms, n)
+        note(f"probe {rec} B: {n} records in {ms:.3f} ms")
+    with pytest.raises(S.StreamiError):
+        S.streami_probe_gather(buf[:8], 16, 8, 2, 4)
+
+
 def test_solid_body_rotation_closed_form(S):
     """v = w(-(y-3), x-3, 0) lies in the trilinear span: vertices follow R(hA)^n exactly up
     to FP32 rounding (circles shrinking by the RK4 radius factor)."""

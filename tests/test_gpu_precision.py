@@ -56,3 +56,36 @@ def test_precision_table(S):
     assert errs["f32"][0] <= 1e-4
     assert errs["bf16"][0] <= 2e-3 and errs["f16"][0] <= 2e-3
     assert errs["f16"][0] <= errs["bf16"][0]  # 11-bit vs 8-bit significand
+
+
+def test_full_size_512_accuracy_vs_fp64(S):
+    """The 512^3 workload as benchmarked (4M seeds in 64 blobs, h = 0.5, up to 4000 steps,
+    every 8th vertex kept), stored in FP32, BF16 and FP16: the endpoint error of the first
+    2048 seeds against the FP64 oracle on the unrounded field, per format."""
+    seeds = fg.blob_seeds(3, 64, 65536, 512.0, 24.0, 8.0)
+    k, h, m = 2048, 0.5, 4000
+    acc = None
+    rows = {}
+    for fmt in (fg.F32, fg.BF16, fg.F16):
+        name = fg.DTYPE_NAMES[fmt]
+        note("512^3 accuracy", name)
+        blk = fg.turbulence_block(3, edge=512, fmt=fmt)
+        f = S.Field([blk], fmt)
+        f.seed(0, seeds, default_max_steps=m, record_stride=8)
+        st = f.advect(h)
+        assert st.active == 0
+        L = f.lines(0, 0, k)
+        f.close()
+        if acc is None:
+            acc = oracle.Field.from_block(blk, use_values=True).trace(seeds[:k], h, m, keep_verts=False)
+        del blk
+        end = L["xyz"][L["offsets"][1:] - 1].astype(np.float64)
+        err = np.abs(end - acc["final_pos"]).max(axis=1) / 512.0
+        same = (acc["code"] == L["codes"]) & (acc["steps"] == L["steps"])
+        rows[name] = dict(median=float(np.median(err)), p90=float(np.quantile(err, 0.9)), max=float(err.max()),
+                          within_2e3=float((err <= 2e-3).mean()), within_1e4=float((err <= 1e-4).mean()),
+                          same_code_and_steps=float(same.mean()))
+        note(name, rows[name])
+    assert rows["f32"]["median"] <= 1e-4 and rows["f32"]["within_2e3"] >= 0.95
+    assert rows["bf16"]["median"] <= 2e-3 and rows["f16"]["median"] <= 2e-3
+    assert rows["f32"]["median"] <= rows["f16"]["median"] <= rows["bf16"]["median"]
