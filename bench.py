@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 LAYOUT_NAMES = {1: "linear", 2: "brick4", 3: "cell"}
+CLOCK_GHZ = 2.4  # MI355X peak engine clock
 MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak, published
 # one network evaluation: 2 * (3*256 + 3*256*256 + 256*3) multiply-adds
 MLP_FLOPS_PER_EVAL = 2 * (3 * 256 + 3 * 256 * 256 + 256 * 3)
@@ -464,9 +465,9 @@ def main():
             tj = json.load(open(tfile))
             if tj.get("kernel_hash") == kernel_source_hash() and tj.get("layout", 0) == layout:
                 traffic = tj.get("hbm_bytes_per_launch")
-                if "valu_issue" in tj:
+                if "valu_instructions" in tj:
                     # what bounds the kernel, from the same profiled revision's counters
-                    counters = {"valu_issue_frac": tj["valu_issue"], "l2_hit_rate": tj.get("l2_hit"),
+                    counters = {"valu_instructions": tj["valu_instructions"], "l2_hit_rate": tj.get("l2_hit"),
                                 "source": os.path.relpath(tfile, ROOT)}
         except Exception:
             traffic = counters = None
@@ -495,10 +496,25 @@ def main():
                      "mean_launch_ms": mean_adv_s * 1e3, "kernel_hash": kernel_source_hash(),
                      "counters": counters},
         "advect_only_steps_per_s": steps_per_pass / mean_adv_s,
+        "cell_refills_per_step": int(st0.gathers) / steps_per_pass,
         "ingest_ms": ingest_s * 1e3,
         "fetch_lines_ms_per_65536": fetch_s * 1e3,
         "outbox_records": int(len(ob)),
     }
+    if counters is not None:
+        # VALU busy fraction: the profiled instruction count at the measured issue cost of a
+        # VOP2 add (lower bound) and of a VOP3 FMA (upper bound) per wave64 instruction
+        n_simd = 4 * torch.cuda.get_device_properties(0).multi_processor_count
+        cyc = {}
+        for kind, name in ((0, "fma_f32"), (1, "add_u32")):
+            ms, n = S.streami_probe_valu(kind, 32)
+            cyc[name] = n_simd * CLOCK_GHZ * 1e9 * ms * 1e-3 / n
+        slots = n_simd * CLOCK_GHZ * 1e9 * mean_adv_s
+        counters["valu_cycles_per_instruction"] = cyc
+        counters["valu_busy_range"] = [counters["valu_instructions"] * cyc["add_u32"] / slots,
+                                       counters["valu_instructions"] * cyc["fma_f32"] / slots]
+        log(f"VALU busy between {counters['valu_busy_range'][0]:.2f} and {counters['valu_busy_range'][1]:.2f} "
+            f"(fma {cyc['fma_f32']:.2f}, add {cyc['add_u32']:.2f} cycles per wave64 instruction)")
     if layout == S.LAYOUT_CELL:
         # gather roofline: the lanes' cell-cache misses are random 96-byte record reads from
         # the stored field; set their rate against the measured rate of such reads

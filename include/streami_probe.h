@@ -32,6 +32,16 @@ int streami_probe_gather(const void* buf, int64_t bytes, int32_t record_bytes, i
                          int32_t in_flight, int32_t waves_per_cu, void* hip_stream, float* ms,
                          int64_t* records_read);
 
+/* VALU issue rate: waves_per_cu (a multiple of 4 in [4, 64]) waves per CU
+ * each run 8 independent chains of one instruction kind -- kind 0 v_fma_f32
+ * (a VOP3 encoding), kind 1 v_add_u32 (VOP2) -- 131,072 instructions per wave.
+ * One untimed launch, then one timed with HIP events on hip_stream: *ms is
+ * its time and *instructions (nullable) the wave-level instructions of the
+ * chains, so (4 x CUs) x clock x time / instructions is the cycles a SIMD
+ * spends per wave64 instruction of that kind.  Synchronises the stream.  Errors:
+ * E_ARG (NULL ms, kind, waves_per_cu), E_NOMEM, E_DEVICE. */
+int streami_probe_valu(int32_t kind, int32_t waves_per_cu, void* hip_stream, float* ms, int64_t* instructions);
+
 #ifdef __cplusplus
 }
 #endif

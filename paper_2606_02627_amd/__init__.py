@@ -111,6 +111,7 @@ def _load():
         "streami_mlp_forward": [vp, vp, i64, vp],
         "streami_mlp_train_step": [vp, vp, vp, i64, ctypes.c_float, vp, vp],
         "streami_probe_gather": [vp, i64, i32, i32, i32, i32, vp, vp, vp],
+        "streami_probe_valu": [i32, i32, vp, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -244,6 +245,14 @@ def streami_probe_gather(buf, record_bytes, loads_per_lane, in_flight=4, waves_p
     _check(_load().streami_probe_gather(ptr, buf.numel() * buf.element_size(), int(record_bytes),
                                         int(loads_per_lane), int(in_flight), int(waves_per_cu), _stream(stream),
                                         ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+def streami_probe_valu(kind, waves_per_cu=32, stream=None):
+    """VALU issue-rate probe (kind 0 v_fma_f32, 1 v_add_u32): (ms, wave-level instructions)."""
+    ms, n = ctypes.c_float(), ctypes.c_int64()
+    _check(_load().streami_probe_valu(int(kind), int(waves_per_cu), _stream(stream), ctypes.byref(ms),
+                                      ctypes.byref(n)))
     return ms.value, n.value
 
 

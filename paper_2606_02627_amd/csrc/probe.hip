@@ -52,6 +52,28 @@ __global__ void __launch_bounds__(256) k_probe_gather(const uint4* __restrict__ 
   sink[tid] = acc;
 }
 
+// VALU issue rate: 8 independent chains per lane of one instruction kind
+// (0: v_fma_f32, a VOP3 encoding; 1: v_add_u32, VOP2), 16 x 8 per iteration.
+template <int KIND>
+__global__ void __launch_bounds__(256) k_probe_valu(unsigned* __restrict__ sink, int iters) {
+  unsigned x[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) x[c] = threadIdx.x * 2654435761u + (unsigned)c;
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        if (KIND == 0) x[c] = __float_as_uint(fmaf(__uint_as_float(x[c]), 0.999f, 0.5f));
+        else x[c] = x[c] + x[(c + 1) & 7];
+      }
+  }
+  unsigned acc = 0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) acc ^= x[c];
+  sink[blockIdx.x * blockDim.x + threadIdx.x] = acc;
+}
+
 int perr(int code, const char* msg) { return streami::set_error(code, msg); }
 
 template <int R16>
@@ -120,6 +142,52 @@ extern "C" int streami_probe_gather(const void* buf, int64_t bytes, int32_t reco
         rc = perr(STREAMI_E_DEVICE, "probe timing failed");
       else if (records_read)
         *records_read = (int64_t)lanes * loads_per_lane;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(sink);
+  return rc;
+}
+
+extern "C" int streami_probe_valu(int32_t kind, int32_t waves_per_cu, void* hip_stream, float* ms,
+                                  int64_t* instructions) {
+  if (!ms) return perr(STREAMI_E_ARG, "ms must not be NULL");
+  if (kind != 0 && kind != 1) return perr(STREAMI_E_ARG, "kind must be 0 (v_fma_f32) or 1 (v_add_u32)");
+  if (waves_per_cu < 4 || waves_per_cu > 64 || waves_per_cu % 4 != 0)
+    return perr(STREAMI_E_ARG, "waves_per_cu must be a multiple of 4 in [4, 64]");
+  hipStream_t st = (hipStream_t)hip_stream;
+  int dev = 0, n_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return perr(STREAMI_E_DEVICE, "no HIP device");
+  const unsigned grid = (unsigned)n_cu * (unsigned)waves_per_cu / 4;
+  const int iters = 1024;
+  unsigned* sink = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipMalloc(&sink, (size_t)grid * 256 * sizeof(unsigned)) != hipSuccess) {
+    (void)hipGetLastError();
+    return perr(STREAMI_E_NOMEM, "probe sink allocation failed");
+  }
+  int rc = STREAMI_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    rc = perr(STREAMI_E_DEVICE, "event creation failed");
+  } else {
+    for (int rep = 0; rep < 2 && rc == STREAMI_OK; ++rep) {
+      if (rep == 1) (void)hipEventRecord(e0, st);
+      if (kind == 0)
+        hipLaunchKernelGGL(k_probe_valu<0>, dim3(grid), dim3(256), 0, st, sink, iters);
+      else
+        hipLaunchKernelGGL(k_probe_valu<1>, dim3(grid), dim3(256), 0, st, sink, iters);
+      if (hipGetLastError() != hipSuccess) rc = perr(STREAMI_E_DEVICE, "probe launch failed");
+      if (rep == 1) (void)hipEventRecord(e1, st);
+    }
+    if (rc == STREAMI_OK) {
+      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+        rc = perr(STREAMI_E_DEVICE, "probe timing failed");
+      else if (instructions)
+        *instructions = (int64_t)grid * 4 * iters * 16 * 8;  // wave-level instructions of the chains
     }
   }
   if (e0) (void)hipEventDestroy(e0);

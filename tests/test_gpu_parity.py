@@ -126,8 +126,8 @@ def test_gather_counts(S):
 
 
 def test_memory_probe_reads_what_it_reports(S):
-    """The memory probe (random record reads over a device buffer) runs for every record size
-    and reports lanes x loads records and a positive time."""
+    """The probes (random record reads over a device buffer; VALU issue rate) run for every
+    record size and instruction kind and report the work they did and a positive time."""
     import torch
     buf = torch.zeros(1 << 20, dtype=torch.uint8, device="cuda")
     n_cu = torch.cuda.get_device_properties(0).multi_processor_count
@@ -137,6 +137,10 @@ def test_memory_probe_reads_what_it_reports(S):
         note(f"probe {rec} B: {n} records in {ms:.3f} ms")
     with pytest.raises(S.StreamiError):
         S.streami_probe_gather(buf[:8], 16, 8, 2, 4)
+    for kind in (0, 1):
+        ms, n = S.streami_probe_valu(kind, 4)
+        assert ms > 0 and n == n_cu * 4 * 1024 * 128, (kind, ms, n)
+        note(f"valu probe kind {kind}: {4 * n_cu * 2.4e6 * ms / n:.2f} cycles per wave64 instruction at 2.4 GHz")
 
 
 def test_solid_body_rotation_closed_form(S):
