@@ -189,6 +189,8 @@ typedef struct {
                                a common time and give bit-identical results to one call without a
                                window */
   float t_end;              /* end of the window (with use_t_end); must not be NaN */
+  int32_t checked_samples;  /* 1: test every sample's domain, also for steps that start deep inside a
+                               single block (A/B measurement; results are bit-identical either way) */
 } streami_advect_params;
 
 typedef struct {

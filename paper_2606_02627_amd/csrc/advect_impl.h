@@ -101,12 +101,19 @@ __device__ __forceinline__ unsigned off_z(const BlockDev& B, int k) {
 // Cell location along one axis, without branches.  Block: defined iff
 // 0 <= s <= n-1 (closed); i0 = min(floor(s), n-2), f = s - i0.  Periodic:
 // i0 = floor(s) mod n (exact in float for |s| < 2^24), i1 = (i0+1) mod n.
-// Undefined coordinates still produce in-range indices.
-template <bool PERIODIC>
+// Undefined coordinates still produce in-range indices.  Without CHECK the
+// caller guarantees 0 <= s < n-1 (a step deep inside the block), where the
+// test and the clamp change nothing.
+template <bool PERIODIC, bool CHECK = true>
 __device__ __forceinline__ void locate_axis(float x, float scale, float offs, float fn, float inv_fn,
                                             int& i0, int& i1, float& f, bool& ok) {
   const float s = fmaf(x, scale, offs);
-  if (PERIODIC) {
+  if (!PERIODIC && !CHECK) {
+    const float fl = floorf(s);
+    f = s - fl;
+    i0 = (int)fl;
+    i1 = i0 + 1;
+  } else if (PERIODIC) {
     ok = ok && (__builtin_fabsf(s) < 8388608.0f);
     const float fl = floorf(s);
     f = s - fl;
@@ -210,14 +217,21 @@ struct Sampler {
     d[7] = load_node<FMT>(p11 + dx);
   }
 
-  __device__ __forceinline__ bool operator()(const BlockDev& B, const char* base, float3 x, float t,
-                                             float3& v) {
+  // inner (wave-uniform): every sample of this step is known to lie inside
+  __device__ __forceinline__ bool sample(const BlockDev& B, const char* base, float3 x, float t, float3& v,
+                                         bool inner = false) {
     bool ok = true;
     int x0, x1, y0, y1, z0, z1;
     float fx, fy, fz;
-    locate_axis<PERIODIC>(x.x, B.scale[0], B.offs[0], B.fn[0], B.inv_fn[0], x0, x1, fx, ok);
-    locate_axis<PERIODIC>(x.y, B.scale[1], B.offs[1], B.fn[1], B.inv_fn[1], y0, y1, fy, ok);
-    locate_axis<PERIODIC>(x.z, B.scale[2], B.offs[2], B.fn[2], B.inv_fn[2], z0, z1, fz, ok);
+    if (!PERIODIC && inner) {
+      locate_axis<false, false>(x.x, B.scale[0], B.offs[0], B.fn[0], B.inv_fn[0], x0, x1, fx, ok);
+      locate_axis<false, false>(x.y, B.scale[1], B.offs[1], B.fn[1], B.inv_fn[1], y0, y1, fy, ok);
+      locate_axis<false, false>(x.z, B.scale[2], B.offs[2], B.fn[2], B.inv_fn[2], z0, z1, fz, ok);
+    } else {
+      locate_axis<PERIODIC>(x.x, B.scale[0], B.offs[0], B.fn[0], B.inv_fn[0], x0, x1, fx, ok);
+      locate_axis<PERIODIC>(x.y, B.scale[1], B.offs[1], B.fn[1], B.inv_fn[1], y0, y1, fy, ok);
+      locate_axis<PERIODIC>(x.z, B.scale[2], B.offs[2], B.fn[2], B.inv_fn[2], z0, z1, fz, ok);
+    }
     const unsigned o000 = off_x<LAYOUT, NB>(x0) + off_y<LAYOUT, NB>(B, y0) + off_z<LAYOUT, NB>(B, z0);
     if (MODE == SM_CACHED) {
       if (ok && o000 != key) {
@@ -344,14 +358,21 @@ struct PackedSlicesSampler {
     return v;
   }
 
-  __device__ __forceinline__ bool operator()(const BlockDev& B, const char* base, float3 x, float t,
-                                             float3& v) {
+  // inner (wave-uniform): every sample of this step is known to lie inside
+  __device__ __forceinline__ bool sample(const BlockDev& B, const char* base, float3 x, float t, float3& v,
+                                         bool inner = false) {
     bool ok = true;
     int x0, x1, y0, y1, z0, z1;
     float fx, fy, fz;
-    locate_axis<PERIODIC>(x.x, B.scale[0], B.offs[0], B.fn[0], B.inv_fn[0], x0, x1, fx, ok);
-    locate_axis<PERIODIC>(x.y, B.scale[1], B.offs[1], B.fn[1], B.inv_fn[1], y0, y1, fy, ok);
-    locate_axis<PERIODIC>(x.z, B.scale[2], B.offs[2], B.fn[2], B.inv_fn[2], z0, z1, fz, ok);
+    if (!PERIODIC && inner) {
+      locate_axis<false, false>(x.x, B.scale[0], B.offs[0], B.fn[0], B.inv_fn[0], x0, x1, fx, ok);
+      locate_axis<false, false>(x.y, B.scale[1], B.offs[1], B.fn[1], B.inv_fn[1], y0, y1, fy, ok);
+      locate_axis<false, false>(x.z, B.scale[2], B.offs[2], B.fn[2], B.inv_fn[2], z0, z1, fz, ok);
+    } else {
+      locate_axis<PERIODIC>(x.x, B.scale[0], B.offs[0], B.fn[0], B.inv_fn[0], x0, x1, fx, ok);
+      locate_axis<PERIODIC>(x.y, B.scale[1], B.offs[1], B.fn[1], B.inv_fn[1], y0, y1, fy, ok);
+      locate_axis<PERIODIC>(x.z, B.scale[2], B.offs[2], B.fn[2], B.inv_fn[2], z0, z1, fz, ok);
+    }
     const unsigned o000 = off_x<LAYOUT, NB>(x0) + off_y<LAYOUT, NB>(B, y0) + off_z<LAYOUT, NB>(B, z0);
     int s = 0;
     float al = 0.0f;
@@ -407,20 +428,20 @@ struct SamplerFor<FMT_BF16, LAYOUT, PERIODIC, SM_UNSTEADY> {
 // undefined stage point is non-finite, or the new position is.
 template <class S>
 __device__ __forceinline__ int rk4_step(S& smp, const BlockDev& B, const char* base, float3 P, float t,
-                                        float h, float eps2, float3& P1, float3& fail) {
+                                        float h, float eps2, float3& P1, float3& fail, bool inner = false) {
   float3 k, q, sum;
-  if (!smp(B, base, P, t, k)) { fail = P; return HALO_MISS; }
+  if (!smp.sample(B, base, P, t, k, inner)) { fail = P; return HALO_MISS; }
   if (fmaf(k.x, k.x, fmaf(k.y, k.y, k.z * k.z)) < eps2) return STAGNANT;
   const float hh = 0.5f * h;
   sum = k;  // k1 + 2 k2 + 2 k3 + k4, accumulated as the stages come in
   q = make_float3(fmaf(hh, k.x, P.x), fmaf(hh, k.y, P.y), fmaf(hh, k.z, P.z));
-  if (!smp(B, base, q, t + hh, k)) { fail = q; return finite3(q) ? HALO_MISS : NONFINITE; }
+  if (!smp.sample(B, base, q, t + hh, k, inner)) { fail = q; return finite3(q) ? HALO_MISS : NONFINITE; }
   sum = make_float3(fmaf(2.0f, k.x, sum.x), fmaf(2.0f, k.y, sum.y), fmaf(2.0f, k.z, sum.z));
   q = make_float3(fmaf(hh, k.x, P.x), fmaf(hh, k.y, P.y), fmaf(hh, k.z, P.z));
-  if (!smp(B, base, q, t + hh, k)) { fail = q; return finite3(q) ? HALO_MISS : NONFINITE; }
+  if (!smp.sample(B, base, q, t + hh, k, inner)) { fail = q; return finite3(q) ? HALO_MISS : NONFINITE; }
   sum = make_float3(fmaf(2.0f, k.x, sum.x), fmaf(2.0f, k.y, sum.y), fmaf(2.0f, k.z, sum.z));
   q = make_float3(fmaf(h, k.x, P.x), fmaf(h, k.y, P.y), fmaf(h, k.z, P.z));
-  if (!smp(B, base, q, t + h, k)) { fail = q; return finite3(q) ? HALO_MISS : NONFINITE; }
+  if (!smp.sample(B, base, q, t + h, k, inner)) { fail = q; return finite3(q) ? HALO_MISS : NONFINITE; }
   sum = make_float3(sum.x + k.x, sum.y + k.y, sum.z + k.z);
   P1 = make_float3(P.x + div6(h * sum.x), P.y + div6(h * sum.y), P.z + div6(h * sum.z));
   if (!finite3(P1)) return NONFINITE;
@@ -478,6 +499,22 @@ __device__ __forceinline__ void advect_body(const AdvectArgs& A) {
   } else {
     B0 = A.blocks[0];
     base0 = reinterpret_cast<const char*>(A.nodes) + (size_t)B0.base * NB;
+  }
+  // interior of a single non-periodic block: a step that starts with its
+  // storage coordinates in [ilo, ihi] on every axis samples only where the
+  // field is defined and below the last node, so its samples skip the domain
+  // test and the clamp (bit-identical results); NaN bounds disable it.  Only
+  // the cell layout has the registers for the second path: with node rows
+  // it would cost a wave per SIMD (96 -> 100 VGPRs), more than it saves.
+  constexpr bool INTERIOR = !BATCHED && !PERIODIC && LAYOUT == LAYOUT_CELL;
+  float ilo[3], ihi[3];
+  if constexpr (INTERIOR) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float mg = fmaf(fabsf(A.h), B0.vs[a], B0.sl[a]);
+      ilo[a] = A.checked ? INFINITY : mg;
+      ihi[a] = B0.fn[a] - 1.0f - mg;
+    }
   }
   const int lane = __lane_id();
   int p = -1;  // particle index (< 2^31, enforced at seeding)
@@ -548,7 +585,18 @@ __device__ __forceinline__ void advect_body(const AdvectArgs& A) {
         left = 0;  // the window ends here: park the particle, still ACTIVE
       } else {
         float3 P1, fail;
-        const int st = rk4_step(smp, B, lbase, P, t, A.h, A.eps2, P1, fail);
+        int st;
+        bool inner = false;
+        if constexpr (INTERIOR) {
+          bool in = true;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            const float sa = fmaf(a == 0 ? P.x : a == 1 ? P.y : P.z, B0.scale[a], B0.offs[a]);
+            in = in && sa >= ilo[a] && sa <= ihi[a];
+          }
+          inner = __ballot(!in) == 0;  // the lanes taking a step, all inside: a uniform branch
+        }
+        st = rk4_step(smp, B, lbase, P, t, A.h, A.eps2, P1, fail, inner);
         if (st == ACTIVE) {
           P = P1;
           ++n;

@@ -37,6 +37,7 @@ int launch_scatter_lines(const VertexLog& log, long long n_rec, long long n_part
                          const long long* offsets, float* out, hipStream_t st);
 int launch_mark_rows(const long long* idx, long long count, int* row_of, hipStream_t st);
 int launch_fill_u32(unsigned* p, long long n, unsigned v, hipStream_t st);
+int launch_max_abs(const void* src, int fmt, long long n, unsigned* out, hipStream_t st);
 int launch_work_order(const float4* pos, const int4* meta, const int4* meta2, const BlockDev* blocks, long long n,
                       int bits, unsigned n_buckets, float h, float t_end, unsigned* key, unsigned* hist,
                       unsigned* cursor, int* order, unsigned* n_work, hipStream_t st);
@@ -489,7 +490,9 @@ int streami_field_create(const streami_block_desc* blocks, int32_t n_blocks, int
     if (hipMemsetAsync(f->d_nodes.p, 0, f->d_nodes.bytes, f->stream) != hipSuccess)
       return cleanup(fail(STREAMI_E_DEVICE, "hipMemsetAsync failed"));
   std::vector<BlockDev> devs(n_blocks);
-  DevBuf staging;
+  DevBuf staging, vmax;
+  if ((rc = vmax.reserve(sizeof(unsigned) * 3 * n_blocks, 0, f->stream))) return cleanup(rc);
+  launch_fill_u32((unsigned*)vmax.p, 3LL * n_blocks, 0u, f->stream);
   for (int i = 0; i < n_blocks; ++i) {
     HostBlock& hb = f->blocks[i];
     devs[i] = hb.dev;
@@ -502,10 +505,38 @@ int streami_field_create(const streami_block_desc* blocks, int32_t n_blocks, int
       src = staging.p;
     }
     launch_ingest(src, f->d_nodes.p, hb.dev, dtype, layout, hb.nx, hb.ny, hb.nz, hb.desc.n_slices, f->stream);
+    launch_max_abs(src, dtype, (long long)hb.nx * hb.ny * hb.nz * hb.desc.n_slices, (unsigned*)vmax.p + 3 * i,
+                   f->stream);
     if (hipGetLastError() != hipSuccess) return cleanup(fail(STREAMI_E_DEVICE, "ingest launch failed"));
     if (!hb.desc.nodes_on_device && hipStreamSynchronize(f->stream) != hipSuccess)
       return cleanup(fail(STREAMI_E_DEVICE, "ingest failed"));
     hb.desc.nodes = nullptr;  // the caller keeps ownership; never read again
+  }
+  // interior-test bounds per block: the largest |v_a| over the stored nodes
+  // bounds every interpolated value (a convex combination), with 2^-10
+  // relative slack for the FP32 interpolation; the rounding slack covers a
+  // few ulps of the largest world coordinate and of the storage coordinate
+  {
+    std::vector<unsigned> mx(3 * (size_t)n_blocks);
+    if (hipMemcpyAsync(mx.data(), vmax.p, mx.size() * sizeof(unsigned), hipMemcpyDeviceToHost, f->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(f->stream) != hipSuccess)
+      return cleanup(fail(STREAMI_E_DEVICE, "field maximum readback failed"));
+    for (int i = 0; i < n_blocks; ++i) {
+      const streami_block_desc& d = blocks[i];
+      const int g = d.boundary == STREAMI_BOUNDARY_PERIODIC ? 0 : d.ghost;
+      for (int a = 0; a < 3; ++a) {
+        float m;
+        std::memcpy(&m, &mx[3 * i + a], 4);
+        const double sc = 1.0 / d.spacing[a];
+        const double w = std::max(std::fabs(d.origin[a] - g * d.spacing[a]),
+                                  std::fabs(d.origin[a] + (devs[i].nst[a] - 1 - g) * d.spacing[a]));
+        devs[i].vs[a] = (float)((double)m * sc * (1.0 + 0x1p-10));
+        devs[i].sl[a] = (float)(w * 0x1p-22 * sc + devs[i].nst[a] * 0x1p-20 + 0x1p-6);
+        f->blocks[i].dev.vs[a] = devs[i].vs[a];
+        f->blocks[i].dev.sl[a] = devs[i].sl[a];
+      }
+    }
   }
   if ((rc = f->d_blocks.reserve(sizeof(BlockDev) * n_blocks, 0, f->stream))) return cleanup(rc);
   if (hipMemcpyAsync(f->d_blocks.p, devs.data(), sizeof(BlockDev) * n_blocks, hipMemcpyHostToDevice, f->stream) !=
@@ -644,6 +675,8 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
   if (p->work_order != 0 && p->work_order != 1) return fail(STREAMI_E_ARG, "work_order must be 0 or 1");
   if (f->n_particles == 0) return fail(STREAMI_E_STATE, "no particles seeded");
   if (p->use_t_end != 0 && p->use_t_end != 1) return fail(STREAMI_E_ARG, "use_t_end must be 0 or 1");
+  if (p->checked_samples != 0 && p->checked_samples != 1)
+    return fail(STREAMI_E_ARG, "checked_samples must be 0 or 1");
   if (p->use_t_end && std::isnan(p->t_end)) return fail(STREAMI_E_ARG, "t_end is NaN");
   if (p->mode == STREAMI_MODE_SURROGATE) {
     if (p->use_t_end) return fail(STREAMI_E_UNSUPPORTED, "surrogate mode takes no time window");
@@ -671,6 +704,7 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
   // cell records (wider loads per miss) want 32 already at 1M seeds (5% faster)
   a.refill = p->refill_threshold > 0 ? p->refill_threshold : 1;
   a.windowed = p->use_t_end;
+  a.checked = p->checked_samples;
   a.t_end = p->use_t_end ? p->t_end : INFINITY;
   const int wpc = p->waves_per_cu > 0 ? p->waves_per_cu
                                       : (f->layout != LAYOUT_CELL && f->n_particles <= (1LL << 21) ? 16 : 32);

@@ -39,6 +39,12 @@ struct alignas(16) BlockDev {
   unsigned pad1;
   float fn[3];           // stored nodes per axis as float
   float inv_fn[3];       // 1/fn (periodic wrap)
+  // interior test: a step's stage points lie within |h| vs[a] storage units of
+  // its start along axis a (the interpolant is a convex combination of node
+  // values), up to sl[a] units of rounding; vs = max |v_a| over the stored
+  // nodes x scale x (1 + 2^-10), NaN or Inf when a node is not finite
+  float vs[3];
+  float sl[3];
 };
 
 // Outbox record, 32 bytes (same layout as streami_outbox_rec).
@@ -107,6 +113,7 @@ struct AdvectArgs {
   int refill;               // free lanes that trigger a refill
   float t_end;              // with `windowed`, a step starts only at t < t_end
   int windowed;             // 0: no time window (the time is then only the sampler's)
+  int checked;              // 1: test every sample's domain even deep inside the block
 };
 
 // One surrogate jump (16 plain steps) for every active particle of a single

@@ -74,6 +74,46 @@ __global__ void k_ingest_cell(const float* src, float4* pool, BlockDev B, int nx
   }
 }
 
+// max |v_a| per component over n nodes of the caller's array (xyz per node,
+// FP32 or 16-bit), as the bit pattern of a non-negative float so that an
+// unsigned max orders it; a NaN node wins (its pattern exceeds Inf's), so a
+// field with a NaN never passes the interior test
+__global__ void k_max_abs(const void* src, int fmt, long long n, unsigned* out) {
+  unsigned m[3] = {0u, 0u, 0u};
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n;
+       t += (long long)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      float v;
+      if (fmt == FMT_F32) {
+        v = reinterpret_cast<const float*>(src)[3 * t + a];
+      } else {
+        const unsigned short u = reinterpret_cast<const unsigned short*>(src)[3 * t + a];
+        v = fmt == FMT_F16 ? (float)__builtin_bit_cast(_Float16, u) : __uint_as_float((unsigned)u << 16);
+      }
+      const unsigned b = __float_as_uint(v) & 0x7fffffffu;
+      m[a] = b > m[a] ? b : m[a];
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    unsigned w = m[a];
+    for (int off = 32; off > 0; off >>= 1) {
+      const unsigned o = __shfl_xor(w, off, 64);
+      w = o > w ? o : w;
+    }
+    if (__lane_id() == 0 && w) atomicMax(out + a, w);
+  }
+}
+
+int launch_max_abs(const void* src, int fmt, long long n, unsigned* out, hipStream_t st) {
+  int grid = (int)((n + 255) / 256);
+  if (grid > 4096) grid = 4096;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(k_max_abs, dim3(grid), dim3(256), 0, st, src, fmt, n, out);
+  return 0;
+}
+
 int launch_ingest(const void* src, void* pool, const BlockDev& B, int fmt, int layout, int nx, int ny,
                   int nz, int n_slices, hipStream_t st) {
   const long long total = (long long)nx * ny * nz * n_slices;
