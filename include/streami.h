@@ -128,7 +128,7 @@ typedef struct {
  * hip_stream: the hipStream_t all later work of this handle is enqueued on
  * (NULL = the default stream).  opts may be NULL.
  * Errors: E_ARG for an invalid descriptor (the message names the field);
- * E_UNSUPPORTED for more than 448 blocks, a PERIODIC block in a handle with
+ * E_UNSUPPORTED for more than 315 blocks, a PERIODIC block in a handle with
  * several blocks or time slices, the CELL layout with a 16-bit dtype, or a
  * block whose time slice exceeds 2 GiB or whose z plane of nodes (CELL: of
  * cell records) exceeds 16 MiB in the chosen layout (the kernels use 32-bit

@@ -430,8 +430,8 @@ int streami_field_create(const streami_block_desc* blocks, int32_t n_blocks, int
                          const streami_field_opts* opts, void* hip_stream, streami_field* out) {
   if (!out) return fail(STREAMI_E_ARG, "out is NULL");
   if (!blocks || n_blocks < 1) return fail(STREAMI_E_ARG, "need at least one block");
-  // the batched kernel stages the block table in LDS (144 B per block, <= 64 KiB)
-  if (n_blocks > 448) return fail(STREAMI_E_UNSUPPORTED, "at most 448 blocks per handle");
+  // the batched kernel stages the block table in LDS (at most 64 KiB of it)
+  if (n_blocks > MAX_BLOCKS) return fail(STREAMI_E_UNSUPPORTED, "at most %d blocks per handle", MAX_BLOCKS);
   if (dtype != STREAMI_F32 && dtype != STREAMI_F16 && dtype != STREAMI_BF16)
     return fail(STREAMI_E_ARG, "dtype must be STREAMI_F32, STREAMI_F16 or STREAMI_BF16");
   int layout = opts ? opts->layout : STREAMI_LAYOUT_AUTO;

@@ -173,7 +173,8 @@ def test_cell_layout_needs_fp32(dtype):
 
 
 def test_field_create_rejects_too_many_blocks():
+    """The batched launch keeps the block table in at most 64 KiB of LDS: 315 blocks."""
     import paper_2606_02627_amd as S
     with pytest.raises(S.StreamiError) as e:
-        S.streami_field_create([_desc()] * 449, S.F32)
-    assert e.value.code == S.E_UNSUPPORTED and "448" in str(e.value)
+        S.streami_field_create([_desc()] * 316, S.F32)
+    assert e.value.code == S.E_UNSUPPORTED and "315" in str(e.value)
