@@ -51,6 +51,10 @@ int launch_count_codes(const int4* meta, long long n, unsigned long long* counts
 
 using namespace streami;
 
+// the batched kernel stages the block table in LDS: at most 64 KiB of it
+constexpr int MAX_BLOCKS = 65536 / (int)sizeof(BlockDev);
+static_assert(MAX_BLOCKS >= 256, "block table too large for LDS");
+
 namespace {
 
 thread_local std::string g_err;

@@ -147,9 +147,6 @@ __device__ __forceinline__ void to_monomial(float3 c[8]) {
 }
 
 constexpr int QCTR_STRIDE = 16;  // one 128-byte line per queue counter
-// the batched kernel stages the block table in LDS: at most 64 KiB of it
-constexpr int MAX_BLOCKS = 65536 / (int)sizeof(BlockDev);
-static_assert(MAX_BLOCKS >= 256, "block table too large for LDS");
 constexpr int MAX_QUEUES = 8;
 
 // Per-axis offsets of node i within a slice of a block.
