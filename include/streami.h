@@ -202,8 +202,9 @@ typedef struct {
   int64_t surrogate_fallback;  /* jumps rejected and redone with plain RK4 */
   int64_t terminated[6];       /* particles per termination code after the call */
   double device_ms;            /* device time of the advect kernels of this call */
-  int64_t gathers;             /* PLAIN mode: cells fetched from memory in this call (one per
-                                  time slice blended), i.e. the lanes' cell-cache misses */
+  int64_t gathers;             /* PLAIN mode: the lanes' cell-cache refills in this call (a
+                                  refill of a time-sliced field reads both slices; without the
+                                  cache every defined sample is one) */
 } streami_stats;
 
 /*
