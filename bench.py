@@ -101,10 +101,22 @@ def cpu_baseline(blk, seeds, h, m, budget_s=12.0):
         total_steps += int(r["steps"].sum())
         used += k
         n *= 2
+    # one thread, on the first seeds only (about a second)
+    k1 = min(len(seeds), 4096)
+    t0 = time.perf_counter()
+    r1 = F.trace(seeds[:k1], h, m, threads=1, keep_verts=False)
+    one = int(r1["steps"].sum()) / (time.perf_counter() - t0)
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), None)
+    except OSError:
+        pass
     return dict(value=total_steps / total_t, unit="particle-steps/s", cores=threads, kind="oracle",
                 sample=f"first {used} of the {len(seeds)} seeds, full trajectories "
                        f"(<= {m} steps each, {total_steps} steps) on the same stored field, FP64",
-                seconds=round(total_t, 2))
+                seconds=round(total_t, 2), one_thread_value=one, one_thread_sample=f"first {k1} seeds",
+                cpu_model=model)
 
 
 def surrogate_bench(args):
