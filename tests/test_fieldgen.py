@@ -45,3 +45,21 @@ def test_seed_sets():
     assert (b >= 0).all() and (b < 512).all() and b.shape == (8000, 3)
     for k in range(4):
         assert 6.5 < b[k * 2000:(k + 1) * 2000].std(axis=0).mean() < 9.5
+
+
+def test_turbulence_energy_spectrum_slope():
+    """Per-mode amplitudes |k|^-5/6 with |k| uniform in [1, 32] give a shell energy spectrum
+    E(k) ~ k^-5/3: a windowed FFT of a 128^3 field recovers the slope over k = 2..24."""
+    n = 128
+    v = fg.turbulence_values(91, (n, n, n), n_modes=512, kmin=1.0, kmax=32.0)[0][1:-1, 1:-1, 1:-1]
+    w = np.hanning(n)
+    win = w[:, None, None] * w[None, :, None] * w[None, None, :]
+    k = np.fft.fftfreq(n) * n
+    shell = np.rint(np.sqrt(k[:, None, None] ** 2 + k[None, :, None] ** 2 + k[None, None, :] ** 2)).astype(int)
+    energy = np.zeros(n)
+    for c in range(3):
+        power = np.abs(np.fft.fftn(v[..., c] * win)) ** 2
+        energy += np.bincount(shell.ravel(), weights=power.ravel(), minlength=n)[:n]
+    ks = np.arange(2, 25)
+    slope = np.polyfit(np.log(ks), np.log(energy[ks]), 1)[0]
+    assert abs(slope + 5.0 / 3.0) < 0.2, slope
