@@ -143,6 +143,29 @@ def test_memory_probe_reads_what_it_reports(S):
         note(f"valu probe kind {kind}: {4 * n_cu * 2.4e6 * ms / n:.2f} cycles per wave64 instruction at 2.4 GHz")
 
 
+def test_time_blend_closed_form(S):
+    """Two slices of a uniform flow, V1 = 2 V0, slice_dt = 8: the velocity grows linearly in
+    time, RK4 integrates it exactly (Simpson's rule), and with dyadic data every vertex equals
+    P0 + c (t + t^2 / 16) bit for bit -- for FP32 node rows and cell records and FP16 nodes."""
+    import dataclasses
+    note("time blend closed form")
+    c = np.array([0.375, -0.25, 0.125])
+    base = fg.closed_form_block(lambda x, y, z: (0 * x + c[0], 0 * x + c[1], 0 * x + c[2]), (16, 16, 16),
+                                ghost=1, origin=(0.5, 0.5, 0.5), lo=(0, 0, 0), hi=(16, 16, 16))
+    vals = np.concatenate([base.values, 2.0 * base.values])
+    rng = np.random.default_rng(8)
+    seeds = (4.0 + rng.integers(0, 6 * 32, size=(300, 3)) / 32.0).astype(np.float32)  # stay inside
+    h, steps, dt = 0.5, 16, 8.0
+    t = np.arange(steps + 1) * h
+    for fmt, layout in ((fg.F32, S.LAYOUT_LINEAR), (fg.F32, S.LAYOUT_CELL), (fg.F16, S.LAYOUT_LINEAR)):
+        blk = dataclasses.replace(base, values=vals, n_slices=2, slice_dt=dt, t0=0.0).quantise(fmt)
+        f, lines, ob, st = run(S, [blk], [seeds], h, steps, fmt, layout=layout)
+        assert st.steps == len(seeds) * steps and (lines[0]["codes"] == S.MAX_STEPS).all()
+        for i, seg in enumerate(parity.split_lines(lines[0])):
+            want = seeds[i].astype(np.float64) + (t + t * t / (2 * dt))[:, None] * c
+            np.testing.assert_array_equal(seg, want, err_msg=f"{fg.DTYPE_NAMES[fmt]} layout {layout}")
+
+
 def test_solid_body_rotation_closed_form(S):
     """v = w(-(y-3), x-3, 0) lies in the trilinear span: vertices follow R(hA)^n exactly up
     to FP32 rounding (circles shrinking by the RK4 radius factor)."""
