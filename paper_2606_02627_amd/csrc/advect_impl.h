@@ -8,8 +8,9 @@
 // that leave go to the outbox with destinationID() of their new position
 // (Sec. 3.1.1), others append a polyline vertex (Sec. 3.2, assembleOutput).
 //
-// gfx950 design (measured: the kernel is VALU-issue bound once the field is
-// cached, so the per-step instruction count is what matters):
+// gfx950 design (measured: a lane's step is a chain of dependent instructions
+// and cell-cache refills, so instruction count and latency are what matter;
+// the 16-bit kernels at 512^3 keep the VALU busy, the FP32 one does not):
 //  * one lane per particle, persistent grid; a wave refills its free lanes
 //    from per-XCD work queues over a spatially sorted order, with one atomic
 //    per refill (ballot + mbcnt), so long and short trajectories share waves;
@@ -18,11 +19,13 @@
 //    fields the packed corners of the two bracketing slices; a particle moves
 //    ~0.1-0.3 cells per step, so most samples re-use them and only a cell
 //    change issues the gather;
+//  * FP32 fields are stored by default as one 96-byte record of coefficients
+//    per cell (the cell layout), so a refill is six 16-byte loads and no
+//    arithmetic; node rows hold FP32 (12 B) or FP16/BF16 nodes padded to 8 B;
 //  * addresses are 32-bit byte offsets from a per-block base (uniform for a
-//    single block), the byte offset of the cell's first corner doubles as the
-//    cache key, and cell location is branch-free (med3 domain test and clamp);
-//  * nodes are FP32 (12 B) or FP16/BF16 padded to 8 B, so a node is one
-//    aligned load; 16-bit values are widened in registers, all arithmetic FP32;
+//    single block), the byte offset of the cell's first corner (or record)
+//    doubles as the cache key, and cell location is branch-free (med3 domain
+//    test and clamp), skipped for whole steps that start deep inside a block;
 //  * vertices go to a log in wave-aggregated runs inside 8192-record chunks,
 //    outbox records with one atomic per wave and event.
 #pragma once
