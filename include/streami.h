@@ -246,8 +246,10 @@ typedef struct {
 /*
  * Move up to `cap` outbox records into `out` (host or device memory,
  * detected) and remove them from the outbox; *n_out = records copied.  Record
- * order is unspecified.  If more records remain than cap, the first cap are
- * copied and the call returns E_CAPACITY with *n_out = cap; the rest stay.
+ * order is unspecified.  If more records remain than cap, cap of them are
+ * copied and the call returns E_CAPACITY with *n_out = cap; the rest stay for
+ * the next call.  Waits for the handle's stream.  Errors: E_ARG (NULL handle,
+ * n_out, or out with records to copy; cap < 0), E_CAPACITY, E_DEVICE.
  */
 int streami_fetch_outbox(streami_field f, streami_outbox_rec* out, int64_t cap, int64_t* n_out);
 
