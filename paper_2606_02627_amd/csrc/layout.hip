@@ -138,7 +138,10 @@ int launch_ingest(const void* src, void* pool, const BlockDev& B, int fmt, int l
 // the seed as vertex 0 of its line to the vertex log (one atomic per wave); a
 // seed outside the owned bounds of a non-periodic block ends at once (EXIT,
 // 0 steps) and goes to the outbox.
-__global__ void k_seed(const float* xyz, const unsigned long long* ids, unsigned long long auto_id0,
+constexpr int SEED_THREADS = 1024;  // one log reservation per 16 waves
+
+__global__ void __launch_bounds__(SEED_THREADS) k_seed(const float* xyz, const unsigned long long* ids,
+                       unsigned long long auto_id0,
                        const int* max_steps, int default_max, int stride, float t_birth, const float* t_births, int blk,
                        BlockDev B, long long first, long long n, float4* pos, int4* meta, int4* meta2,
                        unsigned long long* pid, VertexLog log, OutRec* outbox, unsigned long long* outbox_count) {
@@ -161,21 +164,30 @@ __global__ void k_seed(const float* xyz, const unsigned long long* ids, unsigned
     pid[q] = id;
     emit = out;
   }
-  // vertex 0 of every new line (the host sized the log for it)
+  // vertex 0 of every new line (the host sized the log for it): one
+  // reservation per workgroup, so that a million seeds do not serialise on
+  // the log counter
+  __shared__ unsigned s_cnt[SEED_THREADS / 64];
+  __shared__ unsigned long long s_base;
   const unsigned long long vm = __ballot(i < n);
-  if (vm) {
-    const int lane = __lane_id();
-    unsigned long long b = 0;
-    if (lane == 0) b = atomicAdd(log.count, (unsigned long long)__popcll(vm));
-    b = __shfl(b, 0, 64);
-    if (i < n) {
-      const unsigned long long r = b + __builtin_amdgcn_mbcnt_hi((unsigned)(vm >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)vm, 0u));
-      if (r < (unsigned long long)log.cap) {
-        log.v[r] = make_float4(x.x, x.y, x.z, __uint_as_float((unsigned)q));
-        log.j[r] = 0u;
-      }
+  const int wv = threadIdx.x >> 6, lane = __lane_id();
+  if (lane == 0) s_cnt[wv] = (unsigned)__popcll(vm);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned tot = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += s_cnt[w];
+    s_base = tot ? atomicAdd(log.count, (unsigned long long)tot) : 0ull;
+    if (blockIdx.x == 0) atomicAdd(log.real, (unsigned long long)n);
+  }
+  __syncthreads();
+  if (i < n) {
+    unsigned long long r = s_base;
+    for (int w = 0; w < wv; ++w) r += s_cnt[w];
+    r += __builtin_amdgcn_mbcnt_hi((unsigned)(vm >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)vm, 0u));
+    if (r < (unsigned long long)log.cap) {
+      log.v[r] = make_float4(x.x, x.y, x.z, __uint_as_float((unsigned)q));
+      log.j[r] = 0u;
     }
-    if (lane == 0) atomicAdd(log.real, (unsigned long long)__popcll(vm));
   }
   const unsigned long long em = __ballot(emit);
   if (em) {
@@ -210,8 +222,9 @@ int launch_seed(const float* xyz, const unsigned long long* ids, unsigned long l
                 unsigned long long* pid, const VertexLog& log, OutRec* outbox,
                 unsigned long long* outbox_count, hipStream_t st) {
   if (n <= 0) return 0;
-  const long long grid = (n + 255) / 256;
-  hipLaunchKernelGGL(k_seed, dim3((unsigned)grid), dim3(256), 0, st, xyz, ids, auto_id0, max_steps, default_max,
+  const long long grid = (n + SEED_THREADS - 1) / SEED_THREADS;
+  hipLaunchKernelGGL(k_seed, dim3((unsigned)grid), dim3(SEED_THREADS), 0, st, xyz, ids, auto_id0, max_steps,
+                     default_max,
                      stride, t_birth, t_births, blk, B, first, n, pos, meta, meta2, pid, log, outbox, outbox_count);
   return 0;
 }
