@@ -256,8 +256,8 @@ def batched_bench(args, unsteady=False):
         With stats: the last call's stats and the sums over the pass's advect calls of
         steps, vertices and device time."""
         f.clear()
-        for b in range(len(blocks)):
-            f.seed(b, dseeds[b], max_steps=dlim[b], record_stride=stride, t_births=dtb[b] if dtb else None)
+        f.seed_batches([dict(block=b, xyz=dseeds[b], max_steps=dlim[b], t_births=dtb[b] if dtb else None)
+                        for b in range(len(blocks))], record_stride=stride)
         tot = dict(steps=0, vertices=0, dev_ms=0.0)
         for te in (t_ends or [None]):
             kw = dict(use_graph=1) if te is None else dict(t_end=te)

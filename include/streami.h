@@ -166,6 +166,27 @@ typedef struct {
 int streami_seed(streami_field f, int32_t block, const float* xyz, const uint64_t* ids,
                  const int32_t* max_steps, int64_t n, const streami_seed_opts* opts);
 
+/* One seed batch of streami_seed_batches(): the arguments of one
+ * streami_seed() call (birth times per batch instead of in the options). */
+typedef struct {
+  int32_t block;
+  const float* xyz;         /* n*3 positions */
+  const uint64_t* ids;      /* n ids or NULL */
+  const int32_t* max_steps; /* n limits or NULL */
+  const float* t_births;    /* n birth times or NULL (then opts->t_birth) */
+  int64_t n;
+} streami_seed_batch;
+
+/*
+ * Seed several batches (e.g. one per block of a batched launch) with shared
+ * options: the same particles, ids and lines as n_batches consecutive
+ * streami_seed() calls, but one device reduction of all step limits and at
+ * most one wait instead of one per call.  opts->t_births must be NULL.  On
+ * an error nothing is seeded.  Errors: as streami_seed(), naming the batch.
+ */
+int streami_seed_batches(streami_field f, const streami_seed_batch* batches, int32_t n_batches,
+                         const streami_seed_opts* opts);
+
 typedef struct {
   float h;                  /* step size in world units per unit time, > 0 */
   int32_t step_budget;      /* >0: at most this many steps per particle in this call (step());

@@ -55,6 +55,11 @@ class SeedOpts(ctypes.Structure):
                 ("t_births", ctypes.c_void_p)]
 
 
+class SeedBatch(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("xyz", ctypes.c_void_p), ("ids", ctypes.c_void_p),
+                ("max_steps", ctypes.c_void_p), ("t_births", ctypes.c_void_p), ("n", ctypes.c_int64)]
+
+
 class AdvectParams(ctypes.Structure):
     _fields_ = [("h", ctypes.c_float), ("step_budget", ctypes.c_int32),
                 ("stagnation_eps", ctypes.c_float), ("mode", ctypes.c_int32),
@@ -99,6 +104,7 @@ def _load():
         "streami_field_create": [vp, i32, i32, vp, vp, vp],
         "streami_field_destroy": [vp],
         "streami_seed": [vp, i32, vp, vp, vp, i64, vp],
+        "streami_seed_batches": [vp, vp, i32, vp],
         "streami_advect": [vp, vp, vp],
         "streami_fetch_lines": [vp, i32, i64, i64, vp, vp, i64, vp, vp, vp, vp],
         "streami_fetch_outbox": [vp, vp, i64, vp],
@@ -207,6 +213,32 @@ def streami_seed(f, block, xyz, ids=None, max_steps=None, default_max_steps=0, r
     return _check(_load().streami_seed(f, int(block), px, pi, pm, int(n), ctypes.byref(opts)))
 
 
+def streami_seed_batches(f, batches, default_max_steps=0, record_stride=1, t_birth=0.0):
+    """Seed several batches with shared options; each batch is a dict with block, xyz and
+    optionally ids, max_steps, t_births (all host or all device arrays, like streami_seed)."""
+    arr = (SeedBatch * max(1, len(batches)))()
+    on_dev = None
+    for k, b in enumerate(batches):
+        xyz = b["xyz"]
+        px, dx = _addr(xyz)
+        parts = [_addr(b.get(key)) for key in ("ids", "max_steps", "t_births")]
+        for key, (_, d) in zip(("ids", "max_steps", "t_births"), parts):
+            if b.get(key) is not None and d != dx:
+                raise ValueError("a batch's arrays must all be host or all device arrays")
+        if on_dev is None:
+            on_dev = dx
+        elif dx != on_dev:
+            raise ValueError("all batches must be host or all device arrays")
+        n = (xyz.numel() if hasattr(xyz, "numel") else xyz.size) // 3
+        arr[k].block = int(b["block"])
+        arr[k].xyz = px.value
+        arr[k].ids, arr[k].max_steps, arr[k].t_births = (None if p is None else p.value for p, _ in parts)
+        arr[k].n = int(n)
+    opts = SeedOpts(default_max_steps=int(default_max_steps), record_stride=int(record_stride),
+                    inputs_on_device=int(bool(on_dev)), t_birth=float(t_birth), t_births=None)
+    return _check(_load().streami_seed_batches(f, arr, len(batches), ctypes.byref(opts)))
+
+
 def streami_advect(f, params: AdvectParams, want_stats=True):
     st = Stats() if want_stats else None
     _check(_load().streami_advect(f, ctypes.byref(params), ctypes.byref(st) if st else None))
@@ -313,6 +345,9 @@ class Field:
 
     def seed(self, block, xyz, **kw):
         return streami_seed(self.h, block, xyz, **kw)
+
+    def seed_batches(self, batches, **kw):
+        return streami_seed_batches(self.h, batches, **kw)
 
     def advect(self, h, **kw):
         return streami_advect(self.h, advect_params(h, **kw))

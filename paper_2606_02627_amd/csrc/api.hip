@@ -572,47 +572,68 @@ int streami_field_destroy(streami_field f) {
   return STREAMI_OK;
 }
 
-int streami_seed(streami_field f, int32_t block, const float* xyz, const uint64_t* ids, const int32_t* max_steps,
-                 int64_t n, const streami_seed_opts* opts) {
-  if (!f) return fail(STREAMI_E_ARG, "field handle is NULL");
-  if (block < 0 || block >= (int)f->blocks.size()) return fail(STREAMI_E_ARG, "block %d out of range", block);
-  if (n < 0) return fail(STREAMI_E_ARG, "n must be >= 0");
-  if (n == 0) return STREAMI_OK;
-  if (f->n_particles + n >= (1LL << 31)) return fail(STREAMI_E_ARG, "more than 2^31 particles per handle");
-  if (!xyz) return fail(STREAMI_E_ARG, "xyz is NULL");
+}  // extern "C"
+
+namespace {
+
+// Seeding of one or several batches, as consecutive streami_seed() calls
+// would do them, with one reduction and at most one wait for all batches.
+int seed_batches(streami_field_s* f, const streami_seed_batch* bt, int nb, const streami_seed_opts* opts) {
   if (!opts) return fail(STREAMI_E_ARG, "opts is NULL");
   if (opts->record_stride < 1) return fail(STREAMI_E_ARG, "record_stride must be >= 1");
-  if (!max_steps && opts->default_max_steps < 0) return fail(STREAMI_E_ARG, "default_max_steps must be >= 0");
   const bool dev_in = opts->inputs_on_device != 0;
-  // per-particle limits on the host, to reserve vertex slots
-  // every particle may record at most max_steps/stride + 2 vertices
+  long long total = 0;
+  bool any_dev_ms = false;
+  for (int k = 0; k < nb; ++k) {
+    const streami_seed_batch& b = bt[k];
+    if (b.block < 0 || b.block >= (int)f->blocks.size())
+      return fail(STREAMI_E_ARG, "batch %d: block %d out of range", k, b.block);
+    if (b.n < 0) return fail(STREAMI_E_ARG, "batch %d: n must be >= 0", k);
+    if (b.n == 0) continue;
+    if (!b.xyz) return fail(STREAMI_E_ARG, "batch %d: xyz is NULL", k);
+    if (!b.max_steps && opts->default_max_steps < 0) return fail(STREAMI_E_ARG, "default_max_steps must be >= 0");
+    total += b.n;
+    any_dev_ms = any_dev_ms || (b.max_steps && dev_in);
+  }
+  if (total == 0) return STREAMI_OK;
+  if (f->n_particles + total >= (1LL << 31)) return fail(STREAMI_E_ARG, "more than 2^31 particles per handle");
+  // every particle may record at most max_steps/stride + 2 vertices: reserve
+  // that in the log; limits on the device are reduced on the device, all
+  // batches into one accumulator (24 bytes come back, one wait)
   long long bound = 0;
   int batch_max = 0;
   int rc;
-  if (max_steps && dev_in) {  // reduce on the device; 24 bytes come back
+  if (any_dev_ms) {
     if ((rc = f->d_seedred.reserve(32, 0, f->stream))) return rc;
     if (!f->h_seedred && hipHostMalloc((void**)&f->h_seedred, 32, hipHostMallocDefault) != hipSuccess) {
       f->h_seedred = nullptr;
       return fail(STREAMI_E_NOMEM, "pinned host allocation failed");
     }
-    launch_seed_bound(max_steps, n, opts->record_stride, (unsigned long long*)f->d_seedred.p, f->stream);
+    launch_fill_u64((unsigned long long*)f->d_seedred.p, 3, 0, f->stream);
+    for (int k = 0; k < nb; ++k)
+      if (bt[k].n > 0 && bt[k].max_steps)
+        launch_seed_bound(bt[k].max_steps, bt[k].n, opts->record_stride, (unsigned long long*)f->d_seedred.p,
+                          f->stream);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(f->h_seedred, f->d_seedred.p, 24, hipMemcpyDeviceToHost, f->stream));
     HIP_TRY(hipStreamSynchronize(f->stream));
     if (f->h_seedred[2]) return fail(STREAMI_E_ARG, "max_steps has a negative entry");
     bound = (long long)f->h_seedred[0];
     batch_max = (int)f->h_seedred[1];
-  } else {
-    for (long long i = 0; i < n; ++i) {
-      const int m = max_steps ? max_steps[i] : opts->default_max_steps;
-      if (m < 0) return fail(STREAMI_E_ARG, "max_steps[%lld] < 0", i);
+  }
+  for (int k = 0; k < nb; ++k) {
+    const streami_seed_batch& b = bt[k];
+    if (b.n == 0 || (b.max_steps && dev_in)) continue;
+    for (long long i = 0; i < b.n; ++i) {
+      const int m = b.max_steps ? b.max_steps[i] : opts->default_max_steps;
+      if (m < 0) return fail(STREAMI_E_ARG, "batch %d: max_steps[%lld] < 0", k, i);
       bound += m / opts->record_stride + 2;
       batch_max = std::max(batch_max, m);
     }
   }
   drop_graph(f);
-  if ((rc = ensure_particles(f, f->n_particles + n))) return rc;
-  // Seeding k particles inside the block adds k records and k real vertices
+  if ((rc = ensure_particles(f, f->n_particles + total))) return rc;
+  // Seeding k particles inside a block adds k records and k real vertices
   // and raises vert_bound by `bound` >= k, so the need grows by at most
   // bound + bound/8 + 1: while the host bound covers that, no read-back.
   const long long grow = bound + bound / 8 + 1;
@@ -623,46 +644,78 @@ int streami_seed(streami_field f, int32_t block, const float* xyz, const uint64_
     f->vert_bound -= bound;
     return rc;
   }
-  const long long first = f->n_particles;
-  // stage host inputs on the device
-  DevBuf s_xyz, s_ids, s_ms, s_tb;
-  const float* d_tb = opts->t_births;
-  const float* d_xyz = xyz;
-  const unsigned long long* d_ids = reinterpret_cast<const unsigned long long*>(ids);
-  const int* d_ms = max_steps;
-  if (!dev_in) {
-    if ((rc = s_xyz.reserve(n * 12, 0, f->stream))) return rc;
-    HIP_TRY(hipMemcpyAsync(s_xyz.p, xyz, n * 12, hipMemcpyHostToDevice, f->stream));
-    d_xyz = (const float*)s_xyz.p;
-    if (ids) {
-      if ((rc = s_ids.reserve(n * 8, 0, f->stream))) return rc;
-      HIP_TRY(hipMemcpyAsync(s_ids.p, ids, n * 8, hipMemcpyHostToDevice, f->stream));
-      d_ids = (const unsigned long long*)s_ids.p;
+  // stage host inputs on the device (kept until the one wait below)
+  std::vector<DevBuf> stage(dev_in ? 0 : 4 * (size_t)nb);
+  for (int k = 0; k < nb; ++k) {
+    const streami_seed_batch& b = bt[k];
+    if (b.n == 0) continue;
+    const float* d_tb = b.t_births;
+    const float* d_xyz = b.xyz;
+    const unsigned long long* d_ids = reinterpret_cast<const unsigned long long*>(b.ids);
+    const int* d_ms = b.max_steps;
+    if (!dev_in) {
+      DevBuf* sb = &stage[4 * (size_t)k];
+      if ((rc = sb[0].reserve(b.n * 12, 0, f->stream))) return rc;
+      HIP_TRY(hipMemcpyAsync(sb[0].p, b.xyz, b.n * 12, hipMemcpyHostToDevice, f->stream));
+      d_xyz = (const float*)sb[0].p;
+      if (b.ids) {
+        if ((rc = sb[1].reserve(b.n * 8, 0, f->stream))) return rc;
+        HIP_TRY(hipMemcpyAsync(sb[1].p, b.ids, b.n * 8, hipMemcpyHostToDevice, f->stream));
+        d_ids = (const unsigned long long*)sb[1].p;
+      }
+      if (b.max_steps) {
+        if ((rc = sb[2].reserve(b.n * 4, 0, f->stream))) return rc;
+        HIP_TRY(hipMemcpyAsync(sb[2].p, b.max_steps, b.n * 4, hipMemcpyHostToDevice, f->stream));
+        d_ms = (const int*)sb[2].p;
+      }
+      if (b.t_births) {
+        if ((rc = sb[3].reserve(b.n * 4, 0, f->stream))) return rc;
+        HIP_TRY(hipMemcpyAsync(sb[3].p, b.t_births, b.n * 4, hipMemcpyHostToDevice, f->stream));
+        d_tb = (const float*)sb[3].p;
+      }
     }
-    if (max_steps) {
-      if ((rc = s_ms.reserve(n * 4, 0, f->stream))) return rc;
-      HIP_TRY(hipMemcpyAsync(s_ms.p, max_steps, n * 4, hipMemcpyHostToDevice, f->stream));
-      d_ms = (const int*)s_ms.p;
-    }
-    if (opts->t_births) {
-      if ((rc = s_tb.reserve(n * 4, 0, f->stream))) return rc;
-      HIP_TRY(hipMemcpyAsync(s_tb.p, opts->t_births, n * 4, hipMemcpyHostToDevice, f->stream));
-      d_tb = (const float*)s_tb.p;
-    }
+    HostBlock& hb = f->blocks[b.block];
+    const long long first = f->n_particles;
+    launch_seed(d_xyz, d_ids, f->next_auto_id, d_ms, opts->default_max_steps, opts->record_stride, opts->t_birth,
+                d_tb, b.block, hb.dev, first, b.n, (float4*)f->d_pos.p, (int4*)f->d_meta.p, (int4*)f->d_meta2.p,
+                (unsigned long long*)f->d_ids.p, f->log(), (OutRec*)f->d_outbox.p, f->outbox_count(), f->stream);
+    HIP_TRY(hipGetLastError());
+    if (!b.ids) f->next_auto_id += (unsigned long long)b.n;
+    f->n_particles += b.n;
+    hb.ranges.push_back({first, b.n});
+    hb.n_particles += b.n;
   }
-  HostBlock& hb = f->blocks[block];
-  launch_seed(d_xyz, d_ids, f->next_auto_id, d_ms, opts->default_max_steps, opts->record_stride, opts->t_birth, d_tb,
-              block, hb.dev, first, n, (float4*)f->d_pos.p, (int4*)f->d_meta.p, (int4*)f->d_meta2.p,
-              (unsigned long long*)f->d_ids.p, f->log(), (OutRec*)f->d_outbox.p, f->outbox_count(), f->stream);
-  HIP_TRY(hipGetLastError());
   if (!dev_in) HIP_TRY(hipStreamSynchronize(f->stream));  // staging buffers are freed on return
-  if (!ids) f->next_auto_id += (unsigned long long)n;
-  f->n_particles += n;
   f->max_m = std::max(f->max_m, batch_max);
   if (opts->record_stride % 16 != 0) f->strides_mult16 = false;
-  hb.ranges.push_back({first, n});
-  hb.n_particles += n;
   return STREAMI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int streami_seed(streami_field f, int32_t block, const float* xyz, const uint64_t* ids, const int32_t* max_steps,
+                 int64_t n, const streami_seed_opts* opts) {
+  if (!f) return fail(STREAMI_E_ARG, "field handle is NULL");
+  if (n == 0 && block >= 0 && block < (int)f->blocks.size()) return STREAMI_OK;
+  streami_seed_batch b;
+  b.block = block;
+  b.xyz = xyz;
+  b.ids = ids;
+  b.max_steps = max_steps;
+  b.t_births = opts ? opts->t_births : nullptr;
+  b.n = n;
+  return seed_batches(f, &b, 1, opts);
+}
+
+int streami_seed_batches(streami_field f, const streami_seed_batch* batches, int32_t n_batches,
+                         const streami_seed_opts* opts) {
+  if (!f) return fail(STREAMI_E_ARG, "field handle is NULL");
+  if (n_batches < 0 || (n_batches > 0 && !batches)) return fail(STREAMI_E_ARG, "batches is NULL or n_batches < 0");
+  if (n_batches == 0) return STREAMI_OK;
+  if (opts && opts->t_births) return fail(STREAMI_E_ARG, "opts->t_births: give birth times per batch");
+  return seed_batches(f, batches, n_batches, opts);
 }
 
 int streami_advect(streami_field f, const streami_advect_params* p, streami_stats* stats) {

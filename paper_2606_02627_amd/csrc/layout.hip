@@ -319,8 +319,8 @@ __global__ void k_seed_bound(const int* ms, long long n, int stride, unsigned lo
   }
 }
 
+// accumulates into out (sum, max, negative flag): the caller clears it
 int launch_seed_bound(const int* ms, long long n, int stride, unsigned long long* out, hipStream_t st) {
-  launch_fill_u64(out, 3, 0, st);
   long long grid = (n + 255) / 256;
   if (grid > 1024) grid = 1024;
   if (grid < 1) grid = 1;

@@ -88,6 +88,7 @@ def test_calls_on_null_handle_fail_cleanly():
     assert lib.streami_advect(null, None, None) == S.E_ARG
     assert lib.streami_fetch_outbox(null, None, 0, None) == S.E_ARG
     assert lib.streami_fetch_lines(null, 0, 0, 0, None, None, 0, None, None, None, None) == S.E_ARG
+    assert lib.streami_seed_batches(null, None, 1, None) == S.E_ARG
     assert lib.streami_field_destroy(null) == S.OK
     assert b"NULL" in lib.streami_last_error()
 
@@ -114,7 +115,8 @@ def test_probe_rejects_invalid_arguments_before_device_work():
 
 
 STRUCTS = [("streami_block_desc", "BlockDesc"), ("streami_field_opts", "FieldOpts"),
-           ("streami_seed_opts", "SeedOpts"), ("streami_advect_params", "AdvectParams"),
+           ("streami_seed_opts", "SeedOpts"), ("streami_seed_batch", "SeedBatch"),
+           ("streami_advect_params", "AdvectParams"),
            ("streami_stats", "Stats")]
 
 

@@ -408,6 +408,41 @@ def test_unsteady_parity(S):
     np.testing.assert_array_equal(lines[0]["codes"][~sens], ref["code"][~sens])
 
 
+def test_seed_batches_equal_consecutive_seeds(S):
+    """streami_seed_batches gives the same particles, ids, lines and outbox as one
+    streami_seed call per batch (device and host inputs, per-batch birth times, auto ids)."""
+    import torch
+    note("seed batches")
+    rng = np.random.default_rng(17)
+    blocks, seeds, ms, tbs = [], [], [], []
+    for b in range(6):
+        dims = tuple(int(v) for v in rng.integers(10, 24, size=3))
+        blocks.append(fg.turbulence_block(4, dims=dims, fmt=fg.F16, sub=30 + b, rank_grid=(1, 1, 1),
+                                          rank_coord=(0, 0, 0), n_slices=2, slice_dt=60.0))
+        n = int(rng.integers(1, 500))
+        seeds.append(fg.uniform_seeds(4, n, (-1, -1, -1), tuple(d + 1 for d in dims), sub=300 + b))
+        ms.append(rng.integers(0, 200, size=n).astype(np.int32))
+        tbs.append((rng.integers(0, 8, size=n) * 0.5).astype(np.float32))
+    order = [3, 0, 5, 1, 4, 2, 0]  # uneven order, a block seeded twice
+    for dev in (True, False):
+        conv = (lambda a: torch.from_numpy(a).cuda()) if dev else (lambda a: a)
+        a = S.Field(blocks, fg.F16)
+        for b in order:
+            a.seed(b, conv(seeds[b]), max_steps=conv(ms[b]), t_births=conv(tbs[b]), record_stride=3)
+        a.advect(0.5)
+        c = S.Field(blocks, fg.F16)
+        c.seed_batches([dict(block=b, xyz=conv(seeds[b]), max_steps=conv(ms[b]), t_births=conv(tbs[b]))
+                        for b in order], record_stride=3)
+        c.advect(0.5)
+        for b in range(len(blocks)):
+            la, lc = a.lines(b), c.lines(b)
+            for k in ("offsets", "xyz", "steps", "codes", "ids"):
+                np.testing.assert_array_equal(la[k], lc[k])
+        np.testing.assert_array_equal(np.sort(a.outbox(), order="id"), np.sort(c.outbox(), order="id"))
+        a.close()
+        c.close()
+
+
 def test_cell_records_periodic_batched_unsteady(S):
     """Cell records (FP32 interpolant coefficients per cell) on the other paths: the
     periodic ABC block (records wrap across the domain) and several blocks in one launch
