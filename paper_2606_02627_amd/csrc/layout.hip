@@ -322,7 +322,7 @@ __global__ void k_seed_bound(const int* ms, long long n, int stride, unsigned lo
 // accumulates into out (sum, max, negative flag): the caller clears it
 int launch_seed_bound(const int* ms, long long n, int stride, unsigned long long* out, hipStream_t st) {
   long long grid = (n + 255) / 256;
-  if (grid > 1024) grid = 1024;
+  if (grid > 64) grid = 64;  // grid-stride: few waves, so few contended atomics on the three results
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL(k_seed_bound, dim3((unsigned)grid), dim3(256), 0, st, ms, n, stride, out);
   return 0;
