@@ -181,8 +181,9 @@ typedef struct {
  * Seed several batches (e.g. one per block of a batched launch) with shared
  * options: the same particles, ids and lines as n_batches consecutive
  * streami_seed() calls, but one device reduction of all step limits and at
- * most one wait instead of one per call.  opts->t_births must be NULL.  On
- * an error nothing is seeded.  Errors: as streami_seed(), naming the batch.
+ * most one wait instead of one per call (and one seeding launch per 48
+ * batches).  opts->t_births must be NULL.  Every argument error is found
+ * before anything is seeded.  Errors: as streami_seed(), naming the batch.
  */
 int streami_seed_batches(streami_field f, const streami_seed_batch* batches, int32_t n_batches,
                          const streami_seed_opts* opts);

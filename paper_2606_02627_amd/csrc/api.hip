@@ -28,11 +28,9 @@ int launch_surrogate_bf16(const SurrogateArgs& s, int layout, bool periodic, boo
 int mlp_forward_rows(streami_mlp m, const float* xyz, int xstride, long long n, float* out, hipStream_t st);
 int launch_ingest(const void* src, void* pool, const BlockDev& B, int fmt, int layout, int nx, int ny, int nz,
                   int n_slices, hipStream_t st);
-int launch_seed(const float* xyz, const unsigned long long* ids, unsigned long long auto_id0, const int* max_steps,
-                int default_max, int stride, float t_birth, const float* t_births, int blk, const BlockDev& B,
-                long long first,
-                long long n, float4* pos, int4* meta, int4* meta2, unsigned long long* pid, const VertexLog& log,
-                OutRec* outbox, unsigned long long* outbox_count, hipStream_t st);
+int launch_seed(const SeedJobs& J, unsigned n_wg, const BlockDev* blocks, float4* pos, int4* meta, int4* meta2,
+                unsigned long long* pid, const VertexLog& log, OutRec* outbox, unsigned long long* outbox_count,
+                hipStream_t st);
 int launch_scatter_lines(const VertexLog& log, long long n_rec, long long n_particles, const int* row_of,
                          const long long* offsets, float* out, hipStream_t st);
 int launch_mark_rows(const long long* idx, long long count, int* row_of, hipStream_t st);
@@ -42,7 +40,7 @@ int launch_work_order(const float4* pos, const int4* meta, const int4* meta2, co
                       int bits, unsigned n_buckets, float h, float t_end, unsigned* key, unsigned* hist,
                       unsigned* cursor, int* order, unsigned* n_work, hipStream_t st);
 int launch_fill_u64(unsigned long long* p, long long n, unsigned long long v, hipStream_t st);
-int launch_seed_bound(const int* ms, long long n, int stride, unsigned long long* out, hipStream_t st);
+int launch_seed_bound(const SeedJobs& J, long long total, unsigned long long* out, hipStream_t st);
 int launch_gather_meta(const long long* idx, long long count, const int4* meta, const int4* meta2,
                        const unsigned long long* pid, long long* nverts, int* steps, int* codes,
                        unsigned long long* ids, hipStream_t st);
@@ -610,10 +608,23 @@ int seed_batches(streami_field_s* f, const streami_seed_batch* bt, int nb, const
       return fail(STREAMI_E_NOMEM, "pinned host allocation failed");
     }
     launch_fill_u64((unsigned long long*)f->d_seedred.p, 3, 0, f->stream);
-    for (int k = 0; k < nb; ++k)
-      if (bt[k].n > 0 && bt[k].max_steps)
-        launch_seed_bound(bt[k].max_steps, bt[k].n, opts->record_stride, (unsigned long long*)f->d_seedred.p,
-                          f->stream);
+    SeedJobs J;
+    std::memset(&J, 0, sizeof J);
+    J.stride = opts->record_stride;
+    long long part = 0;
+    for (int k = 0; k <= nb; ++k) {
+      if (k < nb && bt[k].n > 0 && bt[k].max_steps) {
+        J.j[J.n_jobs].max_steps = bt[k].max_steps;
+        J.j[J.n_jobs].n = bt[k].n;
+        ++J.n_jobs;
+        part += bt[k].n;
+      }
+      if (J.n_jobs == SEED_JOBS || (k == nb && J.n_jobs > 0)) {
+        launch_seed_bound(J, part, (unsigned long long*)f->d_seedred.p, f->stream);
+        J.n_jobs = 0;
+        part = 0;
+      }
+    }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(f->h_seedred, f->d_seedred.p, 24, hipMemcpyDeviceToHost, f->stream));
     HIP_TRY(hipStreamSynchronize(f->stream));
@@ -644,46 +655,65 @@ int seed_batches(streami_field_s* f, const streami_seed_batch* bt, int nb, const
     f->vert_bound -= bound;
     return rc;
   }
-  // stage host inputs on the device (kept until the one wait below)
+  // stage host inputs on the device (kept until the one wait below), then
+  // seed up to SEED_JOBS batches per launch
   std::vector<DevBuf> stage(dev_in ? 0 : 4 * (size_t)nb);
-  for (int k = 0; k < nb; ++k) {
-    const streami_seed_batch& b = bt[k];
-    if (b.n == 0) continue;
-    const float* d_tb = b.t_births;
-    const float* d_xyz = b.xyz;
-    const unsigned long long* d_ids = reinterpret_cast<const unsigned long long*>(b.ids);
-    const int* d_ms = b.max_steps;
-    if (!dev_in) {
-      DevBuf* sb = &stage[4 * (size_t)k];
-      if ((rc = sb[0].reserve(b.n * 12, 0, f->stream))) return rc;
-      HIP_TRY(hipMemcpyAsync(sb[0].p, b.xyz, b.n * 12, hipMemcpyHostToDevice, f->stream));
-      d_xyz = (const float*)sb[0].p;
-      if (b.ids) {
-        if ((rc = sb[1].reserve(b.n * 8, 0, f->stream))) return rc;
-        HIP_TRY(hipMemcpyAsync(sb[1].p, b.ids, b.n * 8, hipMemcpyHostToDevice, f->stream));
-        d_ids = (const unsigned long long*)sb[1].p;
+  SeedJobs J;
+  std::memset(&J, 0, sizeof J);
+  J.default_max = opts->default_max_steps;
+  J.stride = opts->record_stride;
+  J.t_birth = opts->t_birth;
+  unsigned n_wg = 0;
+  for (int k = 0; k <= nb; ++k) {
+    if (k < nb && bt[k].n > 0) {
+      const streami_seed_batch& b = bt[k];
+      SeedJob& jb = J.j[J.n_jobs];
+      jb.xyz = b.xyz;
+      jb.ids = reinterpret_cast<const unsigned long long*>(b.ids);
+      jb.max_steps = b.max_steps;
+      jb.t_births = b.t_births;
+      if (!dev_in) {
+        DevBuf* sb = &stage[4 * (size_t)k];
+        if ((rc = sb[0].reserve(b.n * 12, 0, f->stream))) return rc;
+        HIP_TRY(hipMemcpyAsync(sb[0].p, b.xyz, b.n * 12, hipMemcpyHostToDevice, f->stream));
+        jb.xyz = (const float*)sb[0].p;
+        if (b.ids) {
+          if ((rc = sb[1].reserve(b.n * 8, 0, f->stream))) return rc;
+          HIP_TRY(hipMemcpyAsync(sb[1].p, b.ids, b.n * 8, hipMemcpyHostToDevice, f->stream));
+          jb.ids = (const unsigned long long*)sb[1].p;
+        }
+        if (b.max_steps) {
+          if ((rc = sb[2].reserve(b.n * 4, 0, f->stream))) return rc;
+          HIP_TRY(hipMemcpyAsync(sb[2].p, b.max_steps, b.n * 4, hipMemcpyHostToDevice, f->stream));
+          jb.max_steps = (const int*)sb[2].p;
+        }
+        if (b.t_births) {
+          if ((rc = sb[3].reserve(b.n * 4, 0, f->stream))) return rc;
+          HIP_TRY(hipMemcpyAsync(sb[3].p, b.t_births, b.n * 4, hipMemcpyHostToDevice, f->stream));
+          jb.t_births = (const float*)sb[3].p;
+        }
       }
-      if (b.max_steps) {
-        if ((rc = sb[2].reserve(b.n * 4, 0, f->stream))) return rc;
-        HIP_TRY(hipMemcpyAsync(sb[2].p, b.max_steps, b.n * 4, hipMemcpyHostToDevice, f->stream));
-        d_ms = (const int*)sb[2].p;
-      }
-      if (b.t_births) {
-        if ((rc = sb[3].reserve(b.n * 4, 0, f->stream))) return rc;
-        HIP_TRY(hipMemcpyAsync(sb[3].p, b.t_births, b.n * 4, hipMemcpyHostToDevice, f->stream));
-        d_tb = (const float*)sb[3].p;
-      }
+      jb.first = f->n_particles;
+      jb.n = b.n;
+      jb.auto_id0 = f->next_auto_id;
+      jb.blk = b.block;
+      jb.wg0 = n_wg;
+      n_wg += (unsigned)((b.n + 1023) / 1024);
+      ++J.n_jobs;
+      HostBlock& hb = f->blocks[b.block];
+      if (!b.ids) f->next_auto_id += (unsigned long long)b.n;
+      f->n_particles += b.n;
+      hb.ranges.push_back({jb.first, b.n});
+      hb.n_particles += b.n;
     }
-    HostBlock& hb = f->blocks[b.block];
-    const long long first = f->n_particles;
-    launch_seed(d_xyz, d_ids, f->next_auto_id, d_ms, opts->default_max_steps, opts->record_stride, opts->t_birth,
-                d_tb, b.block, hb.dev, first, b.n, (float4*)f->d_pos.p, (int4*)f->d_meta.p, (int4*)f->d_meta2.p,
-                (unsigned long long*)f->d_ids.p, f->log(), (OutRec*)f->d_outbox.p, f->outbox_count(), f->stream);
-    HIP_TRY(hipGetLastError());
-    if (!b.ids) f->next_auto_id += (unsigned long long)b.n;
-    f->n_particles += b.n;
-    hb.ranges.push_back({first, b.n});
-    hb.n_particles += b.n;
+    if (J.n_jobs == SEED_JOBS || (k == nb && J.n_jobs > 0)) {
+      launch_seed(J, n_wg, (const BlockDev*)f->d_blocks.p, (float4*)f->d_pos.p, (int4*)f->d_meta.p,
+                  (int4*)f->d_meta2.p, (unsigned long long*)f->d_ids.p, f->log(), (OutRec*)f->d_outbox.p,
+                  f->outbox_count(), f->stream);
+      HIP_TRY(hipGetLastError());
+      J.n_jobs = 0;
+      n_wg = 0;
+    }
   }
   if (!dev_in) HIP_TRY(hipStreamSynchronize(f->stream));  // staging buffers are freed on return
   f->max_m = std::max(f->max_m, batch_max);

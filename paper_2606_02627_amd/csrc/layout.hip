@@ -140,27 +140,39 @@ int launch_ingest(const void* src, void* pool, const BlockDev& B, int fmt, int l
 // 0 steps) and goes to the outbox.
 constexpr int SEED_THREADS = 1024;  // one log reservation per 16 waves
 
-__global__ void __launch_bounds__(SEED_THREADS) k_seed(const float* xyz, const unsigned long long* ids,
-                       unsigned long long auto_id0,
-                       const int* max_steps, int default_max, int stride, float t_birth, const float* t_births, int blk,
-                       BlockDev B, long long first, long long n, float4* pos, int4* meta, int4* meta2,
-                       unsigned long long* pid, VertexLog log, OutRec* outbox, unsigned long long* outbox_count) {
-  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+// Initialise the particles of up to SEED_JOBS batches in one launch: each
+// batch (job) owns a run of workgroups starting at wg0, and its particle i
+// goes to slot first + i: positions, ids, limits; the seed is vertex 0 of its
+// line in the vertex log (one reservation per workgroup); a seed outside the
+// owned bounds of a non-periodic block ends at once (EXIT, 0 steps) and goes
+// to the outbox.
+__global__ void __launch_bounds__(SEED_THREADS) k_seed(SeedJobs J, const BlockDev* blocks, float4* pos,
+                                                       int4* meta, int4* meta2, unsigned long long* pid,
+                                                       VertexLog log, OutRec* outbox,
+                                                       unsigned long long* outbox_count) {
+  int jb = 0;  // the job of this workgroup (uniform): the last one starting at or before it
+  for (int j = 1; j < J.n_jobs; ++j)
+    if (J.j[j].wg0 <= blockIdx.x) jb = j;
+  const SeedJob& S = J.j[jb];
+  const long long i = (long long)(blockIdx.x - S.wg0) * blockDim.x + threadIdx.x;
+  const long long n = S.n;
+  const int blk = S.blk;
+  const BlockDev& B = blocks[blk];
   bool emit = false;
-  const long long q = first + i;
+  const long long q = S.first + i;
   float3 x = make_float3(0.f, 0.f, 0.f);
   unsigned long long id = 0;
   if (i < n) {
-    x = make_float3(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]);
-    id = ids ? ids[i] : auto_id0 + (unsigned long long)i;
-    const int m = max_steps ? max_steps[i] : default_max;
+    x = make_float3(S.xyz[3 * i], S.xyz[3 * i + 1], S.xyz[3 * i + 2]);
+    id = S.ids ? S.ids[i] : S.auto_id0 + (unsigned long long)i;
+    const int m = S.max_steps ? S.max_steps[i] : J.default_max;
     bool out = false;
     if (!B.periodic)
       out = !(x.x >= B.lo[0] && x.x < B.hi[0] && x.y >= B.lo[1] && x.y < B.hi[1] && x.z >= B.lo[2] &&
               x.z < B.hi[2]);
-    pos[q] = make_float4(x.x, x.y, x.z, t_births ? t_births[i] : t_birth);
+    pos[q] = make_float4(x.x, x.y, x.z, S.t_births ? S.t_births[i] : J.t_birth);
     meta[q] = make_int4(0, m, out ? EXIT : ACTIVE, 1);
-    meta2[q] = make_int4(stride, blk, m / stride + 2, 0);
+    meta2[q] = make_int4(J.stride, blk, m / J.stride + 2, 0);
     pid[q] = id;
     emit = out;
   }
@@ -177,7 +189,7 @@ __global__ void __launch_bounds__(SEED_THREADS) k_seed(const float* xyz, const u
     unsigned tot = 0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += s_cnt[w];
     s_base = tot ? atomicAdd(log.count, (unsigned long long)tot) : 0ull;
-    if (blockIdx.x == 0) atomicAdd(log.real, (unsigned long long)n);
+    if (blockIdx.x == S.wg0) atomicAdd(log.real, (unsigned long long)n);  // once per job
   }
   __syncthreads();
   if (i < n) {
@@ -215,17 +227,12 @@ __global__ void __launch_bounds__(SEED_THREADS) k_seed(const float* xyz, const u
   }
 }
 
-int launch_seed(const float* xyz, const unsigned long long* ids, unsigned long long auto_id0,
-                const int* max_steps, int default_max, int stride, float t_birth, const float* t_births, int blk,
-                const BlockDev& B,
-                long long first, long long n, float4* pos, int4* meta, int4* meta2,
-                unsigned long long* pid, const VertexLog& log, OutRec* outbox,
-                unsigned long long* outbox_count, hipStream_t st) {
-  if (n <= 0) return 0;
-  const long long grid = (n + SEED_THREADS - 1) / SEED_THREADS;
-  hipLaunchKernelGGL(k_seed, dim3((unsigned)grid), dim3(SEED_THREADS), 0, st, xyz, ids, auto_id0, max_steps,
-                     default_max,
-                     stride, t_birth, t_births, blk, B, first, n, pos, meta, meta2, pid, log, outbox, outbox_count);
+int launch_seed(const SeedJobs& J, unsigned n_wg, const BlockDev* blocks, float4* pos, int4* meta, int4* meta2,
+                unsigned long long* pid, const VertexLog& log, OutRec* outbox, unsigned long long* outbox_count,
+                hipStream_t st) {
+  if (J.n_jobs <= 0 || n_wg == 0) return 0;
+  hipLaunchKernelGGL(k_seed, dim3(n_wg), dim3(SEED_THREADS), 0, st, J, blocks, pos, meta, meta2, pid, log, outbox,
+                     outbox_count);
   return 0;
 }
 
@@ -293,17 +300,22 @@ __global__ void k_fill_u64(unsigned long long* p, long long n, unsigned long lon
 
 int launch_fill_u64(unsigned long long* p, long long n, unsigned long long v, hipStream_t st);
 
-// Vertex bound of a seed batch whose step limits are on the device:
-// out[0] += sum(m / stride + 2), out[1] = max(out[1], m), out[2] |= (any m < 0).
-__global__ void k_seed_bound(const int* ms, long long n, int stride, unsigned long long* out) {
+// Vertex bound of the jobs' device step limits: sum of m/stride + 2, the
+// largest m, and a flag for a negative m, accumulated into out[0..2] (the
+// caller clears it); grid-stride over every job in turn
+__global__ void k_seed_bound(SeedJobs J, unsigned long long* out) {
   unsigned long long s = 0, mx = 0, neg = 0;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    const int m = ms[i];
-    if (m < 0) {
-      neg = 1;
-    } else {
-      s += (unsigned long long)(m / stride + 2);
-      mx = mx > (unsigned long long)m ? mx : (unsigned long long)m;
+  const long long t0 = blockIdx.x * (long long)blockDim.x + threadIdx.x, dt = (long long)gridDim.x * blockDim.x;
+  for (int j = 0; j < J.n_jobs; ++j) {
+    const int* ms = J.j[j].max_steps;
+    for (long long i = t0; i < J.j[j].n; i += dt) {
+      const int m = ms[i];
+      if (m < 0) {
+        neg = 1;
+      } else {
+        s += (unsigned long long)(m / J.stride + 2);
+        mx = mx > (unsigned long long)m ? mx : (unsigned long long)m;
+      }
     }
   }
   for (int o = 32; o > 0; o >>= 1) {
@@ -313,18 +325,18 @@ __global__ void k_seed_bound(const int* ms, long long n, int stride, unsigned lo
     neg |= __shfl_xor(neg, o, 64);
   }
   if (__lane_id() == 0) {
-    atomicAdd(&out[0], s);
-    atomicMax(&out[1], mx);
+    if (s) atomicAdd(&out[0], s);
+    if (mx) atomicMax(&out[1], mx);
     if (neg) atomicOr(&out[2], neg);
   }
 }
 
-// accumulates into out (sum, max, negative flag): the caller clears it
-int launch_seed_bound(const int* ms, long long n, int stride, unsigned long long* out, hipStream_t st) {
-  long long grid = (n + 255) / 256;
-  if (grid > 64) grid = 64;  // grid-stride: few waves, so few contended atomics on the three results
+// at most 64 workgroups, so the three result atomics do not serialise
+int launch_seed_bound(const SeedJobs& J, long long total, unsigned long long* out, hipStream_t st) {
+  long long grid = (total + 255) / 256;
+  if (grid > 64) grid = 64;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(k_seed_bound, dim3((unsigned)grid), dim3(256), 0, st, ms, n, stride, out);
+  hipLaunchKernelGGL(k_seed_bound, dim3((unsigned)grid), dim3(256), 0, st, J, out);
   return 0;
 }
 
