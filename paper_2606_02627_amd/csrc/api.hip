@@ -14,6 +14,7 @@
 
 #include "../../include/streami.h"
 #include "device.h"
+#include "seed.h"
 
 namespace streami {
 int launch_advect_f32(const AdvectArgs& a, int layout, bool periodic, int mode, bool batched, int grid,

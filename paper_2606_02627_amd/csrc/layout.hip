@@ -4,6 +4,7 @@
 // cell's interpolation coefficients); 16-bit nodes are padded to 8 bytes so a
 // node is one aligned 64-bit load in the advection kernel.
 #include "device.h"
+#include "seed.h"
 
 namespace streami {
 
