@@ -320,7 +320,8 @@ def batched_bench(args, unsteady=False):
         # work-order kernels and k_advect), summed over the pass's windows
         "roofline": {"bound": "hbm", "achieved": alg / (dev_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": alg / (dev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_advect (batched)", "advect_ms_per_step": dev_ms},
+                     "kernel": "k_advect (batched)", "advect_ms_per_step": dev_ms,
+                     "kernel_hash": kernel_source_hash()},
         "one_block_per_launch_steps_per_s": steps_per_pass / wall_pb,
         "batching_speedup": wall_pb / wall,
         "terminated": list(st0.terminated),
