@@ -97,9 +97,30 @@ bool is_device_ptr(const void* p) {
 }
 
 // A device buffer that grows by reallocation (contents preserved on `st`).
+// A device allocation owned by one object: freed when the object goes away
+// (hipFree waits for the device, so no launch still reads it), moved, never
+// copied.  Temporaries of a call free themselves on every return path.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) {
+    o.p = nullptr;
+    o.bytes = 0;
+  }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      bytes = o.bytes;
+      o.p = nullptr;
+      o.bytes = 0;
+    }
+    return *this;
+  }
+  ~DevBuf() { release(); }
   void release() {
     if (p) (void)hipFree(p);
     p = nullptr;
