@@ -861,6 +861,10 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
       drop_graph(f);
       hipStream_t cs;
       HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+      struct StreamGuard {  // the capture stream goes away on every return path
+        hipStream_t s;
+        ~StreamGuard() { (void)hipStreamDestroy(s); }
+      } guard{cs};
       hipGraph_t g;
       HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
       launch_fill_u64(a.ctr, CTR_N, 0, cs);
@@ -874,7 +878,6 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
       HIP_TRY(hipStreamEndCapture(cs, &g));
       HIP_TRY(hipGraphInstantiate(&f->graph, g, nullptr, nullptr, 0));
       (void)hipGraphDestroy(g);
-      (void)hipStreamDestroy(cs);
       std::memcpy(f->graph_key, key, sizeof key);
       f->graph_args = a;
     }
