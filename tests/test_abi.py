@@ -180,3 +180,13 @@ def test_field_create_rejects_too_many_blocks():
     with pytest.raises(S.StreamiError) as e:
         S.streami_field_create([_desc()] * 316, S.F32)
     assert e.value.code == S.E_UNSUPPORTED and "315" in str(e.value)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs on exactly one GPU and says so for --gpus N > 1 (before any
+    device work)."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 2 and "one GPU" in r.stderr, (r.returncode, r.stderr[-500:])
