@@ -123,7 +123,7 @@ def surrogate_bench(args):
     """Learned flow-map form on the ABC field: train on GPU-generated 16-step windows, then
     advect seeds for 2000 steps with plain RK4, with the surrogate (both residual kinds) and
     with one RK4 step of 16h per jump (the surrogate's gather budget without the network).
-    Plain RK4 is the judge: every run's endpoints are compared with the plain run's (its own
+    Plain RK4 is the yardstick: every run's endpoints are compared with the plain run's (its own
     error against the FP64 oracle is a test's business, not the benchmark's)."""
     import torch
     import fieldgen as fg
