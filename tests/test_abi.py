@@ -190,3 +190,22 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=300)
     assert r.returncode == 2 and "one GPU" in r.stderr, (r.returncode, r.stderr[-500:])
+
+
+def test_missing_library_fails_loudly():
+    """Without the built HIP library every call raises ImportError naming the build step; there
+    is no CPU fallback to run instead (checked in a child process so the loaded library of this
+    one stays untouched)."""
+    import subprocess
+    import sys
+    code = ("import paper_2606_02627_amd as s\n"
+            "s.LIB_PATH = '/nonexistent/libstreami.so'\n"
+            "s._lib = None\n"
+            "try:\n"
+            "    s._load()\n"
+            "except ImportError as e:\n"
+            "    print('ImportError:', e)\n"
+            "else:\n"
+            "    raise SystemExit('loaded')\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300, cwd=ROOT)
+    assert r.returncode == 0 and "ImportError" in r.stdout and "build" in r.stdout, (r.stdout, r.stderr[-500:])
