@@ -301,13 +301,19 @@ def test_graph_replays(S):
 
 
 # ---------------------------------------------------------------- edge cases
-def test_edge_cases(S):
-    note("edge cases")
+# Every exit, limit and error rule holds for each stored layout and format (the
+# values involved are exact in all three formats).
+EDGE_FORMS = [(fg.F32, 0), (fg.F32, 1), (fg.F32, 2), (fg.F32, 3), (fg.BF16, 1), (fg.F16, 2)]
+
+
+@pytest.mark.parametrize("dtype,layout", EDGE_FORMS)
+def test_edge_cases(S, dtype, layout):
+    note("edge cases", fg.DTYPE_NAMES[dtype], "layout", layout)
     c = (0.25, 0.0, 0.0)
     blk = fg.closed_form_block(lambda x, y, z: (0 * x + c[0], 0 * x, 0 * x), (4, 4, 4), ghost=1,
                                origin=(0.5, 0.5, 0.5), lo=(0, 0, 0), hi=(4, 4, 4),
-                               rank_grid=(3, 3, 3), rank_coord=(1, 1, 1))
-    f = S.Field([blk], fg.F32)
+                               rank_grid=(3, 3, 3), rank_coord=(1, 1, 1), fmt=dtype)
+    f = S.Field([blk], dtype, layout=layout)
     seeds = np.array([[4.0, 1, 1], [-1e-3, 1, 1], [1, 1, 1], [1, 2, 3], [2.5, 0.5, 3.9]], np.float32)
     ms = np.array([10, 10, 0, 3, 100], np.int32)
     f.seed(0, seeds, max_steps=ms, record_stride=2)
@@ -329,12 +335,13 @@ def test_edge_cases(S):
     assert st2.steps == 0 and st2.active == 0
 
 
-def test_stagnation_nonfinite_halo(S):
-    note("stagnation / nonfinite / halo miss")
-    # stagnant field
+@pytest.mark.parametrize("dtype,layout", EDGE_FORMS)
+def test_stagnation_nonfinite_halo(S, dtype, layout):
+    note("stagnation / nonfinite / halo miss", fg.DTYPE_NAMES[dtype], "layout", layout)
+    # stagnant field (1e-7 stores as about 1e-7 in every format, below eps = 1e-6)
     blk = fg.closed_form_block(lambda x, y, z: (0 * x + 1e-7, 0 * x, 0 * x), (4, 4, 4),
-                               lo=(-10, -10, -10), hi=(10, 10, 10))
-    f = S.Field([blk], fg.F32)
+                               lo=(-10, -10, -10), hi=(10, 10, 10), fmt=dtype)
+    f = S.Field([blk], dtype, layout=layout)
     f.seed(0, np.array([[1, 1, 1]], np.float32), default_max_steps=5)
     f.advect(0.5)
     assert f.lines(0)["codes"][0] == S.STAGNANT
@@ -342,8 +349,8 @@ def test_stagnation_nonfinite_halo(S):
     b2 = fg.closed_form_block(lambda x, y, z: (0 * x + 1, 0 * x, 0 * x), (4, 4, 4),
                               lo=(-10, -10, -10), hi=(10, 10, 10))
     b2.values[0, 2, 2, 3, 1] = np.nan
-    b2 = b2.quantise(fg.F32)
-    f = S.Field([b2], fg.F32)
+    b2 = b2.quantise(dtype)
+    f = S.Field([b2], dtype, layout=layout)
     f.seed(0, np.array([[0.25, 1.5, 1.5]], np.float32), default_max_steps=10)
     f.advect(0.5)
     L = f.lines(0)
@@ -352,8 +359,8 @@ def test_stagnation_nonfinite_halo(S):
     # halo miss
     b3 = fg.closed_form_block(lambda x, y, z: (0 * x + 2.0, 0 * x, 0 * x), (4, 4, 4), ghost=1,
                               origin=(0.5, 0.5, 0.5), lo=(0, 0, 0), hi=(4, 4, 4),
-                              rank_grid=(3, 3, 3), rank_coord=(1, 1, 1))
-    f = S.Field([b3], fg.F32)
+                              rank_grid=(3, 3, 3), rank_coord=(1, 1, 1), fmt=dtype)
+    f = S.Field([b3], dtype, layout=layout)
     f.seed(0, np.array([[2.0, 2.0, 2.0]], np.float32), default_max_steps=100)
     f.advect(0.75)
     L = f.lines(0)
