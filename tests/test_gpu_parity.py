@@ -166,6 +166,35 @@ def test_time_blend_closed_form(S):
             np.testing.assert_array_equal(seg, want, err_msg=f"{fg.DTYPE_NAMES[fmt]} layout {layout}")
 
 
+
+def test_time_clamped_at_both_ends(S):
+    """Slices c, 2c, 3c at t0 = 0.5, slice_dt = 4: particles born at t = 10 (past the last
+    slice, 8.5) move on straight lines at 3c, and particles that live in t < t0 at c -- the
+    blend is clamped to the end slices, as in the oracle."""
+    import dataclasses
+    note("time clamp")
+    c = np.array([0.375, -0.25, 0.125])
+    base = fg.closed_form_block(lambda x, y, z: (0 * x + c[0], 0 * x + c[1], 0 * x + c[2]), (16, 16, 16),
+                                ghost=1, origin=(0.5, 0.5, 0.5), lo=(0, 0, 0), hi=(16, 16, 16))
+    vals = np.concatenate([base.values, 2.0 * base.values, 3.0 * base.values])
+    rng = np.random.default_rng(9)
+    seeds = (4.0 + rng.integers(0, 6 * 32, size=(200, 3)) / 32.0).astype(np.float32)  # stay inside
+    h, steps = 0.5, 8
+    tau = (np.arange(steps + 1) * h)[:, None]
+    for fmt, layout in ((fg.F32, S.LAYOUT_LINEAR), (fg.F32, S.LAYOUT_CELL), (fg.F16, S.LAYOUT_LINEAR)):
+        blk = dataclasses.replace(base, values=vals, n_slices=3, slice_dt=4.0, t0=0.5).quantise(fmt)
+        for t_birth, speed in ((10.0, 3.0), (-6.0, 1.0)):
+            f = S.Field([blk], fmt, layout=layout)
+            f.seed(0, seeds, default_max_steps=steps, t_birth=t_birth)
+            st = f.advect(h)
+            L = f.lines(0)
+            assert st.steps == len(seeds) * steps and (L["codes"] == S.MAX_STEPS).all()
+            for i, seg in enumerate(parity.split_lines(L)):
+                want = seeds[i].astype(np.float64) + speed * c * tau
+                np.testing.assert_allclose(seg, want, rtol=0, atol=1e-5,
+                                           err_msg=f"{fg.DTYPE_NAMES[fmt]} layout {layout} birth {t_birth}")
+            f.close()
+
 def test_solid_body_rotation_closed_form(S):
     """v = w(-(y-3), x-3, 0) lies in the trilinear span: vertices follow R(hA)^n exactly up
     to FP32 rounding (circles shrinking by the RK4 radius factor)."""

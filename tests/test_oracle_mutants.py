@@ -22,6 +22,7 @@ MUTANTS = {
     "exit_closed_upper": ("if (!(x[a] >= b->lo[a] && x[a] < b->hi[a])) return 0;", "if (!(x[a] >= b->lo[a] && x[a] <= b->hi[a])) return 0;"),
     "dest_axis_mix": ("(r[0] + (int64_t)b->rank_grid[0] * (r[1] + (int64_t)b->rank_grid[1] * r[2]))", "(r[0] + (int64_t)b->rank_grid[1] * (r[1] + (int64_t)b->rank_grid[0] * r[2]))"),
     "time_blend_swapped": ("v[c] = (1.0 - al) * v0[c] + al * v1[c];", "v[c] = al * v0[c] + (1.0 - al) * v1[c];"),
+    "time_blend_extrapolates": ("  if (al > 1) al = 1;\n", "\n"),
     "halo_miss_at_new_pos": ("io->out_dest[p] = orc_dest(b, fp);", "io->out_dest[p] = orc_dest(b, P);"),
     "stagnation_after_step": ("if (sqrt(k1[0] * k1[0] + k1[1] * k1[1] + k1[2] * k1[2]) < eps) return ORC_STAGNANT;", ""),
 }

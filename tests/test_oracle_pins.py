@@ -201,6 +201,29 @@ def test_unsteady_time_blend_closed_form():
     np.testing.assert_array_equal(fs.trace(s, 0.3, 12)["verts"], fu.trace(s, 0.3, 12)["verts"])
 
 
+
+def test_unsteady_time_clamped_at_both_ends():
+    """Outside the slices' time span the field is the end slice (linear blend clamped): with
+    slices c, 2c, 3c at t0 = 0.5, dt = 4, a particle born at t = 10 (past the last slice, 8.5)
+    moves on a straight line at 3c and one that lives in t < t0 at c. One that crosses t0 leaves
+    the straight line, so the clamp is not a constant offset."""
+    c = np.array([0.25, 0.5, -0.125])
+    dims = (6, 6, 6)
+    one = fg.closed_form_block(lambda x, y, z: (0 * x + c[0], 0 * x + c[1], 0 * x + c[2]), dims,
+                               ghost=1, lo=(-100, -100, -100), hi=(100, 100, 100))
+    vals = np.concatenate([one.values, 2 * one.values, 3 * one.values], axis=0)
+    f = oracle.Field(dims, 1, (0, 0, 0), (1, 1, 1), (-100,) * 3, (100,) * 3, n_slices=3, t0=0.5,
+                     slice_dt=4.0, nodes=vals, fmt=oracle.FMT_F64)
+    p0 = np.array([[2.0, 2.0, 2.5]])
+    h, n = 0.25, 8  # the particles stay inside the stored nodes
+    tau = (np.arange(n + 1) * h)[:, None]
+    late = f.trace(p0, h, n, t_birth=10.0)["verts"][0, :n + 1]
+    np.testing.assert_allclose(late, p0 + 3 * c * tau, rtol=0, atol=1e-13)
+    early = f.trace(p0, h, n, t_birth=-6.0)["verts"][0, :n + 1]  # t stays below -4
+    np.testing.assert_allclose(early, p0 + c * tau, rtol=0, atol=1e-13)
+    across = f.trace(p0, h, n, t_birth=-1.0)["verts"][0, :n + 1]  # t runs from -1 to 1
+    assert np.abs(across[-1] - (p0[0] + c * n * h)).max() > 1e-3
+
 def _rk4_error(field, p0, T, h, ref):
     n = int(round(T / h))
     r = field.trace(p0, h, n, eps=0.0, keep_verts=False)
