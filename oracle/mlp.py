@@ -40,9 +40,14 @@ def dsilu(z):
     return s * (1.0 + z * (1.0 - s))
 
 
-def forward(params, xhat, sigma):
+def forward(params, xhat, sigma, round_act=None):
     """params: list of (W [out, in], b [out]); xhat [B, 3]. Returns out [B, 3] and the
-    per-layer inputs/pre-activations for backprop."""
+    per-layer inputs/pre-activations for backprop.
+
+    round_act: None (plain FP64), or a rounding applied to every hidden activation
+    h_{l+1} = SiLU(z_l) before the next layer uses it -- the precision in which the
+    matrix cores take their operands (BF16), so that a decision taken on the output
+    is taken in the same precision on both sides."""
     h = np.asarray(xhat, np.float64)
     hs, zs = [h], []
     for l, (W, b) in enumerate(params):
@@ -50,6 +55,8 @@ def forward(params, xhat, sigma):
         zs.append(z)
         if l < len(params) - 1:
             h = silu(z)
+            if round_act is not None:
+                h = round_act(h)
             hs.append(h)
     out = zs[-1] * sigma
     return out, (hs, zs)
@@ -60,19 +67,23 @@ def loss(out, target, sigma):
     return float(np.mean(d * d))
 
 
-def backward(params, cache, out, target, sigma):
-    """Gradients of loss() with respect to every W_l and b_l."""
+def backward(params, cache, out, target, sigma, round_grad=None):
+    """Gradients of loss() with respect to every W_l and b_l.
+
+    round_grad: None (plain FP64), or a rounding applied to every dL/dz_l before it
+    enters a product (the precision of the matrix-core operands)."""
     hs, zs = cache
     B = out.shape[0]
+    rg = (lambda a: a) if round_grad is None else round_grad
     # dL/dout = 2 (out - target) / sigma^2 / (B*3); out = sigma * z_last
-    dz = 2.0 * (out - target) / (sigma * sigma) / (B * out.shape[1]) * sigma
+    dz = rg(2.0 * (out - target) / (sigma * sigma) / (B * out.shape[1]) * sigma)
     grads = [None] * len(params)
     for l in range(len(params) - 1, -1, -1):
         W, _ = params[l]
         grads[l] = (dz.T @ hs[l], dz.sum(axis=0))
         if l > 0:
             dh = dz @ W
-            dz = dh * dsilu(zs[l - 1])
+            dz = rg(dh * dsilu(zs[l - 1]))
     return grads
 
 

@@ -1,12 +1,14 @@
 """Pins for the FP64 network oracle (oracle/mlp.py): finite differences, an
-independent autograd implementation (torch CPU float64), Adam's closed-form
-first step, and SiLU identities."""
+independent autograd implementation (torch CPU float64), Adam's closed forms
+(first step; a constant gradient over many steps, where bias correction makes
+every step -lr g/(|g|+eps)), the input normalisation's fixed points and
+period, the BF16 rounding points, and SiLU identities."""
 import numpy as np
 import pytest
 import torch
 
 import fieldgen as fg
-from oracle import mlp
+from tests.oracle_under_test import mlp
 
 RNG = np.random.default_rng(7)
 
@@ -88,3 +90,56 @@ def test_bf16_rounding_is_round_to_nearest_even():
     x = RNG.normal(size=10000).astype(np.float32)
     ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
     np.testing.assert_array_equal(mlp.round_bf16(x), ref)
+
+
+def test_adam_constant_gradient_closed_form_over_many_steps():
+    """With a constant gradient g, m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2, so the
+    bias-corrected moments are g and g^2 at every t and each step moves by
+    -lr g / (|g| + eps): after t steps p_t = p_0 - t lr g / (|g| + eps)."""
+    params = rand_params((3, 4, 3))
+    grads = [(RNG.normal(size=W.shape) * 10.0 ** RNG.integers(-3, 2, size=W.shape),
+              RNG.normal(size=b.shape)) for W, b in params]
+    m, v = mlp.zeros_like(params), mlp.zeros_like(params)
+    before = [(W.copy(), b.copy()) for W, b in params]
+    lr, eps = 1e-3, 1e-8
+    for t in range(1, 8):
+        mlp.adam_step(params, grads, m, v, t, lr, eps=eps)
+        for (W0, b0), (W1, b1), (gw, gb) in zip(before, params, grads):
+            np.testing.assert_allclose(W1 - W0, -t * lr * gw / (np.abs(gw) + eps), rtol=1e-9, atol=1e-15)
+            np.testing.assert_allclose(b1 - b0, -t * lr * gb / (np.abs(gb) + eps), rtol=1e-9, atol=1e-15)
+
+
+def test_adam_second_step_after_a_sign_flip():
+    """g then -g: m_2 = 0.09 g - 0.1 g = -0.01 g, v_2 = 0.001999 g^2 (b2 = 0.999), so the
+    second step moves by -lr (-0.01 g / 0.19) / (sqrt(0.001999 g^2 / 0.001999) + eps)."""
+    p = [(np.array([[0.5, -2.0]]), np.array([0.25]))]
+    g = np.array([[0.3, -4.0]]), np.array([2.0])
+    m, v = mlp.zeros_like(p), mlp.zeros_like(p)
+    lr, eps = 1e-2, 1e-8
+    mlp.adam_step(p, [g], m, v, 1, lr, eps=eps)
+    p1 = p[0][0].copy()
+    mlp.adam_step(p, [(-g[0], -g[1])], m, v, 2, lr, eps=eps)
+    mhat = (0.9 * 0.1 * g[0] - 0.1 * g[0]) / (1 - 0.9 ** 2)
+    vhat = (0.999 * 0.001 * g[0] ** 2 + 0.001 * g[0] ** 2) / (1 - 0.999 ** 2)
+    np.testing.assert_allclose(p[0][0] - p1, -lr * mhat / (np.sqrt(vhat) + eps), rtol=1e-12)
+
+
+def test_normalise_maps_each_period_onto_minus_one_to_one():
+    L = 2 * np.pi
+    x = np.array([0.0, L / 2, L / 4, 3 * L / 4, L - 1e-12])
+    np.testing.assert_allclose(mlp.normalise(x, L), [-1.0, 0.0, -0.5, 0.5, 1.0], atol=1e-11)
+    y = RNG.uniform(-3 * L, 3 * L, size=1000)
+    np.testing.assert_allclose(mlp.normalise(y + 2 * L, L), mlp.normalise(y, L), atol=1e-12)
+    assert (mlp.normalise(y, L) >= -1).all() and (mlp.normalise(y, L) < 1).all()
+
+
+def test_forward_rounds_hidden_activations_where_asked():
+    params = rand_params((3, 16, 16, 3))
+    x = RNG.uniform(-1, 1, size=(50, 3))
+    sigma = np.ones(3)
+    plain, (hs, _) = mlp.forward(params, x, sigma)
+    rounded, (hr, _) = mlp.forward(params, x, sigma, round_act=mlp.round_bf16)
+    for h in hr[1:]:  # every hidden activation is a BF16 value
+        np.testing.assert_array_equal(h, torch.from_numpy(h).to(torch.bfloat16).to(torch.float64).numpy())
+    np.testing.assert_array_equal(hr[0], x)  # the input is the caller's
+    assert 0 < np.abs(rounded - plain).max() < 0.05 * np.abs(plain).max()
