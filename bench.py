@@ -84,11 +84,32 @@ def build_inputs(name):
     return blk, seeds, fmt, m, h, stride
 
 
+def host_cores():
+    """(cores this process may run on, host's logical cores, the cgroup CPU quota or None):
+    the CPU affinity mask, capped by a cgroup v2 `cpu.max` quota when one is set."""
+    host = os.cpu_count() or 1
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = host
+    quota = None
+    try:
+        with open("/sys/fs/cgroup/cpu.max") as fh:
+            q, per = fh.read().split()[:2]
+        if q != "max":
+            quota = float(q) / float(per)
+            avail = max(1, min(avail, int(quota)))
+    except (OSError, ValueError):
+        pass
+    return avail, host, quota
+
+
 def cpu_baseline(blk, seeds, h, m, budget_s=12.0):
-    """The FP64 oracle as it stands, on a bounded sample of the same workload."""
+    """The FP64 oracle as it stands, on a bounded sample of the same workload, with one
+    thread per core this process may use."""
     import oracle
     F = oracle.Field.from_block(blk)
-    threads = min(16, os.cpu_count() or 1)
+    threads, host, quota = host_cores()
     n = 256
     total_steps, total_t = 0, 0.0
     used = 0
@@ -113,10 +134,26 @@ def cpu_baseline(blk, seeds, h, m, budget_s=12.0):
     except OSError:
         pass
     return dict(value=total_steps / total_t, unit="particle-steps/s", cores=threads, kind="oracle",
+                host_logical_cores=host, cgroup_cpu_quota=quota,
                 sample=f"first {used} of the {len(seeds)} seeds, full trajectories "
                        f"(<= {m} steps each, {total_steps} steps) on the same stored field, FP64",
                 seconds=round(total_t, 2), one_thread_value=one, one_thread_sample=f"first {k1} seeds",
                 cpu_model=model)
+
+
+PARTICLE_BYTES = 80  # per particle and launch: pos, meta, meta2 read (48 B); pos, meta written (32 B)
+OUTBOX_BYTES = 40    # per outbox record: the 32-byte record written plus the 8-byte id read
+
+
+def compulsory_bytes(gathers, refill_bytes, vertices, particles, outbox, vertex_bytes=12):
+    """HBM bytes one advect launch cannot avoid with the register cell cache: every refill
+    reads the cell's stored corners (or its record) once, every recorded vertex writes its
+    x, y, z, and every particle's state is read and written once."""
+    d = {"refills": gathers * refill_bytes, "vertices": vertices * vertex_bytes,
+         "particles": particles * PARTICLE_BYTES, "outbox": outbox * OUTBOX_BYTES,
+         "refill_bytes": refill_bytes}
+    d["total"] = d["refills"] + d["vertices"] + d["particles"] + d["outbox"]
+    return d
 
 
 def surrogate_bench(args):
@@ -258,13 +295,14 @@ def batched_bench(args, unsteady=False):
         f.clear()
         f.seed_batches([dict(block=b, xyz=dseeds[b], max_steps=dlim[b], t_births=dtb[b] if dtb else None)
                         for b in range(len(blocks))], record_stride=stride)
-        tot = dict(steps=0, vertices=0, dev_ms=0.0)
+        tot = dict(steps=0, vertices=0, dev_ms=0.0, gathers=0)
         for te in (t_ends or [None]):
             kw = dict(use_graph=1) if te is None else dict(t_end=te)
             st = S.streami_advect(f.h, S.advect_params(h, **kw, **cfg), want_stats=stats)
             if stats:
                 tot["steps"] += int(st.steps)
                 tot["vertices"] += int(st.vertices)
+                tot["gathers"] += int(st.gathers)
                 tot["dev_ms"] += st.device_ms
         return st, tot
 
@@ -305,7 +343,11 @@ def batched_bench(args, unsteady=False):
         fb.close()
     value = steps_per_pass / wall
     vals = 192 if unsteady else 96
-    alg = steps_per_pass * vals * 2 + tot["vertices"] * 20
+    alg = steps_per_pass * vals * 2 + tot["vertices"] * 12
+    # a refill of a time-sliced field reads the cell in both bracketing slices
+    refill = (96 if tuned["layout"] == S.LAYOUT_CELL else 8 * 8) * (2 if unsteady else 1)
+    comp = compulsory_bytes(tot["gathers"], refill, tot["vertices"], n_part, int(st0.outbox))
+    achieved = comp["total"] / (dev_ms * 1e-3) / 1e9
     out = {
         "metric": "RK4 particle-steps/s + HBM GB/s; surrogate vs plain at fixed endpoint error",
         "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -318,10 +360,11 @@ def batched_bench(args, unsteady=False):
                    "graph": not t_ends},
         # the advect calls' device time (HIP events on the handle's stream around the
         # work-order kernels and k_advect), summed over the pass's windows
-        "roofline": {"bound": "hbm", "achieved": alg / (dev_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": alg / (dev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_advect (batched)", "advect_ms_per_step": dev_ms,
-                     "kernel_hash": kernel_source_hash()},
+                     "compulsory_bytes_per_launch": comp, "kernel_hash": kernel_source_hash(),
+                     "reuse": {"alg_bytes_per_launch": alg, "alg_over_compulsory": alg / comp["total"]}},
         "one_block_per_launch_steps_per_s": steps_per_pass / wall_pb,
         "batching_speedup": wall_pb / wall,
         "terminated": list(st0.terminated),
@@ -466,10 +509,15 @@ def main():
     ob = f.outbox(cap=len(seeds))
 
     value = steps_per_pass * args.steps / wall
-    node_bytes = 4 if fmt == S.F32 else 2
-    alg_bytes = steps_per_pass * 96 * node_bytes + verts_per_pass * 12
     mean_adv_s = float(np.mean(adv_ms)) / 1e3
-    achieved = alg_bytes / mean_adv_s / 1e9
+    gathers = int(st0.gathers)
+    node_bytes = 4 if fmt == S.F32 else 2
+    # the method's own count (every sample gathers its 8 corners): an upper bound that ignores
+    # the reuse of a cell across samples, kept only as the reuse ratio below
+    alg_bytes = steps_per_pass * 96 * node_bytes + verts_per_pass * 12
+    refill_bytes = 96 if layout == S.LAYOUT_CELL else 8 * (12 if fmt == S.F32 else 8)
+    comp = compulsory_bytes(gathers, refill_bytes, verts_per_pass, len(seeds), int(st0.outbox))
+    achieved = comp["total"] / mean_adv_s / 1e9
     traffic = None
     counters = None
     tfile = os.path.join(ROOT, "profiles", f"traffic_advect_{args.workload}.json")
@@ -503,13 +551,18 @@ def main():
                    "layout": LAYOUT_NAMES[layout] + (" (auto)" if args.layout == 0 else ""),
                    "field_bytes": field_bytes, "waves_per_cu": args.waves_per_cu,
                    "cell_cache": not args.no_cell_cache, "graph": args.graph},
+        # compulsory bytes of the cached kernel per launch (cell refills x stored refill bytes,
+        # 12 B per recorded vertex, particle state and outbox records) over k_advect's mean
+        # launch time, against the published HBM peak; `traffic` is the counted HBM bytes
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_advect", "alg_bytes_per_launch": alg_bytes,
+                     "traffic_frac": None if traffic is None else traffic / mean_adv_s / 1e9 / HBM_PEAK_GBS,
+                     "kernel": "k_advect", "compulsory_bytes_per_launch": comp,
                      "mean_launch_ms": mean_adv_s * 1e3, "kernel_hash": kernel_source_hash(),
-                     "counters": counters},
+                     "counters": counters,
+                     "reuse": {"alg_bytes_per_launch": alg_bytes, "alg_over_compulsory": alg_bytes / comp["total"]}},
         "advect_only_steps_per_s": steps_per_pass / mean_adv_s,
-        "cell_refills_per_step": int(st0.gathers) / steps_per_pass,
+        "cell_refills_per_step": gathers / steps_per_pass,
         "ingest_ms": ingest_s * 1e3,
         "fetch_lines_ms_per_65536": fetch_s * 1e3,
         "outbox_records": int(len(ob)),
@@ -532,7 +585,6 @@ def main():
         # gather roofline: the lanes' cell-cache misses are random 96-byte record reads from
         # the stored field; set their rate against the measured rate of such reads
         probe = memory_probe(S, field_bytes, 96)
-        gathers = int(st0.gathers)
         g_rate = gathers * 96 / mean_adv_s / 1e9
         peak = probe["read_GBps"]["field"]
         out["gather_roofline"] = {

@@ -274,6 +274,34 @@ def turbulence_block(config: int, edge=256, fmt: int = F32, sub: int = 0, n_slic
     return b.quantise(fmt)
 
 
+def partition(blk: Block, parts) -> list:
+    """Split a one-ghost-layer block into a px x py x pz grid of sub-blocks (x fastest), each
+    holding its share of the interior nodes plus one ghost layer copied from the neighbouring
+    nodes of the whole array, with owned bounds the matching share of the whole block's bounds
+    and rank grid `parts`.  Every sub-block samples the whole field's interpolant on its domain.
+    Interior node counts must divide evenly."""
+    assert blk.ghost == 1 and blk.boundary == BOUNDARY_BLOCK
+    parts = tuple(int(p) for p in parts)
+    n = [d // p for d, p in zip(blk.dims, parts)]
+    assert all(d == k * p for d, k, p in zip(blk.dims, n, parts)), "interior nodes must split evenly"
+    out = []
+    for k in range(parts[2]):
+        for j in range(parts[1]):
+            for i in range(parts[0]):
+                c = (i, j, k)
+                sl = tuple(slice(c[a] * n[a], c[a] * n[a] + n[a] + 2) for a in range(3))
+                lo = tuple(blk.lo[a] + c[a] * n[a] * blk.spacing[a] for a in range(3))
+                hi = tuple(blk.hi[a] if c[a] == parts[a] - 1 else blk.lo[a] + (c[a] + 1) * n[a] * blk.spacing[a]
+                           for a in range(3))
+                sub = dataclasses.replace(
+                    blk, dims=tuple(n), lo=lo, hi=hi, rank_grid=parts, rank_coord=c,
+                    origin=tuple(blk.origin[a] + c[a] * n[a] * blk.spacing[a] for a in range(3)),
+                    values=np.ascontiguousarray(blk.values[:, sl[2], sl[1], sl[0]]),
+                    stored=np.ascontiguousarray(blk.stored[:, sl[2], sl[1], sl[0]]))
+                out.append(sub)
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Seeds
 # ---------------------------------------------------------------------------

@@ -276,6 +276,46 @@ typedef struct {
 int streami_fetch_outbox(streami_field f, streami_outbox_rec* out, int64_t cap, int64_t* n_out);
 
 /*
+ * Loopback forwarding: the exchange of outgoing particles between the blocks
+ * of one handle (the paper's forwarding of outgoing particles to the rank that
+ * owns their new position, rafi_forwardParticles in the step() listing of
+ * Sec. 3.2, followed by its numActiveAcrossAllRanks count), done on the GPU.
+ * Every outbox record whose `dest` (destinationID, Sec. 3.1.1) is the
+ * macrocell of a block of this handle becomes a new particle of that block:
+ * the same id, step count, step limit, birth time and record stride, at the
+ * record's position, which is vertex 0 of the particle's next line segment
+ * (an EXIT record: the exit vertex, also the last vertex of the segment it
+ * left, so stitched segments share that joint; a HALO_MISS record: the old
+ * position, from which the owner of the failing stage point redoes the step;
+ * a halo miss is never sent back to the block it came from).  The forwarded
+ * records leave the outbox; the others (destinations outside the handle, -1)
+ * stay.  A block's forwarded particles follow its earlier ones in
+ * streami_fetch_lines() order, in unspecified order among themselves;
+ * segments of one id are ordered by their step counts.
+ * Needs every block of the handle on the same rank_grid with distinct
+ * rank_coord (E_UNSUPPORTED otherwise).  Waits for the handle's stream.
+ * *n_forwarded (nullable): records forwarded; *n_active (nullable): particles
+ * ACTIVE after the exchange, over all blocks.  Errors: E_ARG, E_UNSUPPORTED
+ * (no common rank grid, or more than 2^31 particles), E_NOMEM, E_DEVICE.
+ */
+int streami_forward(streami_field f, int64_t* n_forwarded, int64_t* n_active);
+
+/*
+ * trace() with forwarding (the step() listing of Sec. 3.2 on one GPU): repeat
+ * { streami_advect(p); streami_forward() } until no particle is active or
+ * max_rounds rounds ran.  With p->step_budget = k each round advances every
+ * particle by at most k steps before the exchange (k = 1 is the paper's
+ * one-step exchange); with 0 each round runs the local particles to
+ * termination or exit first.  *rounds (nullable) receives the rounds run.
+ * stats (nullable) sums steps, vertices, gathers, surrogate counts and device
+ * time over the rounds and reports particle codes and the outbox after the
+ * last exchange.  Errors: as streami_advect() and streami_forward(), E_ARG
+ * for max_rounds < 1.
+ */
+int streami_trace(streami_field f, const streami_advect_params* p, int32_t max_rounds, int32_t* rounds,
+                  streami_stats* stats);
+
+/*
  * Drop every particle, line and outbox record of the handle (the field data
  * stays), so the same handle can trace a new seed set -- a new Tracer run on
  * the same fields (Sec. 3.2).  Device buffers are kept for reuse.

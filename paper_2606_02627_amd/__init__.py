@@ -111,6 +111,8 @@ def _load():
         "streami_block_info": [vp, i32, vp, vp],
         "streami_field_info": [vp, vp, vp],
         "streami_clear": [vp],
+        "streami_forward": [vp, vp, vp],
+        "streami_trace": [vp, vp, i32, vp, vp],
         "streami_mlp_create": [vp, vp, ctypes.c_float, vp, vp],
         "streami_mlp_destroy": [vp],
         "streami_mlp_set_params": [vp, vp],
@@ -269,6 +271,22 @@ def streami_clear(f):
     return _check(_load().streami_clear(f))
 
 
+def streami_forward(f):
+    """Loopback exchange of the outbox between the handle's blocks: (forwarded, active)."""
+    fw, act = ctypes.c_int64(), ctypes.c_int64()
+    _check(_load().streami_forward(f, ctypes.byref(fw), ctypes.byref(act)))
+    return fw.value, act.value
+
+
+def streami_trace(f, params: AdvectParams, max_rounds=1 << 20, want_stats=True):
+    """Advect and forward until no particle is active: (rounds, stats or None)."""
+    st = Stats() if want_stats else None
+    r = ctypes.c_int32()
+    _check(_load().streami_trace(f, ctypes.byref(params), int(max_rounds), ctypes.byref(r),
+                                 ctypes.byref(st) if st else None))
+    return r.value, st
+
+
 def streami_probe_gather(buf, record_bytes, loads_per_lane, in_flight=4, waves_per_cu=16, stream=None):
     """Random record gathers over a device tensor: (ms of the timed launch, records read)."""
     ptr, dev = _addr(buf)
@@ -351,6 +369,12 @@ class Field:
 
     def advect(self, h, **kw):
         return streami_advect(self.h, advect_params(h, **kw))
+
+    def forward(self):
+        return streami_forward(self.h)
+
+    def trace(self, h, max_rounds=1 << 20, **kw):
+        return streami_trace(self.h, advect_params(h, **kw), max_rounds)
 
     def lines(self, block=0, first=0, count=None):
         """Lines of a block in seed order (host numpy CSR)."""

@@ -671,6 +671,7 @@ __device__ __forceinline__ void advect_body(const AdvectArgs& A) {
         r.code = (short)term;
         r.block = (short)blk;
         A.outbox[obase + lanes_below(em)] = r;
+        A.outbox_src[obase + lanes_below(em)] = p;
       }
     }
     if (p >= 0 && (term != ACTIVE || left <= 0)) {
@@ -855,6 +856,7 @@ __global__ void __launch_bounds__(256) k_sur_apply(SurrogateArgs S) {
         rr.code = (short)term;
         rr.block = 0;
         A.outbox[ob + lanes_below(em)] = rr;
+        A.outbox_src[ob + lanes_below(em)] = (int)q;
       }
     }
     if (active) {

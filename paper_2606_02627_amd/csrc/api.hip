@@ -15,6 +15,7 @@
 #include "../../include/streami.h"
 #include "device.h"
 #include "seed.h"
+#include "forward.h"
 
 namespace streami {
 int launch_advect_f32(const AdvectArgs& a, int layout, bool periodic, int mode, bool batched, int grid,
@@ -30,8 +31,8 @@ int mlp_forward_rows(streami_mlp m, const float* xyz, int xstride, long long n, 
 int launch_ingest(const void* src, void* pool, const BlockDev& B, int fmt, int layout, int nx, int ny, int nz,
                   int n_slices, hipStream_t st);
 int launch_seed(const SeedJobs& J, unsigned n_wg, const BlockDev* blocks, float4* pos, int4* meta, int4* meta2,
-                unsigned long long* pid, const VertexLog& log, OutRec* outbox, unsigned long long* outbox_count,
-                hipStream_t st);
+                unsigned long long* pid, const VertexLog& log, OutRec* outbox, int* outbox_src,
+                unsigned long long* outbox_count, hipStream_t st);
 int launch_scatter_lines(const VertexLog& log, long long n_rec, long long n_particles, const int* row_of,
                          const long long* offsets, float* out, hipStream_t st);
 int launch_mark_rows(const long long* idx, long long count, int* row_of, hipStream_t st);
@@ -167,6 +168,12 @@ struct streami_field_s {
   // particles (SoA)
   long long n_particles = 0, cap_particles = 0;
   DevBuf d_pos, d_meta, d_meta2, d_ids, d_outbox;
+  DevBuf d_obsrc;  // particle index of each outbox record
+  // loopback forwarding: macrocell id -> block of this handle (-1: elsewhere);
+  // n_ranks = 0 when the blocks do not share one rank grid with distinct cells
+  std::vector<int> rank_map;
+  int n_ranks = 0;
+  DevBuf d_rankmap, d_fwd, d_outbox2, d_obsrc2;
   // vertex log (see VertexLog): capacity in records, and the sum over all
   // particles of the vertices each may still record at most
   DevBuf d_logv, d_logj;
@@ -321,6 +328,7 @@ int ensure_particles(streami_field_s* f, long long need) {
   HIP_TRY(hipMemcpyAsync(&ob, f->outbox_count(), 8, hipMemcpyDeviceToHost, f->stream));
   HIP_TRY(hipStreamSynchronize(f->stream));
   if ((rc = f->d_outbox.reserve(cap * sizeof(OutRec), ob * sizeof(OutRec), f->stream))) return rc;
+  if ((rc = f->d_obsrc.reserve(cap * sizeof(int), ob * sizeof(int), f->stream))) return rc;
   f->cap_particles = cap;
   return STREAMI_OK;
 }
@@ -407,6 +415,7 @@ int advect_surrogate(streami_field_s* f, const streami_advect_params* p, streami
   a.ids = (const unsigned long long*)f->d_ids.p;
   a.log = f->log();
   a.outbox = (OutRec*)f->d_outbox.p;
+  a.outbox_src = (int*)f->d_obsrc.p;
   a.outbox_count = f->outbox_count();
   a.ctr = f->ctr();
   a.n_particles = n;
@@ -568,6 +577,32 @@ int streami_field_create(const streami_block_desc* blocks, int32_t n_blocks, int
     return cleanup(fail(STREAMI_E_DEVICE, "block table copy failed"));
   if ((rc = f->d_ctr.reserve(sizeof(unsigned long long) * N_COUNTERS, 0, f->stream))) return cleanup(rc);
   launch_fill_u64(f->ctr(), N_COUNTERS, 0, f->stream);
+  // loopback forwarding needs every block on one rank grid, one block per cell
+  {
+    const int* g0 = blocks[0].rank_grid;
+    long long nr = (long long)g0[0] * g0[1] * g0[2];
+    bool ok = nr <= (1LL << 24) && n_blocks <= FWD_MAX_BLOCKS;
+    for (int i = 1; i < n_blocks && ok; ++i)
+      for (int a = 0; a < 3; ++a) ok = ok && blocks[i].rank_grid[a] == g0[a];
+    if (ok) {
+      f->rank_map.assign((size_t)nr, -1);
+      for (int i = 0; i < n_blocks && ok; ++i) {
+        const int* c = blocks[i].rank_coord;
+        const long long id = c[0] + (long long)g0[0] * (c[1] + (long long)g0[1] * c[2]);
+        if (f->rank_map[id] >= 0) ok = false;
+        else f->rank_map[id] = i;
+      }
+    }
+    if (ok) {
+      f->n_ranks = (int)nr;
+      if ((rc = f->d_rankmap.reserve(sizeof(int) * nr, 0, f->stream))) return cleanup(rc);
+      if (hipMemcpyAsync(f->d_rankmap.p, f->rank_map.data(), sizeof(int) * nr, hipMemcpyHostToDevice, f->stream) !=
+          hipSuccess)
+        return cleanup(fail(STREAMI_E_DEVICE, "rank map copy failed"));
+    } else {
+      f->rank_map.clear();
+    }
+  }
   if (hipEventCreate(&f->ev0) != hipSuccess || hipEventCreate(&f->ev1) != hipSuccess)
     return cleanup(fail(STREAMI_E_DEVICE, "event creation failed"));
   if (hipStreamSynchronize(f->stream) != hipSuccess) return cleanup(fail(STREAMI_E_DEVICE, "field upload failed"));
@@ -581,6 +616,7 @@ int streami_field_destroy(streami_field f) {
   (void)hipStreamSynchronize(f->stream);
   drop_graph(f);
   for (DevBuf* b : {&f->d_blocks, &f->d_nodes, &f->d_pos, &f->d_meta, &f->d_meta2, &f->d_ids, &f->d_outbox,
+                    &f->d_obsrc, &f->d_rankmap, &f->d_fwd, &f->d_outbox2, &f->d_obsrc2,
                     &f->d_logv, &f->d_logj, &f->d_ctr, &f->d_qctr, &f->d_key,
                     &f->d_order, &f->d_hist, &f->d_cursor, &f->d_nwork, &f->d_dhat, &f->d_dhat2, &f->d_xh,
                     &f->d_seedred})
@@ -731,7 +767,7 @@ int seed_batches(streami_field_s* f, const streami_seed_batch* bt, int nb, const
     if (J.n_jobs == SEED_JOBS || (k == nb && J.n_jobs > 0)) {
       launch_seed(J, n_wg, (const BlockDev*)f->d_blocks.p, (float4*)f->d_pos.p, (int4*)f->d_meta.p,
                   (int4*)f->d_meta2.p, (unsigned long long*)f->d_ids.p, f->log(), (OutRec*)f->d_outbox.p,
-                  f->outbox_count(), f->stream);
+                  (int*)f->d_obsrc.p, f->outbox_count(), f->stream);
       HIP_TRY(hipGetLastError());
       J.n_jobs = 0;
       n_wg = 0;
@@ -801,6 +837,7 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
   a.meta2 = (const int4*)f->d_meta2.p;
   a.ids = (const unsigned long long*)f->d_ids.p;
   a.outbox = (OutRec*)f->d_outbox.p;
+  a.outbox_src = (int*)f->d_obsrc.p;
   a.outbox_count = f->outbox_count();
   a.ctr = f->ctr();
   a.n_particles = f->n_particles;
@@ -1048,6 +1085,142 @@ int streami_fetch_outbox(streami_field f, streami_outbox_rec* out, int64_t cap, 
     HIP_TRY(hipStreamSynchronize(f->stream));
   }
   if ((long long)cnt > take) return fail(STREAMI_E_CAPACITY, "%lld records remain in the outbox", (long long)(cnt - take));
+  return STREAMI_OK;
+}
+
+int streami_forward(streami_field f, int64_t* n_forwarded, int64_t* n_active) {
+  if (!f) return fail(STREAMI_E_ARG, "field handle is NULL");
+  if (f->n_ranks == 0)
+    return fail(STREAMI_E_UNSUPPORTED, "forwarding needs every block on one rank grid, at most one block per cell "
+                                       "(and at most %d blocks)", FWD_MAX_BLOCKS);
+  const int nb = (int)f->blocks.size();
+  int rc;
+  unsigned long long ob = 0;
+  HIP_TRY(hipMemcpyAsync(&ob, f->outbox_count(), 8, hipMemcpyDeviceToHost, f->stream));
+  HIP_TRY(hipStreamSynchronize(f->stream));
+  // layout of d_fwd (u64 units): counts[nb], vertex bound, cursor[nb], kept, base[nb]
+  if ((rc = f->d_fwd.reserve(sizeof(unsigned long long) * (3 * (size_t)nb + 2), 0, f->stream))) return rc;
+  unsigned long long* counts = (unsigned long long*)f->d_fwd.p;
+  unsigned long long* cursor = counts + nb + 1;
+  unsigned long long* kept = cursor + nb;
+  long long* base = (long long*)(kept + 1);
+  long long total = 0;
+  std::vector<unsigned long long> h(nb + 1, 0);
+  if (ob > 0) {
+    FwdArgs a;
+    a.outbox = (const OutRec*)f->d_outbox.p;
+    a.outbox_src = (const int*)f->d_obsrc.p;
+    a.outbox_count = f->outbox_count();
+    a.rank_map = (const int*)f->d_rankmap.p;
+    a.n_ranks = f->n_ranks;
+    a.n_blocks = nb;
+    a.pos = (const float4*)f->d_pos.p;
+    a.meta = (const int4*)f->d_meta.p;
+    a.meta2 = (const int4*)f->d_meta2.p;
+    launch_fill_u64(counts, 2LL * nb + 2, 0, f->stream);
+    launch_fwd_count(a, counts, (long long)ob, f->stream);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(h.data(), counts, sizeof(unsigned long long) * (nb + 1), hipMemcpyDeviceToHost, f->stream));
+    HIP_TRY(hipStreamSynchronize(f->stream));
+    for (int b = 0; b < nb; ++b) total += (long long)h[b];
+    if (total > 0) {
+      if (f->n_particles + total >= (1LL << 31))
+        return fail(STREAMI_E_UNSUPPORTED, "forwarding would exceed 2^31 particles in one handle");
+      // each block's new particles take one contiguous range after the existing ones
+      std::vector<long long> hb(nb);
+      long long next = f->n_particles;
+      for (int b = 0; b < nb; ++b) {
+        hb[b] = next;
+        next += (long long)h[b];
+      }
+      if ((rc = ensure_particles(f, next))) return rc;
+      f->vert_bound += (long long)h[nb];
+      if ((rc = ensure_log(f, 0))) return rc;
+      if ((rc = f->d_outbox2.reserve(f->cap_particles * sizeof(OutRec), 0, f->stream)) ||
+          (rc = f->d_obsrc2.reserve(f->cap_particles * sizeof(int), 0, f->stream)))
+        return rc;
+      HIP_TRY(hipMemcpyAsync(base, hb.data(), sizeof(long long) * nb, hipMemcpyHostToDevice, f->stream));
+      // the particle arrays may have moved
+      a.pos = (const float4*)f->d_pos.p;
+      a.meta = (const int4*)f->d_meta.p;
+      a.meta2 = (const int4*)f->d_meta2.p;
+      a.outbox = (const OutRec*)f->d_outbox.p;
+      a.outbox_src = (const int*)f->d_obsrc.p;
+      FwdOut o;
+      o.base = base;
+      o.cursor = cursor;
+      o.pos = (float4*)f->d_pos.p;
+      o.meta = (int4*)f->d_meta.p;
+      o.meta2 = (int4*)f->d_meta2.p;
+      o.ids = (unsigned long long*)f->d_ids.p;
+      o.log = f->log();
+      o.kept = (OutRec*)f->d_outbox2.p;
+      o.kept_src = (int*)f->d_obsrc2.p;
+      o.n_kept = kept;
+      launch_fwd_write(a, o, (long long)ob, f->stream);
+      launch_copy_u64(kept, f->outbox_count(), f->stream);
+      HIP_TRY(hipGetLastError());
+      std::swap(f->d_outbox, f->d_outbox2);
+      std::swap(f->d_obsrc, f->d_obsrc2);
+      for (int b = 0; b < nb; ++b)
+        if (h[b] > 0) {
+          f->blocks[b].ranges.push_back({hb[b], (long long)h[b]});
+          f->blocks[b].n_particles += (long long)h[b];
+        }
+      f->n_particles = next;
+      f->log_need_known = false;
+      drop_graph(f);  // the cached launch holds the old buffers
+    }
+  }
+  if (n_forwarded) *n_forwarded = total;
+  if (n_active) {
+    launch_fill_u64(f->code_counts(), 6, 0, f->stream);
+    launch_count_codes((const int4*)f->d_meta.p, f->n_particles, f->code_counts(), f->stream);
+    unsigned long long c = 0;
+    HIP_TRY(hipMemcpyAsync(&c, f->code_counts() + ACTIVE, 8, hipMemcpyDeviceToHost, f->stream));
+    HIP_TRY(hipStreamSynchronize(f->stream));
+    *n_active = (int64_t)c;
+  }
+  return STREAMI_OK;
+}
+
+int streami_trace(streami_field f, const streami_advect_params* p, int32_t max_rounds, int32_t* rounds,
+                  streami_stats* stats) {
+  if (!f) return fail(STREAMI_E_ARG, "field handle is NULL");
+  if (!p) return fail(STREAMI_E_ARG, "params is NULL");
+  if (max_rounds < 1) return fail(STREAMI_E_ARG, "max_rounds must be >= 1");
+  if (f->n_ranks == 0)
+    return fail(STREAMI_E_UNSUPPORTED, "forwarding needs every block on one rank grid, at most one block per cell");
+  streami_stats tot, st;
+  std::memset(&tot, 0, sizeof tot);
+  int r = 0, rc;
+  int64_t active = 1;
+  for (; r < max_rounds && active > 0; ++r) {
+    if ((rc = streami_advect(f, p, stats ? &st : nullptr))) return rc;
+    if (stats) {
+      tot.steps += st.steps;
+      tot.vertices += st.vertices;
+      tot.surrogate_accepted += st.surrogate_accepted;
+      tot.surrogate_fallback += st.surrogate_fallback;
+      tot.device_ms += st.device_ms;
+      tot.gathers += st.gathers;
+    }
+    int64_t fw = 0;
+    if ((rc = streami_forward(f, &fw, &active))) return rc;
+  }
+  if (rounds) *rounds = r;
+  if (stats) {
+    // particle counts and the outbox after the last exchange
+    launch_fill_u64(f->code_counts(), 6, 0, f->stream);
+    launch_count_codes((const int4*)f->d_meta.p, f->n_particles, f->code_counts(), f->stream);
+    unsigned long long h[PER_N + 6];
+    HIP_TRY(hipMemcpyAsync(h, f->persist(), sizeof h, hipMemcpyDeviceToHost, f->stream));
+    HIP_TRY(hipStreamSynchronize(f->stream));
+    for (int k = 0; k < 6; ++k) tot.terminated[k] = (int64_t)h[PER_N + k];
+    tot.active = tot.terminated[ACTIVE];
+    tot.outbox = (int64_t)h[PER_OUTBOX];
+    *stats = tot;
+  }
   return STREAMI_OK;
 }
 

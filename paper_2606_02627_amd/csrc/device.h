@@ -96,6 +96,7 @@ struct AdvectArgs {
   const unsigned long long* ids;
   VertexLog log;
   OutRec* outbox;
+  int* outbox_src;                   // particle index of each outbox record (for forwarding)
   unsigned long long* outbox_count;  // persistent across calls
   unsigned long long* ctr;           // per-call counters
   long long n_particles;

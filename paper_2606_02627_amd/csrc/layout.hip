@@ -149,7 +149,7 @@ constexpr int SEED_THREADS = 1024;  // one log reservation per 16 waves
 // to the outbox.
 __global__ void __launch_bounds__(SEED_THREADS) k_seed(SeedJobs J, const BlockDev* blocks, float4* pos,
                                                        int4* meta, int4* meta2, unsigned long long* pid,
-                                                       VertexLog log, OutRec* outbox,
+                                                       VertexLog log, OutRec* outbox, int* outbox_src,
                                                        unsigned long long* outbox_count) {
   int jb = 0;  // the job of this workgroup (uniform): the last one starting at or before it
   for (int j = 1; j < J.n_jobs; ++j)
@@ -224,16 +224,17 @@ __global__ void __launch_bounds__(SEED_THREADS) k_seed(SeedJobs J, const BlockDe
       r.code = (short)EXIT;
       r.block = (short)blk;
       outbox[base + below] = r;
+      outbox_src[base + below] = (int)q;
     }
   }
 }
 
 int launch_seed(const SeedJobs& J, unsigned n_wg, const BlockDev* blocks, float4* pos, int4* meta, int4* meta2,
-                unsigned long long* pid, const VertexLog& log, OutRec* outbox, unsigned long long* outbox_count,
-                hipStream_t st) {
+                unsigned long long* pid, const VertexLog& log, OutRec* outbox, int* outbox_src,
+                unsigned long long* outbox_count, hipStream_t st) {
   if (J.n_jobs <= 0 || n_wg == 0) return 0;
   hipLaunchKernelGGL(k_seed, dim3(n_wg), dim3(SEED_THREADS), 0, st, J, blocks, pos, meta, meta2, pid, log, outbox,
-                     outbox_count);
+                     outbox_src, outbox_count);
   return 0;
 }
 

@@ -89,6 +89,8 @@ def test_calls_on_null_handle_fail_cleanly():
     assert lib.streami_fetch_outbox(null, None, 0, None) == S.E_ARG
     assert lib.streami_fetch_lines(null, 0, 0, 0, None, None, 0, None, None, None, None) == S.E_ARG
     assert lib.streami_seed_batches(null, None, 1, None) == S.E_ARG
+    assert lib.streami_forward(null, None, None) == S.E_ARG
+    assert lib.streami_trace(null, None, 1, None, None) == S.E_ARG
     assert lib.streami_field_destroy(null) == S.OK
     assert b"NULL" in lib.streami_last_error()
 

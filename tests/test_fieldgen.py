@@ -63,3 +63,26 @@ def test_turbulence_energy_spectrum_slope():
     ks = np.arange(2, 25)
     slope = np.polyfit(np.log(ks), np.log(energy[ks]), 1)[0]
     assert abs(slope + 5.0 / 3.0) < 0.2, slope
+
+
+def test_partition_samples_the_whole_field():
+    """Each sub-block of a partition interpolates the same field as the whole block wherever
+    its sample domain reaches (its ghost layer is the neighbours' nodes), including the
+    strip of the halo beyond its owned bounds; bounds tile the whole block."""
+    import oracle
+    whole = fg.turbulence_block(2, edge=12, dims=(12, 8, 16), rank_grid=(1, 1, 1), rank_coord=(0, 0, 0))
+    parts = fg.partition(whole, (3, 2, 2))
+    W = oracle.Field.from_block(whole)
+    rng = np.random.default_rng(0)
+    vol = 0.0
+    for p in parts:
+        P = oracle.Field.from_block(p)
+        lo, hi = np.array(p.lo) - 0.5, np.array(p.hi) + 0.5  # owned bounds + the half-cell halo
+        x = rng.uniform(lo, hi, size=(500, 3))
+        vw, okw = W.sample(x)
+        vp, okp = P.sample(x)
+        assert okp.all()
+        np.testing.assert_allclose(vp[okw], vw[okw], rtol=0, atol=1e-12)
+        vol += np.prod(np.array(p.hi) - np.array(p.lo))
+        assert p.rank_grid == (3, 2, 2)
+    assert vol == 12 * 8 * 16
