@@ -838,7 +838,11 @@ __global__ void __launch_bounds__(256) k_sur_apply(SurrogateArgs S) {
         }
         ++mt.w;
       }
-      if (lane == leader) atomicAdd(A.log.real, (unsigned long long)__popcll(vm));
+      if (lane == leader) {
+        atomicAdd(A.log.real, (unsigned long long)__popcll(vm));
+        // a record past the reserved log is lost: the call reports it as an error
+        if (b + __popcll(vm) > (unsigned long long)A.log.cap) atomicOr(&A.ctr[CTR_OVERFLOW], 1ull);
+      }
     }
     const bool emit = term == EXIT || term == HALO_MISS;
     const unsigned long long em = __ballot(emit);
