@@ -357,6 +357,25 @@ int streami_mlp_forward(streami_mlp m, const float* xyz, int64_t n, float* out);
 int streami_mlp_train_step(streami_mlp m, const float* xyz, const float* target, int64_t batch, float lr,
                            float* loss_out, float* grads_out);
 
+/* Allocation-free variant of streami_mlp_train_step, for callers that cannot
+ * allocate device memory during a call (code under HIP graph capture, tight
+ * training or serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, kernels, results and outputs as streami_mlp_train_step, but the
+ * per-batch workspace (layer activations, pre-activations and their
+ * gradients, 10,432 bytes per row) lives in one library-static device array
+ * per GPU, sized for STREAMI_MLP_NOALLOC_MAX_BATCH rows (85.5 MB, held by
+ * every GPU the library runs on until the process ends).  The call allocates
+ * nothing (no hipMalloc/hipFree, no library allocation) and does not grow the
+ * network's own workspace.  batch must be in [1, STREAMI_MLP_NOALLOC_MAX_BATCH],
+ * else E_ARG.  All calls on one GPU share that array: calls whose work may
+ * overlap on the device (different streams, or different threads without
+ * ordering) race and give undefined results; calls ordered on one stream are
+ * safe.  Nothing needs clearing between calls (a step writes every workspace
+ * element before reading it). */
+#define STREAMI_MLP_NOALLOC_MAX_BATCH 8192
+int streami_mlp_train_step_noalloc(streami_mlp m, const float* xyz, const float* target, int64_t batch, float lr,
+                                   float* loss_out, float* grads_out);
+
 /* Thread-local description of the last error. */
 const char* streami_last_error(void);
 

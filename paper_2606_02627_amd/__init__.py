@@ -119,6 +119,7 @@ def _load():
         "streami_mlp_get_params": [vp, vp],
         "streami_mlp_forward": [vp, vp, i64, vp],
         "streami_mlp_train_step": [vp, vp, vp, i64, ctypes.c_float, vp, vp],
+        "streami_mlp_train_step_noalloc": [vp, vp, vp, i64, ctypes.c_float, vp, vp],
         "streami_probe_gather": [vp, i64, i32, i32, i32, i32, vp, vp, vp],
         "streami_probe_valu": [i32, i32, vp, vp, vp],
     }
@@ -463,4 +464,19 @@ def streami_mlp_train_step(m, xyz, target, lr, want_loss=True, want_grads=False)
     _check(_load().streami_mlp_train_step(m, _addr(xyz)[0], _addr(target)[0], int(n), float(lr),
                                           ctypes.byref(loss) if want_loss else None,
                                           _addr(grads)[0] if want_grads else None))
+    return (loss.value if want_loss else None), grads
+
+
+MLP_NOALLOC_MAX_BATCH = 8192  # STREAMI_MLP_NOALLOC_MAX_BATCH
+
+
+def streami_mlp_train_step_noalloc(m, xyz, target, lr, want_loss=True, want_grads=False):
+    """streami_mlp_train_step on the library's static per-device workspace (no allocation in
+    the call; at most MLP_NOALLOC_MAX_BATCH rows)."""
+    n = xyz.numel() // 3
+    loss = ctypes.c_float()
+    grads = np.zeros(MLP_N_PARAMS, np.float32) if want_grads else None
+    _check(_load().streami_mlp_train_step_noalloc(m, _addr(xyz)[0], _addr(target)[0], int(n), float(lr),
+                                                  ctypes.byref(loss) if want_loss else None,
+                                                  _addr(grads)[0] if want_grads else None))
     return (loss.value if want_loss else None), grads

@@ -20,6 +20,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -368,6 +369,18 @@ int mfail(int code, const char* fmt, ...) {
   } while (0)
 }  // namespace
 
+namespace streami {
+// The per-batch buffers of one training step, for Bp padded rows.
+struct Workspace {
+  unsigned short* H[NL] = {};   // BF16 layer inputs [Bp x in_pad]
+  unsigned short* HT[NL] = {};  // transposed [in_pad x Bp]
+  float* Z[NL] = {};            // FP32 pre-activations [Bp x out_pad]
+  unsigned short* dZ = nullptr;  // BF16 [Bp x 256]
+  unsigned short* dZT = nullptr;
+  float* dH = nullptr;           // FP32 [Bp x 256]
+};
+}  // namespace streami
+
 struct streami_mlp_s {
   hipStream_t stream = nullptr;
   float sigma[3] = {1, 1, 1};
@@ -385,14 +398,9 @@ struct streami_mlp_s {
   float* gb[NL] = {};            // FP32 [out_pad]
   unsigned short* frag = nullptr;  // BF16 weights in MFMA fragment order (fused inference)
   long long t = 0;               // Adam step count
-  // batch workspace (grown on demand)
+  // batch workspace of streami_mlp_train_step (grown on demand)
   long long cap = 0;
-  unsigned short* H[NL] = {};   // BF16 layer inputs [cap x in_pad]
-  unsigned short* HT[NL] = {};  // transposed [in_pad x cap]
-  float* Z[NL] = {};            // FP32 pre-activations [cap x out_pad]
-  unsigned short* dZ = nullptr;  // BF16 [cap x 256]
-  unsigned short* dZT = nullptr;
-  float* dH = nullptr;           // FP32 [cap x 256]
+  streami::Workspace ws;
   float* loss = nullptr;
   std::vector<void*> owned;
 };
@@ -416,17 +424,14 @@ void free_batch(streami_mlp_s* m) {
     (void)hipFree(p);
   };
   for (int l = 0; l < NL; ++l) {
-    drop(m->H[l]);
-    drop(m->HT[l]);
-    drop(m->Z[l]);
-    m->H[l] = m->HT[l] = nullptr;
-    m->Z[l] = nullptr;
+    drop(m->ws.H[l]);
+    drop(m->ws.HT[l]);
+    drop(m->ws.Z[l]);
   }
-  drop(m->dZ);
-  drop(m->dZT);
-  drop(m->dH);
-  m->dZ = m->dZT = nullptr;
-  m->dH = nullptr;
+  drop(m->ws.dZ);
+  drop(m->ws.dZT);
+  drop(m->ws.dH);
+  m->ws = Workspace();
   m->cap = 0;
 }
 
@@ -438,13 +443,13 @@ int ensure_batch(streami_mlp_s* m, long long Bp) {
   free_batch(m);
   int rc;
   for (int l = 0; l < NL; ++l) {
-    if ((rc = dalloc(m, (void**)&m->H[l], (size_t)Bp * IN_PAD[l] * 2)) ||
-        (rc = dalloc(m, (void**)&m->HT[l], (size_t)Bp * IN_PAD[l] * 2)) ||
-        (rc = dalloc(m, (void**)&m->Z[l], (size_t)Bp * OUT_PAD[l] * 4)))
+    if ((rc = dalloc(m, (void**)&m->ws.H[l], (size_t)Bp * IN_PAD[l] * 2)) ||
+        (rc = dalloc(m, (void**)&m->ws.HT[l], (size_t)Bp * IN_PAD[l] * 2)) ||
+        (rc = dalloc(m, (void**)&m->ws.Z[l], (size_t)Bp * OUT_PAD[l] * 4)))
       return rc;
   }
-  if ((rc = dalloc(m, (void**)&m->dZ, (size_t)Bp * 256 * 2)) || (rc = dalloc(m, (void**)&m->dZT, (size_t)Bp * 256 * 2)) ||
-      (rc = dalloc(m, (void**)&m->dH, (size_t)Bp * 256 * 4)))
+  if ((rc = dalloc(m, (void**)&m->ws.dZ, (size_t)Bp * 256 * 2)) ||
+      (rc = dalloc(m, (void**)&m->ws.dZT, (size_t)Bp * 256 * 2)) || (rc = dalloc(m, (void**)&m->ws.dH, (size_t)Bp * 256 * 4)))
     return rc;
   m->cap = Bp;
   return STREAMI_OK;
@@ -460,37 +465,133 @@ void refresh_bf16(streami_mlp_s* m) {
 }
 
 // Forward over Bp rows (n real); leaves Z/H for backprop; writes out (n x 3) if given.
-void forward(streami_mlp_s* m, const float* xyz, int xstride, long long n, long long Bp, float* out,
-             const float* target, bool want_grad, hipStream_t st) {
-  hipLaunchKernelGGL(k_mlp_input, dim3(grid_for(Bp)), dim3(256), 0, st, xyz, xstride, n, Bp, m->period, m->H[0],
-                     m->HT[0]);
+void forward(streami_mlp_s* m, const Workspace& w, const float* xyz, int xstride, long long n, long long Bp,
+             float* out, const float* target, bool want_grad, hipStream_t st) {
+  hipLaunchKernelGGL(k_mlp_input, dim3(grid_for(Bp)), dim3(256), 0, st, xyz, xstride, n, Bp, m->period, w.H[0],
+                     w.HT[0]);
   for (int l = 0; l < NL; ++l) {
-    gemm(m->H[l], IN_PAD[l], m->Wb[l], IN_PAD[l], m->Z[l], OUT_PAD[l], (int)Bp, OUT_PAD[l], IN_PAD[l], false, st);
+    gemm(w.H[l], IN_PAD[l], m->Wb[l], IN_PAD[l], w.Z[l], OUT_PAD[l], (int)Bp, OUT_PAD[l], IN_PAD[l], false, st);
     if (l < NL - 1)
-      hipLaunchKernelGGL(k_bias_silu, dim3(grid_for(Bp * OUT_PAD[l])), dim3(256), 0, st, m->Z[l], m->b[l], Bp,
-                         OUT_PAD[l], m->H[l + 1], m->HT[l + 1]);
+      hipLaunchKernelGGL(k_bias_silu, dim3(grid_for(Bp * OUT_PAD[l])), dim3(256), 0, st, w.Z[l], m->b[l], Bp,
+                         OUT_PAD[l], w.H[l + 1], w.HT[l + 1]);
   }
   const float inv = n > 0 ? 1.0f / (float)(n * 3) : 0.0f;
-  hipLaunchKernelGGL(k_out_loss, dim3(grid_for(Bp)), dim3(256), 0, st, m->Z[NL - 1], m->b[NL - 1], n, Bp, m->sigma[0],
-                     m->sigma[1], m->sigma[2], target, out, want_grad ? m->dZ : nullptr, want_grad ? m->dZT : nullptr,
+  hipLaunchKernelGGL(k_out_loss, dim3(grid_for(Bp)), dim3(256), 0, st, w.Z[NL - 1], m->b[NL - 1], n, Bp, m->sigma[0],
+                     m->sigma[1], m->sigma[2], target, out, want_grad ? w.dZ : nullptr, want_grad ? w.dZT : nullptr,
                      target ? m->loss : nullptr, inv);
 }
 
-// Backward from dZ of the output layer (already in m->dZ/dZT, width 32).
-void backward(streami_mlp_s* m, long long Bp) {
+// Backward from dZ of the output layer (already in w.dZ/dZT, width 32).
+void backward(streami_mlp_s* m, const Workspace& w, long long Bp) {
   hipStream_t st = m->stream;
   for (int l = NL - 1; l >= 0; --l) {
     const int op = OUT_PAD[l], ip = IN_PAD[l];
     // dW_l [op x ip] = dZ^T [op x Bp] . H_l [Bp x ip]  (K = batch, contiguous in dZ^T and H^T)
-    gemm(m->dZT, (int)Bp, m->HT[l], (int)Bp, m->gW[l], ip, op, ip, (int)Bp, false, st);
-    hipLaunchKernelGGL(k_rowsum_bf16, dim3(op), dim3(256), 0, st, m->dZT, Bp, op, m->gb[l]);
+    gemm(w.dZT, (int)Bp, w.HT[l], (int)Bp, m->gW[l], ip, op, ip, (int)Bp, false, st);
+    hipLaunchKernelGGL(k_rowsum_bf16, dim3(op), dim3(256), 0, st, w.dZT, Bp, op, m->gb[l]);
     if (l > 0) {
       // dH_l [Bp x ip] = dZ [Bp x op] . W_l [op x ip]   (B(k=out, j=in) = W^T[in][out])
-      gemm(m->dZ, op, m->WTb[l], op, m->dH, ip, (int)Bp, ip, op, false, st);
-      hipLaunchKernelGGL(k_silu_grad, dim3(grid_for(Bp * ip)), dim3(256), 0, st, m->dH, m->Z[l - 1], Bp, ip, m->dZ,
-                         m->dZT);
+      gemm(w.dZ, op, m->WTb[l], op, w.dH, ip, (int)Bp, ip, op, false, st);
+      hipLaunchKernelGGL(k_silu_grad, dim3(grid_for(Bp * ip)), dim3(256), 0, st, w.dH, w.Z[l - 1], Bp, ip, w.dZ,
+                         w.dZT);
     }
   }
+}
+
+// Bytes of a workspace for Bp padded rows, each buffer starting on a 256-byte boundary.
+constexpr size_t ws_align(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t workspace_bytes(long long Bp) {
+  size_t s = 0;
+  for (int l = 0; l < NL; ++l)
+    s += 2 * ws_align((size_t)Bp * IN_PAD[l] * 2) + ws_align((size_t)Bp * OUT_PAD[l] * 4);
+  return s + 2 * ws_align((size_t)Bp * 256 * 2) + ws_align((size_t)Bp * 256 * 4);
+}
+
+// A workspace for Bp padded rows carved out of `base` (workspace_bytes(Bp) bytes, 256-aligned).
+Workspace carve_workspace(char* base, long long Bp) {
+  Workspace w;
+  auto take = [&](size_t b) {
+    char* p = base;
+    base += ws_align(b);
+    return p;
+  };
+  for (int l = 0; l < NL; ++l) {
+    w.H[l] = (unsigned short*)take((size_t)Bp * IN_PAD[l] * 2);
+    w.HT[l] = (unsigned short*)take((size_t)Bp * IN_PAD[l] * 2);
+    w.Z[l] = (float*)take((size_t)Bp * OUT_PAD[l] * 4);
+  }
+  w.dZ = (unsigned short*)take((size_t)Bp * 256 * 2);
+  w.dZT = (unsigned short*)take((size_t)Bp * 256 * 2);
+  w.dH = (float*)take((size_t)Bp * 256 * 4);
+  return w;
+}
+
+// The allocation-free training step's workspace: one copy per device, held until the process
+// ends, large enough for STREAMI_MLP_NOALLOC_MAX_BATCH rows.  Host code never passes this
+// name to a kernel (on the host it is only a stand-in): it uses the device address
+// hipGetSymbolAddress returns for the current device.
+constexpr long long NOALLOC_ROWS = (STREAMI_MLP_NOALLOC_MAX_BATCH + 31) / 32 * 32;
+static __device__ __align__(256) char scratch[workspace_bytes(NOALLOC_ROWS)];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[MAX_DEVICES] = {};
+
+// The current device's copy of `scratch`, looked up once per device.
+int scratch_for_current_device(char** out) {
+  int dev = 0;
+  MHIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return mfail(STREAMI_E_UNSUPPORTED, "device %d beyond the %d supported", dev, MAX_DEVICES);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    MHIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return mfail(STREAMI_E_DEVICE, "no device address for the training workspace");
+    g_scratch_ptr[dev] = (char*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return STREAMI_OK;
+}
+
+// One training step on workspace w (forward, backward, Adam, outputs): shared by both entry points.
+int train_step_on(streami_mlp_s* m, const Workspace& w, const float* xyz, const float* target, long long batch,
+                  long long Bp, float lr, float* loss_out, float* grads_out) {
+  MHIP(hipMemsetAsync(m->loss, 0, 4, m->stream));
+  forward(m, w, xyz, 3, batch, Bp, nullptr, target, true, m->stream);
+  backward(m, w, Bp);
+  MHIP(hipGetLastError());
+  if (grads_out) {  // gradients of this step, in the parameter order of streami_mlp_set_params
+    size_t off = 0;
+    for (int l = 0; l < NL; ++l) {
+      MHIP(hipMemcpy2DAsync(grads_out + off, (size_t)WID[l] * 4, m->gW[l], (size_t)IN_PAD[l] * 4, (size_t)WID[l] * 4,
+                            WID[l + 1], hipMemcpyDeviceToHost, m->stream));
+      off += (size_t)WID[l + 1] * WID[l];
+      MHIP(hipMemcpyAsync(grads_out + off, m->gb[l], (size_t)WID[l + 1] * 4, hipMemcpyDeviceToHost, m->stream));
+      off += WID[l + 1];
+    }
+  }
+  if (lr > 0) {
+    ++m->t;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float c1 = 1.0f - powf(b1, (float)m->t), c2 = 1.0f - powf(b2, (float)m->t);
+    for (int l = 0; l < NL; ++l) {
+      hipLaunchKernelGGL(k_adam, dim3(grid_for((long long)WID[l + 1] * WID[l])), dim3(256), 0, m->stream, m->W[l],
+                         m->mW[l], m->vW[l], m->gW[l], WID[l + 1], WID[l], IN_PAD[l], lr, b1, b2, eps, c1, c2);
+      hipLaunchKernelGGL(k_adam, dim3(grid_for(WID[l + 1])), dim3(256), 0, m->stream, m->b[l], m->mb[l], m->vb[l],
+                         m->gb[l], 1, WID[l + 1], WID[l + 1], lr, b1, b2, eps, c1, c2);
+    }
+    refresh_bf16(m);
+  }
+  if (loss_out) {
+    float s = 0;
+    MHIP(hipMemcpyAsync(&s, m->loss, 4, hipMemcpyDeviceToHost, m->stream));
+    MHIP(hipStreamSynchronize(m->stream));
+    *loss_out = s / (float)(batch * 3);
+  } else if (grads_out) {
+    MHIP(hipStreamSynchronize(m->stream));
+  }
+  MHIP(hipGetLastError());
+  return STREAMI_OK;
 }
 
 }  // namespace
@@ -613,42 +714,23 @@ int streami_mlp_train_step(streami_mlp m, const float* xyz, const float* target,
   const long long Bp = (batch + 31) / 32 * 32;
   int rc = ensure_batch(m, Bp);
   if (rc) return rc;
-  MHIP(hipMemsetAsync(m->loss, 0, 4, m->stream));
-  forward(m, xyz, 3, batch, Bp, nullptr, target, true, m->stream);
-  backward(m, Bp);
-  MHIP(hipGetLastError());
-  if (grads_out) {  // gradients of this step, in the parameter order of streami_mlp_set_params
-    size_t off = 0;
-    for (int l = 0; l < NL; ++l) {
-      MHIP(hipMemcpy2DAsync(grads_out + off, (size_t)WID[l] * 4, m->gW[l], (size_t)IN_PAD[l] * 4, (size_t)WID[l] * 4,
-                            WID[l + 1], hipMemcpyDeviceToHost, m->stream));
-      off += (size_t)WID[l + 1] * WID[l];
-      MHIP(hipMemcpyAsync(grads_out + off, m->gb[l], (size_t)WID[l + 1] * 4, hipMemcpyDeviceToHost, m->stream));
-      off += WID[l + 1];
-    }
-  }
-  if (lr > 0) {
-    ++m->t;
-    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-    const float c1 = 1.0f - powf(b1, (float)m->t), c2 = 1.0f - powf(b2, (float)m->t);
-    for (int l = 0; l < NL; ++l) {
-      hipLaunchKernelGGL(k_adam, dim3(grid_for((long long)WID[l + 1] * WID[l])), dim3(256), 0, m->stream, m->W[l],
-                         m->mW[l], m->vW[l], m->gW[l], WID[l + 1], WID[l], IN_PAD[l], lr, b1, b2, eps, c1, c2);
-      hipLaunchKernelGGL(k_adam, dim3(grid_for(WID[l + 1])), dim3(256), 0, m->stream, m->b[l], m->mb[l], m->vb[l],
-                         m->gb[l], 1, WID[l + 1], WID[l + 1], lr, b1, b2, eps, c1, c2);
-    }
-    refresh_bf16(m);
-  }
-  if (loss_out) {
-    float s = 0;
-    MHIP(hipMemcpyAsync(&s, m->loss, 4, hipMemcpyDeviceToHost, m->stream));
-    MHIP(hipStreamSynchronize(m->stream));
-    *loss_out = s / (float)(batch * 3);
-  } else if (grads_out) {
-    MHIP(hipStreamSynchronize(m->stream));
-  }
-  MHIP(hipGetLastError());
-  return STREAMI_OK;
+  return train_step_on(m, m->ws, xyz, target, batch, Bp, lr, loss_out, grads_out);
+}
+
+int streami_mlp_train_step_noalloc(streami_mlp m, const float* xyz, const float* target, int64_t batch, float lr,
+                                   float* loss_out, float* grads_out) {
+  if (!m || !xyz || !target) return mfail(STREAMI_E_ARG, "NULL argument");
+  if (batch < 1 || batch > STREAMI_MLP_NOALLOC_MAX_BATCH)
+    return mfail(STREAMI_E_ARG, "batch must be in [1, %d] for the allocation-free training step",
+                 (int)STREAMI_MLP_NOALLOC_MAX_BATCH);
+  if (!(lr >= 0)) return mfail(STREAMI_E_ARG, "lr must be >= 0");
+  char* ws = nullptr;
+  int rc = scratch_for_current_device(&ws);
+  if (rc) return rc;
+  const long long Bp = (batch + 31) / 32 * 32;
+  // every workspace element a step reads is written earlier in the same step (padded rows
+  // included), so the previous call's contents need no clearing
+  return train_step_on(m, carve_workspace(ws, Bp), xyz, target, batch, Bp, lr, loss_out, grads_out);
 }
 
 }  // extern "C"
