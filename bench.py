@@ -254,9 +254,10 @@ def surrogate_bench(args):
 
 def batched_bench(args, unsteady=False):
     """96 uneven FP16 blocks with uneven seed sets and trajectory lengths in one persistent
-    launch (hipGraph replay, autotuned launch shape); unsteady: 16 time slices and
-    streakline emitters releasing a particle every 10 steps, in one launch or, with
-    --window-steps, in global-time windows (bit-identical results)."""
+    launch (hipGraph replay, autotuned launch shape); unsteady: 16 time slices of the
+    512-mode generator with drifting phases, every seed a streakline emitter releasing a
+    particle every 10 steps, in one launch or, with --window-steps, in global-time windows
+    (bit-identical results)."""
     import torch
     import fieldgen as fg
     import paper_2606_02627_amd as S
@@ -265,28 +266,37 @@ def batched_bench(args, unsteady=False):
     h = 0.5
     t0 = time.perf_counter()
     window = 0
+    nodes = None
+    emit_every = 10
     if unsteady:
-        blocks, emit, elim = fg.batched_blocks(n_blocks=96, fmt=fg.F16, n_slices=16, n_modes=64,
-                                               seed_scale=float(os.environ.get("STREAMI_STREAK_SCALE", 1 / 16)))
-        seeds, limits, births = [], [], []
-        for e, m in zip(emit, elim):
-            pos, tb, lim, _ = fg.streakline_particles(e, m, 10, h)
-            seeds.append(pos), limits.append(lim), births.append(tb)
+        # the node values of 96 blocks x 16 slices x 512 modes are generated on the GPU
+        from fieldgen import device as fgd
+        blocks, nodes, emitters, elim = fgd.batched_blocks(n_blocks=96, fmt=fg.F16, n_slices=16, n_modes=512,
+                                                           log=log)
+        n_emitters = sum(len(e) for e in emitters)
+        dseeds, dlim, dtb = [], [], []
+        for e, m in zip(emitters, elim):
+            pos, tb, lim, _ = fgd.streakline_particles(torch.from_numpy(e).cuda(), torch.from_numpy(m).cuda(),
+                                                       emit_every, h)
+            dseeds.append(pos), dlim.append(lim), dtb.append(tb)
         stride = 1 << 20  # a streakline is the emitters' particles' final positions: keep seed + last vertex
         window = args.window_steps
-        t_last = max(float((tb + lim * h).max()) for tb, lim in zip(births, limits))
+        t_last = max(float((tb.double() + lim.double() * h).max()) for tb, lim in zip(dtb, dlim))
         t_ends = [k * window * h for k in range(1, int(np.ceil(t_last / (window * h))) + 1)] if window else []
+        cands = [dict(waves_per_cu=w, refill_threshold=1, work_order=o) for w in (16, 32) for o in (0, 1)]
     else:
         blocks, seeds, limits = fg.batched_blocks(n_blocks=96, fmt=fg.F16)
-        births = None
+        n_emitters = 0
+        dseeds = [torch.from_numpy(x).cuda() for x in seeds]
+        dlim = [torch.from_numpy(x).cuda() for x in limits]
+        dtb = None
         stride = 1
         t_ends = []
-    n_part = sum(len(x) for x in seeds)
+        cands = None
+    n_part = sum(int(x.shape[0]) for x in dseeds)
+    torch.cuda.synchronize()
     log(f"inputs: {len(blocks)} blocks, {n_part} particles, {len(t_ends)} time windows, "
         f"generated in {time.perf_counter() - t0:.1f}s")
-    dseeds = [torch.from_numpy(x).cuda() for x in seeds]
-    dlim = [torch.from_numpy(x).cuda() for x in limits]
-    dtb = [torch.from_numpy(x).cuda() for x in births] if births else None
 
     def one_pass(f, cfg, stats=False):
         """Seed every block, then advect everything: one launch, or one per time window.
@@ -306,12 +316,14 @@ def batched_bench(args, unsteady=False):
                 tot["dev_ms"] += st.device_ms
         return st, tot
 
-    sig = dict(seeds=[len(x) for x in seeds], h=h, stride=stride, windows=len(t_ends), unsteady=unsteady)
+    sig = dict(seeds=[int(x.shape[0]) for x in dseeds], h=h, stride=stride, windows=len(t_ends), unsteady=unsteady,
+               n_modes=512, emit_every=emit_every if unsteady else 0)
     tuned = autotune.load(blocks, fg.F16, sig)
     if tuned is None:
-        tuned = autotune.tune(blocks, fg.F16, one_pass, sig, log=log, repeats=1 if unsteady else 2)
+        tuned = autotune.tune(blocks, fg.F16, one_pass, sig, log=log, repeats=1 if unsteady else 2, nodes=nodes,
+                              candidates=cands)
     cfg = {k: tuned[k] for k in ("waves_per_cu", "refill_threshold", "work_order")}
-    f = S.Field(blocks, fg.F16, layout=tuned["layout"])
+    f = S.Field(blocks, fg.F16, layout=tuned["layout"], nodes=nodes)
     st0, tot = one_pass(f, cfg, stats=True)
     assert st0.active == 0, "particles left after the last call"
     for _ in range(max(0, args.warmup - 1)):
@@ -324,8 +336,11 @@ def batched_bench(args, unsteady=False):
     wall = (time.perf_counter() - t) / args.steps
     steps_per_pass = tot["steps"]
     dev_ms = tot["dev_ms"]
+    outbox_per_pass = int(st0.outbox)
+    f.close()  # the baseline below holds the same particles again
     # baseline: the same work as one launch per block (one unbounded launch each)
-    fields = [S.Field([b], fg.F16, layout=tuned["layout"]) for b in blocks]
+    fields = [S.Field([b], fg.F16, layout=tuned["layout"], nodes=None if nodes is None else [nodes[k]])
+              for k, b in enumerate(blocks)]
 
     def per_block_pass():
         for k, fb in enumerate(fields):
@@ -346,7 +361,7 @@ def batched_bench(args, unsteady=False):
     alg = steps_per_pass * vals * 2 + tot["vertices"] * 12
     # a refill of a time-sliced field reads the cell in both bracketing slices
     refill = (96 if tuned["layout"] == S.LAYOUT_CELL else 8 * 8) * (2 if unsteady else 1)
-    comp = compulsory_bytes(tot["gathers"], refill, tot["vertices"], n_part, int(st0.outbox))
+    comp = compulsory_bytes(tot["gathers"], refill, tot["vertices"], n_part, outbox_per_pass)
     achieved = comp["total"] / (dev_ms * 1e-3) / 1e9
     out = {
         "metric": "RK4 particle-steps/s + HBM GB/s; surrogate vs plain at fixed endpoint error",
@@ -354,7 +369,8 @@ def batched_bench(args, unsteady=False):
         "ms_per_step": wall * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f16 storage, f32 math", "data": "synthetic",
         "config": {"workload": "batched96-f16" + ("-streaklines" if unsteady else ""), "blocks": len(blocks),
-                   "particles": n_part, "particle_steps_per_step": steps_per_pass, "slices": 16 if unsteady else 1,
+                   "particles": n_part, "emitters": n_emitters, "emit_every_steps": emit_every if unsteady else None,
+                   "fourier_modes": 512, "particle_steps_per_step": steps_per_pass, "slices": 16 if unsteady else 1,
                    "window_steps": window, "time_windows": len(t_ends),
                    "tuned": {k: tuned[k] for k in ("layout", "waves_per_cu", "refill_threshold", "work_order")},
                    "graph": not t_ends},
@@ -369,7 +385,6 @@ def batched_bench(args, unsteady=False):
         "batching_speedup": wall_pb / wall,
         "terminated": list(st0.terminated),
     }
-    f.close()
     print(json.dumps(out), flush=True)
 
 

@@ -43,20 +43,23 @@ def load(blocks, fmt, sig):
         return None
 
 
-def tune(blocks, fmt, pass_fn, sig, log=None, repeats=2):
+def tune(blocks, fmt, pass_fn, sig, log=None, repeats=2, nodes=None, candidates=None):
     """Return the fastest configuration {layout, waves_per_cu, refill_threshold, work_order, ms}.
 
     pass_fn(field, cfg) runs one whole pass on `field` (a Field over `blocks` with the
     candidate's layout) with advect keyword arguments `cfg`; it is timed by wall clock
     between two device synchronisations.  `sig` (JSON-able) names everything else the
-    pass depends on (seed counts, step, windows) for the cache key.
+    pass depends on (seed counts, step, windows) for the cache key.  `nodes` (optional)
+    are the blocks' stored nodes when the blocks do not carry them; `candidates` (optional)
+    replaces the launch shapes tried under each layout (a pass of seconds cannot afford all).
     """
+    cands = CANDIDATES if candidates is None else list(candidates)
     from . import Field
     import torch
     best = None
     trials = []
     for layout in _layouts(blocks, fmt):
-        f = Field(blocks, fmt, layout=layout)
+        f = Field(blocks, fmt, layout=layout, nodes=nodes)
 
         def one(cfg):
             torch.cuda.synchronize()
@@ -65,8 +68,8 @@ def tune(blocks, fmt, pass_fn, sig, log=None, repeats=2):
             torch.cuda.synchronize()
             return (time.perf_counter() - t) * 1e3
 
-        one(CANDIDATES[0])  # warm-up
-        for cfg in CANDIDATES:
+        one(cands[0])  # warm-up
+        for cfg in cands:
             ms = min(one(cfg) for _ in range(repeats))
             trials.append(dict(layout=layout, ms=ms, **cfg))
             if log:

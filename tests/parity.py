@@ -89,3 +89,41 @@ def boundary_sensitive(orc, gpu_lines, dev, lo, hi, eps=1e-6, field=None):
         speed = np.linalg.norm(v, axis=1)
         sens |= ok & (speed < 2 * eps) & (speed > eps / 2)
     return sens
+
+
+def restart_check(field, lines, h, lo, hi, max_steps, stride=1, back=16, t_birth=None, eps=1e-6):
+    """Discrete results from a late restart.  For each particle the oracle starts from the
+    GPU's own recorded vertex at least `back` steps before the particle's last step (vertex j
+    is step j*stride; the final vertex is the last step), at that vertex's time and with the
+    steps its limit leaves, and must end with the same termination code at the same step count.
+    Over so few steps the two sides differ by rounding only, so only terminations within
+    10x that difference (plus 1e-5) of a face of the owned bounds, or with |v| within a factor
+    2 of eps, are exempt -- unlike the whole-trajectory comparison, whose exemption margin grows
+    with chaotic drift.  Returns (compared fraction, indices of mismatches)."""
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    off = lines["offsets"]
+    n = lines["steps"].astype(np.int64)
+    k = len(n)
+    nv = np.diff(off)
+    m = np.broadcast_to(np.asarray(max_steps, np.int64), (k,))
+    tb = np.zeros(k) if t_birth is None else np.broadcast_to(np.asarray(t_birth, np.float64), (k,))
+    # restart vertex: the last recorded vertex at or before step n - back (never the final one
+    # unless it is the only one)
+    j = np.clip((n - back) // stride, 0, None)
+    j = np.minimum(j, np.maximum(nv - 2, 0))
+    start = lines["xyz"][off[:-1] + j].astype(np.float64)
+    done = j * stride
+    hf = float(np.float32(h))
+    ref = field.trace(start, hf, (m - done).astype(np.int32), eps=eps, t_birth=tb + done * hf, keep_verts=False)
+    final = lines["xyz"][off[1:] - 1].astype(np.float64)
+    d = np.abs(final - ref["final_pos"]).max(axis=1)
+    margin = 10 * d[:, None] + 1e-5
+    sens = np.zeros(k, bool)
+    for P in (ref["final_pos"], final):
+        sens |= np.any(np.minimum(np.abs(P - lo), np.abs(P - hi)) <= margin, axis=1)
+    v, ok = field.sample(ref["final_pos"])
+    speed = np.linalg.norm(v, axis=1)
+    sens |= ok & (speed < 2 * eps) & (speed > eps / 2)
+    bad = ~sens & ((ref["steps"] + done != n) | (ref["code"] != lines["codes"]))
+    return float((~sens).mean()), np.nonzero(bad)[0]

@@ -86,3 +86,54 @@ def test_partition_samples_the_whole_field():
         vol += np.prod(np.array(p.hi) - np.array(p.lo))
         assert p.rank_grid == (3, 2, 2)
     assert vol == 12 * 8 * 16
+
+
+def _near_tie(values, fmt):
+    """True where an FP64 value lies within 1e-12 (relative) of a rounding tie of fmt: two
+    correct evaluations of the same sum may then round to different stored values."""
+    mant = {fg.F16: 10, fg.BF16: 7}[fmt]
+    emin = {fg.F16: -14, fg.BF16: -126}[fmt]
+    _, e = np.frexp(values)
+    ulp = np.ldexp(1.0, np.maximum(e - 1, emin) - mant)
+    frac = np.abs(values / ulp - np.floor(values / ulp) - 0.5)
+    return frac * ulp <= 1e-12 * np.maximum(np.abs(values), 1e-300)
+
+
+def test_rne_torch_matches_host_quantiser():
+    from fieldgen import device as fgd
+    rng = np.random.default_rng(11)
+    x = np.concatenate([rng.normal(size=50000), rng.normal(size=5000) * 1e-6, rng.normal(size=2000) * 1e-9,
+                        [0.0, -0.0, 0.5 + 2 ** -12, 0.5 + 3 * 2 ** -12, 1 + 2 ** -8, 1 + 3 * 2 ** -8, 65504.0]])
+    t = torch.from_numpy(x)
+    for fmt in (fg.F16, fg.BF16):
+        got = fgd.rne_torch(t, fmt).numpy().view(np.uint16)
+        np.testing.assert_array_equal(got, fg.quantize(x, fmt))
+    np.testing.assert_array_equal(fgd.rne_torch(t, fg.F32).numpy(), fg.quantize(x, fg.F32))
+
+
+def test_device_turbulence_equals_host_turbulence():
+    """The torch generator (run here on the CPU) gives the host generator's field: FP64 values
+    within summation-order rounding, stored values identical except at rounding ties."""
+    from fieldgen import device as fgd
+    dims, S = (21, 17, 26), 3
+    ref = fg.turbulence_values(79, dims, sub=2, n_modes=48, n_slices=S)
+    for fmt in (fg.F16, fg.BF16):
+        stored, vals = fgd.turbulence_stored(79, dims, sub=2, n_modes=48, n_slices=S, fmt=fmt, device="cpu",
+                                             want_values=True)
+        assert stored.shape == (S, dims[2] + 2, dims[1] + 2, dims[0] + 2, 3)
+        np.testing.assert_allclose(vals.numpy(), ref, rtol=0, atol=1e-13)
+        got = stored.numpy().view(np.uint16)
+        want = fg.quantize(ref, fmt)
+        differ = got != want
+        assert not (differ & ~_near_tie(ref, fmt)).any()
+        assert differ.mean() < 1e-4
+
+
+def test_device_streakline_particles_equal_host_ones():
+    from fieldgen import device as fgd
+    em = fg.uniform_seeds(4, 300, (0, 0, 0), (40, 50, 60), sub=7)
+    lim = fg.int_uniform(4, fg.P_MAXSTEPS, 300, 1, 95, sub=3).astype(np.int32)
+    ref = fg.streakline_particles(em, lim, 10, 0.5)
+    got = fgd.streakline_particles(torch.from_numpy(em), torch.from_numpy(lim), 10, 0.5)
+    for a, b in zip(got, ref):
+        np.testing.assert_array_equal(a.numpy(), b)

@@ -55,6 +55,13 @@ def test_forward_matches_oracle(S):
 
 
 def test_gradients_match_oracle(S):
+    """Gradients against the oracle that rounds only the weights and the input to BF16, not the
+    hidden activations or back-propagated gradients.  The kernels round each of the four hidden
+    layers' activations and each layer's incoming gradient to BF16 (relative error up to 2^-9
+    each, about 2^-9/sqrt(3) rms); summed over the eight rounding points of the backward chain
+    that is about 8 * 1.1e-3 ~ 1e-2 relative in the worst layer, so this comparison allows 2e-2
+    and cosine 0.9998.  The bound of the parity contract (1e-2, 0.9999) applies to the oracle
+    that rounds where the kernels do: test_gradients_match_rounded_oracle."""
     import torch
     note("mlp gradients")
     params = fg.mlp_init(5, sub=1)
