@@ -50,6 +50,7 @@ extern "C" {
 #define STREAMI_E_STATE 4       /* call not valid in the handle's current state */
 #define STREAMI_E_CAPACITY 5    /* output buffer too small; required size reported */
 #define STREAMI_E_UNSUPPORTED 6 /* valid request this build does not implement */
+#define STREAMI_E_IO 7          /* a file could not be opened or written */
 
 /* ---- node storage formats (the GPU never quantises: nodes arrive in this format) ---- */
 #define STREAMI_F32 0
@@ -166,7 +167,48 @@ typedef struct {
 int streami_seed(streami_field f, int32_t block, const float* xyz, const uint64_t* ids,
                  const int32_t* max_steps, int64_t n, const streami_seed_opts* opts);
 
-/* One seed batch of streami_seed_batches(): the arguments of one
+/* A control shape for streami_seed_shape(). */
+#define STREAMI_SHAPE_LINE 0
+#define STREAMI_SHAPE_PLANE 1
+typedef struct {
+  int32_t kind;     /* STREAMI_SHAPE_LINE or STREAMI_SHAPE_PLANE */
+  double origin[3]; /* line: start point; plane: corner */
+  double u[3];      /* line: end - start; plane: first edge */
+  double v[3];      /* plane: second edge (ignored for a line) */
+  int64_t nu;       /* points along u, >= 0 */
+  int64_t nv;       /* points along v, >= 1 (ignored for a line: 1) */
+} streami_shape;
+
+/*
+ * Uniformly distributed seed points on a simple control shape, generated on
+ * the device (Sec. 3.1.2: the low-level interface's convenience kernels seed
+ * planes and lines).  Point k = i + nu*j (i fastest) is the midpoint-rule
+ * sample  origin + ((2i+1)/(2 nu)) u + ((2j+1)/(2 nv)) v  of the segment
+ * (nv = 1, v = 0) or parallelogram, evaluated in FP32 from the FP32-rounded
+ * shape (correctly rounded parameters, two fused multiply-adds per
+ * coordinate: within 3 ulp of |origin|+|u|+|v| of the exact point).  The
+ * points are then seeded exactly as streami_seed() seeds an array of them:
+ * same ids, limits (max_steps: nu*nv limits or NULL, host or device as
+ * opts->inputs_on_device says), birth times, record stride, and the same
+ * treatment of points outside the owned bounds.  The point array is a call
+ * temporary.  Errors: E_ARG (bad block, kind, counts, a non-finite shape or
+ * more than 2^31 points), then those of streami_seed().
+ */
+int streami_seed_shape(streami_field f, int32_t block, const streami_shape* shape, const int32_t* max_steps,
+                       const streami_seed_opts* opts);
+
+/*
+ * Path lines (Sec. 3.2 names them as a further line kind the framework makes
+ * easy): the trajectory of one particle through a time-varying field.  They
+ * need no call of their own: seed the particles of a field with time slices
+ * (n_slices > 1) at their release times (opts->t_birth or t_births), with
+ * record_stride = 1, and advect; each line fetched by streami_fetch_lines()
+ * is then the particle's path line, vertex i at time t_birth + i*h.
+ * Streamlines are the same call on a steady field, streaklines the
+ * emitters' particles' final positions ordered by release time.
+ */
+
+/* One seed batch of streami_seed_batches(): the arguments of one/* One seed batch of streami_seed_batches(): the arguments of one
  * streami_seed() call (birth times per batch instead of in the options). */
 typedef struct {
   int32_t block;
@@ -376,7 +418,34 @@ int streami_mlp_train_step(streami_mlp m, const float* xyz, const float* target,
 int streami_mlp_train_step_noalloc(streami_mlp m, const float* xyz, const float* target, int64_t batch, float lr,
                                    float* loss_out, float* grads_out);
 
-/* Thread-local description of the last error. */
+/* ---------------------------------------------------------------------------
+ * Wavefront OBJ output of field lines (Sec. 4: the command line app writes the
+ * lines of all particles, gathered over every time step and rank, to one joint
+ * obj file of line elements).  Host-side; no device work.
+ * ------------------------------------------------------------------------- */
+
+/*
+ * Write n_lines polylines given as CSR host arrays (offsets[n_lines+1], xyz
+ * [offsets[n_lines]*3] FP32) to `path`: one "v x y z" record per vertex (%.9g,
+ * which reads back as the same FP32 value), then one "l a b c ..." element
+ * per line with at least two vertices (1-based indices); a line with fewer
+ * vertices contributes its vertex records but no element.  append = 0 creates
+ * or truncates the file, 1 appends to it; *vertex_base (in/out, nullable =
+ * 0) is the number of vertex records already in the file and is advanced past
+ * this call's, so repeated appends build one joint file.  Errors: E_ARG (NULL
+ * arrays with n_lines > 0, decreasing offsets), E_IO (open/write failure).
+ */
+int streami_write_obj(const char* path, int64_t n_lines, const int64_t* offsets, const float* xyz, int32_t append,
+                      int64_t* vertex_base);
+
+/*
+ * The lines of every block of a handle, in block then seed order, fetched to
+ * the host and written as one OBJ file (created or truncated).  Errors: those
+ * of streami_fetch_lines() and streami_write_obj(), E_NOMEM for host buffers.
+ */
+int streami_write_obj_field(streami_field f, const char* path);
+
+/* Thread-local description of the last error. *//* Thread-local description of the last error. */
 const char* streami_last_error(void);
 
 #ifdef __cplusplus

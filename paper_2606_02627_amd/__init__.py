@@ -21,7 +21,8 @@ except ImportError:  # pragma: no cover - torch is part of the supported environ
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libstreami.so")
 
-OK, E_ARG, E_NOMEM, E_DEVICE, E_STATE, E_CAPACITY, E_UNSUPPORTED = range(7)
+OK, E_ARG, E_NOMEM, E_DEVICE, E_STATE, E_CAPACITY, E_UNSUPPORTED, E_IO = range(8)
+SHAPE_LINE, SHAPE_PLANE = 0, 1
 F32, F16, BF16 = 0, 1, 2
 BOUNDARY_BLOCK, BOUNDARY_PERIODIC = 0, 1
 ACTIVE, MAX_STEPS, EXIT, STAGNANT, HALO_MISS, NONFINITE = range(6)
@@ -58,6 +59,11 @@ class SeedOpts(ctypes.Structure):
 class SeedBatch(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("xyz", ctypes.c_void_p), ("ids", ctypes.c_void_p),
                 ("max_steps", ctypes.c_void_p), ("t_births", ctypes.c_void_p), ("n", ctypes.c_int64)]
+
+
+class Shape(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("origin", ctypes.c_double * 3), ("u", ctypes.c_double * 3),
+                ("v", ctypes.c_double * 3), ("nu", ctypes.c_int64), ("nv", ctypes.c_int64)]
 
 
 class AdvectParams(ctypes.Structure):
@@ -105,6 +111,9 @@ def _load():
         "streami_field_destroy": [vp],
         "streami_seed": [vp, i32, vp, vp, vp, i64, vp],
         "streami_seed_batches": [vp, vp, i32, vp],
+        "streami_seed_shape": [vp, i32, vp, vp, vp],
+        "streami_write_obj": [ctypes.c_char_p, i64, vp, vp, i32, vp],
+        "streami_write_obj_field": [vp, ctypes.c_char_p],
         "streami_advect": [vp, vp, vp],
         "streami_fetch_lines": [vp, i32, i64, i64, vp, vp, i64, vp, vp, vp, vp],
         "streami_fetch_outbox": [vp, vp, i64, vp],
@@ -242,6 +251,39 @@ def streami_seed_batches(f, batches, default_max_steps=0, record_stride=1, t_bir
     return _check(_load().streami_seed_batches(f, arr, len(batches), ctypes.byref(opts)))
 
 
+def streami_seed_shape(f, block, kind, origin, u, v=(0.0, 0.0, 0.0), nu=1, nv=1, max_steps=None,
+                       default_max_steps=0, record_stride=1, t_birth=0.0, t_births=None):
+    """Seed an nu x nv midpoint grid on a line (origin, origin + u) or a parallelogram
+    (origin, edges u and v), generated on the device."""
+    sh = Shape(kind=int(kind), nu=int(nu), nv=int(nv))
+    sh.origin[:] = [float(c) for c in origin]
+    sh.u[:] = [float(c) for c in u]
+    sh.v[:] = [float(c) for c in v]
+    pm, dm = _addr(max_steps)
+    pt, dt = _addr(t_births)
+    if max_steps is not None and t_births is not None and dm != dt:
+        raise ValueError("max_steps and t_births must both be host or both device arrays")
+    on_dev = dm if max_steps is not None else dt
+    opts = SeedOpts(default_max_steps=int(default_max_steps), record_stride=int(record_stride),
+                    inputs_on_device=int(bool(on_dev)), t_birth=float(t_birth),
+                    t_births=None if pt is None else pt.value)
+    return _check(_load().streami_seed_shape(f, int(block), ctypes.byref(sh), pm, ctypes.byref(opts)))
+
+
+def streami_write_obj(path, offsets, xyz, append=False, vertex_base=0):
+    """Write CSR lines (host arrays) as an OBJ file; returns the vertex count after this call."""
+    off = np.ascontiguousarray(offsets, np.int64)
+    pts = np.ascontiguousarray(xyz, np.float32)
+    base = ctypes.c_int64(int(vertex_base))
+    _check(_load().streami_write_obj(os.fsencode(path), len(off) - 1, _addr(off)[0], _addr(pts)[0], int(append),
+                                     ctypes.byref(base)))
+    return base.value
+
+
+def streami_write_obj_field(f, path):
+    return _check(_load().streami_write_obj_field(f, os.fsencode(path)))
+
+
 def streami_advect(f, params: AdvectParams, want_stats=True):
     st = Stats() if want_stats else None
     _check(_load().streami_advect(f, ctypes.byref(params), ctypes.byref(st) if st else None))
@@ -367,6 +409,12 @@ class Field:
 
     def seed_batches(self, batches, **kw):
         return streami_seed_batches(self.h, batches, **kw)
+
+    def seed_shape(self, block, kind, origin, u, v=(0.0, 0.0, 0.0), nu=1, nv=1, **kw):
+        return streami_seed_shape(self.h, block, kind, origin, u, v, nu, nv, **kw)
+
+    def write_obj(self, path):
+        return streami_write_obj_field(self.h, path)
 
     def advect(self, h, **kw):
         return streami_advect(self.h, advect_params(h, **kw))

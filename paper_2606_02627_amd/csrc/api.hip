@@ -43,6 +43,8 @@ int launch_work_order(const float4* pos, const int4* meta, const int4* meta2, co
                       unsigned* cursor, int* order, unsigned* n_work, hipStream_t st);
 int launch_fill_u64(unsigned long long* p, long long n, unsigned long long v, hipStream_t st);
 int launch_seed_bound(const SeedJobs& J, long long total, unsigned long long* out, hipStream_t st);
+int launch_seed_shape(const double o[3], const double u[3], const double v[3], long long nu, long long nv, float* out,
+                      hipStream_t st);
 int launch_gather_meta(const long long* idx, long long count, const int4* meta, const int4* meta2,
                        const unsigned long long* pid, long long* nverts, int* steps, int* codes,
                        unsigned long long* ids, hipStream_t st);
@@ -455,6 +457,10 @@ int advect_surrogate(streami_field_s* f, const streami_advect_params* p, streami
 
 }  // namespace
 
+namespace streami {
+int block_count(streami_field f) { return (int)f->blocks.size(); }
+}  // namespace streami
+
 extern "C" {
 
 const char* streami_last_error(void) { return g_err.c_str(); }
@@ -795,6 +801,60 @@ int streami_seed(streami_field f, int32_t block, const float* xyz, const uint64_
   b.t_births = opts ? opts->t_births : nullptr;
   b.n = n;
   return seed_batches(f, &b, 1, opts);
+}
+
+int streami_seed_shape(streami_field f, int32_t block, const streami_shape* shape, const int32_t* max_steps,
+                       const streami_seed_opts* opts) {
+  if (!f) return fail(STREAMI_E_ARG, "field handle is NULL");
+  if (!shape || !opts) return fail(STREAMI_E_ARG, "shape and opts must not be NULL");
+  if (block < 0 || block >= (int)f->blocks.size()) return fail(STREAMI_E_ARG, "block %d out of range", block);
+  if (shape->kind != STREAMI_SHAPE_LINE && shape->kind != STREAMI_SHAPE_PLANE)
+    return fail(STREAMI_E_ARG, "shape kind must be STREAMI_SHAPE_LINE or STREAMI_SHAPE_PLANE");
+  const bool plane = shape->kind == STREAMI_SHAPE_PLANE;
+  const long long nu = shape->nu, nv = plane ? shape->nv : 1;
+  if (nu < 0 || nv < 1) return fail(STREAMI_E_ARG, "need nu >= 0 and nv >= 1");
+  if (nu > 0 && nv > ((1LL << 31) - 1) / nu) return fail(STREAMI_E_ARG, "more than 2^31 seed points");
+  double v[3] = {0, 0, 0};
+  for (int c = 0; c < 3; ++c) {
+    if (plane) v[c] = shape->v[c];
+    if (!std::isfinite(shape->origin[c]) || !std::isfinite(shape->u[c]) || !std::isfinite(v[c]))
+      return fail(STREAMI_E_ARG, "the shape must be finite");
+  }
+  const long long n = nu * nv;
+  if (n == 0) return STREAMI_OK;
+  // the points, and any host limits and birth times, staged on the device for the call
+  DevBuf xyz, lim, tb;
+  int rc;
+  if ((rc = xyz.reserve(n * 12, 0, f->stream))) return rc;
+  launch_seed_shape(shape->origin, shape->u, v, nu, nv, (float*)xyz.p, f->stream);
+  HIP_TRY(hipGetLastError());
+  const int32_t* d_lim = max_steps;
+  const float* d_tb = opts->t_births;
+  if (!opts->inputs_on_device) {
+    if (max_steps) {
+      if ((rc = lim.reserve(n * 4, 0, f->stream))) return rc;
+      HIP_TRY(hipMemcpyAsync(lim.p, max_steps, n * 4, hipMemcpyHostToDevice, f->stream));
+      d_lim = (const int32_t*)lim.p;
+    }
+    if (opts->t_births) {
+      if ((rc = tb.reserve(n * 4, 0, f->stream))) return rc;
+      HIP_TRY(hipMemcpyAsync(tb.p, opts->t_births, n * 4, hipMemcpyHostToDevice, f->stream));
+      d_tb = (const float*)tb.p;
+    }
+  }
+  streami_seed_opts o = *opts;
+  o.inputs_on_device = 1;
+  o.t_births = nullptr;
+  streami_seed_batch b;
+  b.block = block;
+  b.xyz = (const float*)xyz.p;
+  b.ids = nullptr;
+  b.max_steps = d_lim;
+  b.t_births = d_tb;
+  b.n = n;
+  rc = seed_batches(f, &b, 1, &o);
+  (void)hipStreamSynchronize(f->stream);  // the staged arrays are freed on return
+  return rc;
 }
 
 int streami_seed_batches(streami_field f, const streami_seed_batch* batches, int32_t n_batches,

@@ -3,6 +3,8 @@
 // node pool in the handle's layout (or, for the cell layout, computes each
 // cell's interpolation coefficients); 16-bit nodes are padded to 8 bytes so a
 // node is one aligned 64-bit load in the advection kernel.
+#include <algorithm>
+
 #include "device.h"
 #include "seed.h"
 
@@ -334,6 +336,33 @@ __global__ void k_seed_bound(SeedJobs J, unsigned long long* out) {
 }
 
 // at most 64 workgroups, so the three result atomics do not serialise
+// Seed points on a control shape (Sec. 3.1.2's convenience seeding): point (i, j), i fastest,
+// of an nu x nv midpoint grid on the parallelogram o + s u + t v, s = (2i+1)/(2nu),
+// t = (2j+1)/(2nv); a line segment is the case nv = 1, v = 0.  FP32: the parameters are
+// correctly rounded quotients and each coordinate is two fused multiply-adds.
+__global__ void k_seed_shape(float ox, float oy, float oz, float ux, float uy, float uz, float vx, float vy, float vz,
+                             long long nu, long long nv, float* out) {
+  const long long n = nu * nv;
+  const float du = (float)(2 * nu), dv = (float)(2 * nv);
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x) {
+    const long long i = k % nu, j = k / nu;
+    const float s = (float)(2 * i + 1) / du, t = (float)(2 * j + 1) / dv;
+    out[3 * k + 0] = fmaf(s, ux, fmaf(t, vx, ox));
+    out[3 * k + 1] = fmaf(s, uy, fmaf(t, vy, oy));
+    out[3 * k + 2] = fmaf(s, uz, fmaf(t, vz, oz));
+  }
+}
+
+int launch_seed_shape(const double o[3], const double u[3], const double v[3], long long nu, long long nv, float* out,
+                      hipStream_t st) {
+  const long long n = nu * nv;
+  if (n <= 0) return 0;
+  const long long grid = std::min<long long>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_seed_shape, dim3((unsigned)grid), dim3(256), 0, st, (float)o[0], (float)o[1], (float)o[2],
+                     (float)u[0], (float)u[1], (float)u[2], (float)v[0], (float)v[1], (float)v[2], nu, nv, out);
+  return 0;
+}
+
 int launch_seed_bound(const SeedJobs& J, long long total, unsigned long long* out, hipStream_t st) {
   long long grid = (total + 255) / 256;
   if (grid > 64) grid = 64;

@@ -117,7 +117,7 @@ def test_probe_rejects_invalid_arguments_before_device_work():
 
 
 STRUCTS = [("streami_block_desc", "BlockDesc"), ("streami_field_opts", "FieldOpts"),
-           ("streami_seed_opts", "SeedOpts"), ("streami_seed_batch", "SeedBatch"),
+           ("streami_seed_opts", "SeedOpts"), ("streami_seed_batch", "SeedBatch"), ("streami_shape", "Shape"),
            ("streami_advect_params", "AdvectParams"),
            ("streami_stats", "Stats")]
 
