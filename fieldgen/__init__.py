@@ -34,7 +34,7 @@ DTYPE_NAMES = {F32: "f32", F16: "f16", BF16: "bf16"}
 DTYPE_BYTES = {F32: 4, F16: 2, BF16: 2}
 
 # stream purposes
-P_MODES, P_SEEDS, P_BLOB, P_MAXSTEPS, P_BLOCKSHAPE, P_NSEEDS, P_MLP, P_TRAIN = range(1, 9)
+P_MODES, P_SEEDS, P_BLOB, P_MAXSTEPS, P_BLOCKSHAPE, P_NSEEDS, P_MLP, P_TRAIN, P_HEXJIT = range(1, 10)
 
 
 def build(verbose: bool = False) -> str:
@@ -416,3 +416,55 @@ def streakline_particles(emitters: np.ndarray, limits: np.ndarray, every: int, h
     tb = (bsteps * h).astype(np.float32)
     lim = (np.asarray(limits)[emi] - bsteps).astype(np.int32)
     return pos, tb, lim, emi
+
+
+# ---------------------------------------------------------------------------
+# Hexahedral meshes (unstructured field inputs): vertices, per-vertex values and
+# cells of 8 vertex indices in VTK hexahedron order
+# ---------------------------------------------------------------------------
+VTK_HEX_CORNERS = ((0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0), (0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 1, 1))
+
+
+def _lattice_cells(nx, ny, nz):
+    """Cells of an nx x ny x nz lattice of vertices (x fastest), VTK order, int32 [cells, 8]."""
+    k, j, i = np.meshgrid(np.arange(nz - 1), np.arange(ny - 1), np.arange(nx - 1), indexing="ij")
+    i, j, k = i.ravel(), j.ravel(), k.ravel()
+    return np.stack([(i + a) + nx * ((j + b) + ny * (k + c)) for a, b, c in VTK_HEX_CORNERS], 1).astype(np.int32)
+
+
+def hex_mesh_from_block(blk: Block) -> dict:
+    """Every cell of a steady FP32 block's stored grid as a hexahedron (the paper's conversion of
+    voxel data to an unstructured field): vertices = the stored nodes' world positions, values
+    = the stored node values, same owned bounds and rank grid."""
+    assert blk.n_slices == 1 and blk.fmt == F32 and blk.boundary == BOUNDARY_BLOCK
+    nx, ny, nz = (d + 2 * blk.ghost for d in blk.dims)
+    xs, ys, zs = (_node_coords(d, o, s, blk.ghost) for d, o, s in zip(blk.dims, blk.origin, blk.spacing))
+    Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+    verts = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1).astype(np.float32)
+    return dict(vertices=verts, values=np.ascontiguousarray(blk.stored[0].reshape(-1, 3), np.float32),
+                cells=_lattice_cells(nx, ny, nz), lo=tuple(blk.lo), hi=tuple(blk.hi),
+                rank_grid=tuple(blk.rank_grid), rank_coord=tuple(blk.rank_coord))
+
+
+def distorted_hex_mesh(config: int, dims, jitter: float = 0.2, sub: int = 0, field=None) -> dict:
+    """A conforming mesh of dims = (cx, cy, cz) hexahedra over [0, cx] x [0, cy] x [0, cz]: a unit
+    lattice whose vertices move by up to `jitter` (uniform, per coordinate; vertices on the
+    box's faces stay on them), so cells are general (non-affine) hexahedra.  Values: field(x, y,
+    z) -> (vx, vy, vz) at the vertices (default a smooth divergence-free rotation-like flow),
+    FP32.  Owned bounds: the box."""
+    cx, cy, cz = (int(d) for d in dims)
+    nx, ny, nz = cx + 1, cy + 1, cz + 1
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    base = np.stack([i.ravel(), j.ravel(), k.ravel()], 1).astype(np.float64)
+    jit = (uniform(stream(config, P_HEXJIT, sub), base.size).reshape(-1, 3) * 2 - 1) * jitter
+    for a, n in enumerate((nx, ny, nz)):  # keep face vertices on their faces
+        on = (base[:, a] == 0) | (base[:, a] == n - 1)
+        jit[on, a] = 0.0
+    verts = (base + jit).astype(np.float32)
+    if field is None:
+        def field(x, y, z):
+            return (np.sin(0.4 * z) + 0.5 * np.cos(0.3 * y), 0.6 * np.sin(0.35 * x) + 0.4 * np.cos(0.25 * z),
+                    0.5 * np.sin(0.3 * y) + 0.45 * np.cos(0.4 * x))
+    v = np.stack(field(*verts.astype(np.float64).T), 1)
+    return dict(vertices=verts, values=v.astype(np.float32), cells=_lattice_cells(nx, ny, nz),
+                lo=(0.0, 0.0, 0.0), hi=(float(cx), float(cy), float(cz)), rank_grid=(1, 1, 1), rank_coord=(0, 0, 0))
