@@ -388,6 +388,81 @@ def batched_bench(args, unsteady=False):
     print(json.dumps(out), flush=True)
 
 
+def hex_bench(args):
+    """The default workload's block converted to hexahedra (every cell of its stored grid, as
+    the paper converts voxels for its unstructured field): 257^3 cells located through the
+    BVH, the same 1M seeds and limits, each pass clear -> seed -> advect; the structured
+    field's pass on the same seeds is timed alongside for the ratio."""
+    import torch
+    import fieldgen as fg
+    import paper_2606_02627_amd as S
+    blk, seeds, fmt, m, h, stride = build_inputs("turb256-f32")
+    mesh = fg.hex_mesh_from_block(blk)
+    t0 = time.perf_counter()
+    f = S.Field.hex(mesh)
+    build_s = time.perf_counter() - t0
+    field_bytes = S.streami_field_info(f.h)[1]
+    log(f"hex field: {len(mesh['cells'])} cells, BVH + records built and uploaded in {build_s:.1f}s, "
+        f"{field_bytes / 1e9:.2f} GB")
+    d_seeds = torch.from_numpy(seeds).cuda()
+    stream = torch.cuda.current_stream()
+
+    def passes(fld, k, stats=False):
+        out, ms = None, []
+        for _ in range(k):
+            fld.clear()
+            fld.seed(0, d_seeds, default_max_steps=m, record_stride=stride)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            st = S.streami_advect(fld.h, S.advect_params(h), want_stats=stats)
+            e1.record(stream)
+            out = out or st
+            ms.append((e0, e1))
+        return out, ms
+
+    st0, _ = passes(f, max(1, args.warmup), stats=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, ev = passes(f, args.steps)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t) / args.steps
+    adv_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    f.close()
+    g = S.Field([blk], fmt)
+    stg, _ = passes(g, 1, stats=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, evg = passes(g, args.steps)
+    torch.cuda.synchronize()
+    wall_g = (time.perf_counter() - t) / args.steps
+    g.close()
+    steps = int(st0.steps)
+    # a BVH walk ends by reading the found cell's 192-byte record; every sample re-reads the
+    # lane's current record (from the caches); compulsory: each walk's record once
+    comp = compulsory_bytes(int(st0.gathers), 192, int(st0.vertices), len(seeds), int(st0.outbox))
+    achieved = comp["total"] / (adv_ms * 1e-3) / 1e9
+    out = {
+        "metric": "RK4 particle-steps/s + HBM GB/s; surrogate vs plain at fixed endpoint error",
+        "value": steps / wall, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "hex256-f32", "field": "256^3 + ghost turbulence block, every cell a hexahedron",
+                   "cells": int(len(mesh["cells"])), "vertices": int(len(mesh["vertices"])), "seeds": len(seeds),
+                   "max_steps": m, "h": h, "particle_steps_per_step": steps, "field_bytes": field_bytes},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_advect (hexahedra)",
+                     "mean_launch_ms": adv_ms, "compulsory_bytes_per_launch": comp,
+                     "kernel_hash": kernel_source_hash(),
+                     "reuse": {"alg_bytes_per_launch": steps * 4 * 192 + int(st0.vertices) * 12}},
+        "bvh_walks_per_step": int(st0.gathers) / steps,
+        "build_seconds": build_s,
+        "structured_steps_per_s": int(stg.steps) / wall_g,
+        "hex_over_structured": (steps / wall) / (int(stg.steps) / wall_g),
+        "same_step_count_as_structured": steps == int(stg.steps),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def memory_probe(S, field_bytes, record_bytes):
     """Measured peaks of the memory levels for the kernel's access: a plain device copy (HBM
     stream rate) and random record reads (streami_probe_gather) over footprints that live in
@@ -428,7 +503,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="turb256-f32",
-                    choices=sorted(WORKLOADS) + ["surrogate-abc", "batched96-f16", "batched96-f16-streaklines"])
+                    choices=sorted(WORKLOADS) + ["surrogate-abc", "batched96-f16", "batched96-f16-streaklines",
+                                                 "hex256-f32"])
     ap.add_argument("--window-steps", type=int, default=0,
                     help="streaklines: advance in global-time windows of this many steps (0: one launch)")
     ap.add_argument("--layout", type=int, default=0, help="0 auto, 1 linear, 2 brick4, 3 cell records (FP32)")
@@ -454,6 +530,8 @@ def main():
         return surrogate_bench(args)
     if args.workload.startswith("batched96"):
         return batched_bench(args, unsteady=args.workload.endswith("streaklines"))
+    if args.workload == "hex256-f32":
+        return hex_bench(args)
     dev = torch.device("cuda:0")
     log("building inputs", args.workload)
     t0 = time.perf_counter()

@@ -78,6 +78,7 @@ extern "C" {
  * 8x the bytes of LINEAR, and results bit-identical to LINEAR for steady
  * fields. */
 #define STREAMI_LAYOUT_CELL 3
+#define STREAMI_LAYOUT_HEX 4 /* reported by streami_field_info for a hexahedral field (never requested) */
 
 /* ---- advection modes ---- */
 #define STREAMI_MODE_PLAIN 0
@@ -140,6 +141,40 @@ int streami_field_create(const streami_block_desc* blocks, int32_t n_blocks, int
                          const streami_field_opts* opts, void* hip_stream, streami_field* out);
 
 int streami_field_destroy(streami_field f);
+
+/* An unstructured field of hexahedral cells (Sec. 3.3: the paper's second
+ * field type, located by a bounding volume hierarchy and point containment;
+ * Sec. 5 converts every voxel of a structured data set to a hexahedron). */
+typedef struct {
+  int64_t n_vertices;
+  const float* vertices;   /* [n_vertices][3] world positions */
+  const float* values;     /* [n_vertices][3] FP32 vector values at the vertices */
+  int64_t n_cells;         /* 1 .. 2^28 - 1 */
+  const int32_t* cells;    /* [n_cells][8] vertex indices in VTK hexahedron order:
+                              (0,0,0) (1,0,0) (1,1,0) (0,1,0) (0,0,1) (1,0,1) (1,1,1) (0,1,1) */
+  double bounds_lo[3];     /* owned macrocell, half-open [lo, hi) (Sec. 3.1.1) */
+  double bounds_hi[3];
+  int32_t rank_grid[3];    /* macrocell grid for destinationID() */
+  int32_t rank_coord[3];
+  int32_t inputs_on_device;/* 1: the three arrays are device pointers, 0: host memory */
+} streami_hex_desc;
+
+/*
+ * Create a handle over one hexahedral field.  sample(x) is defined where a
+ * cell holds x: the cell's trilinear map X(r,s,u) (corners as listed above)
+ * is inverted by Newton's method in FP32 and x is accepted when (r,s,u) lies
+ * in [-1e-4, 1 + 1e-4]^3 (slack for points on shared faces); the value is the
+ * same trilinear interpolation of the vertex values.  The library builds, on
+ * the host, a depth-first BVH over the cells' boxes and one 192-byte record per
+ * cell (both maps in monomial form) and keeps them on the device; the caller
+ * keeps ownership of the arrays (read during the call only).  The handle takes
+ * the same seeding, advection (PLAIN mode, steady), fetch, outbox, forwarding
+ * and OBJ calls as a structured one; streami_field_info reports
+ * STREAMI_LAYOUT_HEX.  Errors: E_ARG (NULL arrays, counts out of range, a cell
+ * index outside the vertices, a non-finite vertex, bounds with lo >= hi, a
+ * rank grid < 1 or coordinate outside it), E_NOMEM, E_DEVICE.
+ */
+int streami_field_create_hex(const streami_hex_desc* desc, void* hip_stream, streami_field* out);
 
 /* Seeding options (Sec. 3.2: streamlines seed once at step 0). */
 typedef struct {

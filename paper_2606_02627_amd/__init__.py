@@ -26,7 +26,7 @@ SHAPE_LINE, SHAPE_PLANE = 0, 1
 F32, F16, BF16 = 0, 1, 2
 BOUNDARY_BLOCK, BOUNDARY_PERIODIC = 0, 1
 ACTIVE, MAX_STEPS, EXIT, STAGNANT, HALO_MISS, NONFINITE = range(6)
-LAYOUT_AUTO, LAYOUT_LINEAR, LAYOUT_BRICK4, LAYOUT_CELL = 0, 1, 2, 3
+LAYOUT_AUTO, LAYOUT_LINEAR, LAYOUT_BRICK4, LAYOUT_CELL, LAYOUT_HEX = 0, 1, 2, 3, 4
 MODE_PLAIN, MODE_SURROGATE = 0, 1
 
 
@@ -44,6 +44,13 @@ class BlockDesc(ctypes.Structure):
                 ("rank_coord", ctypes.c_int32 * 3), ("n_slices", ctypes.c_int32),
                 ("t0", ctypes.c_double), ("slice_dt", ctypes.c_double),
                 ("nodes", ctypes.c_void_p), ("nodes_on_device", ctypes.c_int32)]
+
+
+class HexDesc(ctypes.Structure):
+    _fields_ = [("n_vertices", ctypes.c_int64), ("vertices", ctypes.c_void_p), ("values", ctypes.c_void_p),
+                ("n_cells", ctypes.c_int64), ("cells", ctypes.c_void_p), ("bounds_lo", ctypes.c_double * 3),
+                ("bounds_hi", ctypes.c_double * 3), ("rank_grid", ctypes.c_int32 * 3),
+                ("rank_coord", ctypes.c_int32 * 3), ("inputs_on_device", ctypes.c_int32)]
 
 
 class FieldOpts(ctypes.Structure):
@@ -109,6 +116,7 @@ def _load():
     sig = {
         "streami_field_create": [vp, i32, i32, vp, vp, vp],
         "streami_field_destroy": [vp],
+        "streami_field_create_hex": [vp, vp, vp],
         "streami_seed": [vp, i32, vp, vp, vp, i64, vp],
         "streami_seed_batches": [vp, vp, i32, vp],
         "streami_seed_shape": [vp, i32, vp, vp, vp],
@@ -201,6 +209,28 @@ def streami_field_create(descs, dtype, layout=LAYOUT_AUTO, stream=None):
     out = ctypes.c_void_p()
     _check(_load().streami_field_create(arr, len(descs), dtype, ctypes.byref(opts), _stream(stream),
                                         ctypes.byref(out)))
+    return out
+
+
+def streami_field_create_hex(mesh, stream=None):
+    """Handle over a hexahedral field: mesh = dict(vertices [nv,3] f32, values [nv,3] f32, cells
+    [nc,8] int32 (VTK order), lo, hi, rank_grid, rank_coord), all host or all device arrays."""
+    arrs = [mesh["vertices"], mesh["values"], mesh["cells"]]
+    if isinstance(arrs[0], np.ndarray):
+        arrs = [np.ascontiguousarray(arrs[0], np.float32), np.ascontiguousarray(arrs[1], np.float32),
+                np.ascontiguousarray(arrs[2], np.int32)]
+    ptrs = [_addr(a) for a in arrs]
+    if len({d for _, d in ptrs}) != 1:
+        raise ValueError("vertices, values and cells must all be host or all device arrays")
+    d = HexDesc(n_vertices=int(arrs[0].shape[0]), n_cells=int(arrs[2].shape[0]),
+                inputs_on_device=int(ptrs[0][1]))
+    d.vertices, d.values, d.cells = (p.value for p, _ in ptrs)
+    d.bounds_lo[:] = [float(v) for v in mesh["lo"]]
+    d.bounds_hi[:] = [float(v) for v in mesh["hi"]]
+    d.rank_grid[:] = [int(v) for v in mesh.get("rank_grid", (1, 1, 1))]
+    d.rank_coord[:] = [int(v) for v in mesh.get("rank_coord", (0, 0, 0))]
+    out = ctypes.c_void_p()
+    _check(_load().streami_field_create_hex(ctypes.byref(d), _stream(stream), ctypes.byref(out)))
     return out
 
 
@@ -389,6 +419,15 @@ class Field:
         self._descs = [make_block_desc(b, n) for b, n in zip(blocks, nodes)]
         self.h = streami_field_create(self._descs, dtype, layout, stream)
         self.n_blocks = len(blocks)
+
+    @classmethod
+    def hex(cls, mesh, stream=None):
+        """A handle over a hexahedral field (streami_field_create_hex)."""
+        f = cls.__new__(cls)
+        f._descs = []
+        f.h = streami_field_create_hex(mesh, stream)
+        f.n_blocks = 1
+        return f
 
     def close(self):
         if self.h is not None and self.h.value:

@@ -32,6 +32,7 @@
 #include <type_traits>
 
 #include "device.h"
+#include "hex.h"
 
 namespace streami {
 
@@ -414,6 +415,10 @@ struct PackedSlicesSampler {
 template <int FMT, int LAYOUT, bool PERIODIC, int MODE>
 struct SamplerFor {
   using type = Sampler<FMT, LAYOUT, PERIODIC, MODE == SM_UNSTEADY_UNCACHED ? SM_UNSTEADY : MODE>;
+};
+template <int MODE>
+struct SamplerFor<FMT_F32, LAYOUT_HEX, false, MODE> {
+  using type = HexSampler;
 };
 template <int LAYOUT, bool PERIODIC>
 struct SamplerFor<FMT_F16, LAYOUT, PERIODIC, SM_UNSTEADY> {
@@ -931,8 +936,13 @@ int launch_advect_fmt(const AdvectArgs& a, int layout, bool periodic, int mode, 
   if (FMT == FMT_F32 && mode == SM_UNSTEADY_UNCACHED) mode = SM_UNSTEADY;  // the same sampler
   if constexpr (FMT == FMT_F32) {
     if (layout == LAYOUT_CELL) { STREAMI_L(LAYOUT_CELL) }
+    if (layout == LAYOUT_HEX) {  // one steady block; the sampler keeps its own cell cache
+      if (batched || periodic || mode >= SM_UNSTEADY) return -1;
+      launch_variant<FMT, LAYOUT_HEX, false, SM_CACHED, false>(a, grid, st);
+      return 0;
+    }
   } else {
-    if (layout == LAYOUT_CELL) return -1;
+    if (layout == LAYOUT_CELL || layout == LAYOUT_HEX) return -1;
   }
   if (layout == LAYOUT_BRICK4) {
     STREAMI_L(LAYOUT_BRICK4)

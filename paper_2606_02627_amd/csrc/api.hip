@@ -43,6 +43,8 @@ int launch_work_order(const float4* pos, const int4* meta, const int4* meta2, co
                       unsigned* cursor, int* order, unsigned* n_work, hipStream_t st);
 int launch_fill_u64(unsigned long long* p, long long n, unsigned long long v, hipStream_t st);
 int launch_seed_bound(const SeedJobs& J, long long total, unsigned long long* out, hipStream_t st);
+std::string build_hex_blob(const float* V, long long nv, const float* val, const int* cells, long long nc, float tol,
+                           std::vector<float>& blob, unsigned& n_nodes);
 int launch_seed_shape(const double o[3], const double u[3], const double v[3], long long nu, long long nv, float* out,
                       hipStream_t st);
 int launch_gather_meta(const long long* idx, long long count, const int4* meta, const int4* meta2,
@@ -391,8 +393,8 @@ int collect_stats(streami_field_s* f, streami_stats* stats) {
 int advect_surrogate(streami_field_s* f, const streami_advect_params* p, streami_stats* stats) {
   const int J = 16;
   if (!p->mlp) return fail(STREAMI_E_STATE, "surrogate mode needs a network (params.mlp)");
-  if (f->blocks.size() != 1 || f->unsteady)
-    return fail(STREAMI_E_UNSUPPORTED, "surrogate mode supports one steady block");
+  if (f->blocks.size() != 1 || f->unsteady || f->layout == LAYOUT_HEX)
+    return fail(STREAMI_E_UNSUPPORTED, "surrogate mode supports one steady structured block");
   if (!f->strides_mult16) return fail(STREAMI_E_ARG, "surrogate mode needs record strides that are multiples of 16");
   if (p->step_budget % J != 0) return fail(STREAMI_E_ARG, "surrogate step_budget must be a multiple of 16");
   if (p->residual_kind != 0 && p->residual_kind != 1) return fail(STREAMI_E_ARG, "residual_kind must be 0 or 1");
@@ -460,6 +462,40 @@ int advect_surrogate(streami_field_s* f, const streami_advect_params* p, streami
 namespace streami {
 int block_count(streami_field f) { return (int)f->blocks.size(); }
 }  // namespace streami
+
+namespace {
+// Loopback forwarding needs every block on one rank grid, one block per cell:
+// then the rank -> block map goes to the device; otherwise forwarding is off.
+int setup_rank_map(streami_field_s* f) {
+  const int n_blocks = (int)f->blocks.size();
+  const int* g0 = f->blocks[0].desc.rank_grid;
+  long long nr = (long long)g0[0] * g0[1] * g0[2];
+  bool ok = nr <= (1LL << 24) && n_blocks <= FWD_MAX_BLOCKS;
+  for (int i = 1; i < n_blocks && ok; ++i)
+    for (int a = 0; a < 3; ++a) ok = ok && f->blocks[i].desc.rank_grid[a] == g0[a];
+  if (ok) {
+    f->rank_map.assign((size_t)nr, -1);
+    for (int i = 0; i < n_blocks && ok; ++i) {
+      const int* c = f->blocks[i].desc.rank_coord;
+      const long long id = c[0] + (long long)g0[0] * (c[1] + (long long)g0[1] * c[2]);
+      if (f->rank_map[id] >= 0) ok = false;
+      else f->rank_map[id] = i;
+    }
+  }
+  if (!ok) {
+    f->rank_map.clear();
+    return STREAMI_OK;
+  }
+  f->n_ranks = (int)nr;
+  int rc;
+  if ((rc = f->d_rankmap.reserve(sizeof(int) * nr, 0, f->stream))) return rc;
+  if (hipMemcpyAsync(f->d_rankmap.p, f->rank_map.data(), sizeof(int) * nr, hipMemcpyHostToDevice, f->stream) !=
+      hipSuccess)
+    return fail(STREAMI_E_DEVICE, "rank map copy failed");
+  return STREAMI_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -583,38 +619,114 @@ int streami_field_create(const streami_block_desc* blocks, int32_t n_blocks, int
     return cleanup(fail(STREAMI_E_DEVICE, "block table copy failed"));
   if ((rc = f->d_ctr.reserve(sizeof(unsigned long long) * N_COUNTERS, 0, f->stream))) return cleanup(rc);
   launch_fill_u64(f->ctr(), N_COUNTERS, 0, f->stream);
-  // loopback forwarding needs every block on one rank grid, one block per cell
-  {
-    const int* g0 = blocks[0].rank_grid;
-    long long nr = (long long)g0[0] * g0[1] * g0[2];
-    bool ok = nr <= (1LL << 24) && n_blocks <= FWD_MAX_BLOCKS;
-    for (int i = 1; i < n_blocks && ok; ++i)
-      for (int a = 0; a < 3; ++a) ok = ok && blocks[i].rank_grid[a] == g0[a];
-    if (ok) {
-      f->rank_map.assign((size_t)nr, -1);
-      for (int i = 0; i < n_blocks && ok; ++i) {
-        const int* c = blocks[i].rank_coord;
-        const long long id = c[0] + (long long)g0[0] * (c[1] + (long long)g0[1] * c[2]);
-        if (f->rank_map[id] >= 0) ok = false;
-        else f->rank_map[id] = i;
-      }
-    }
-    if (ok) {
-      f->n_ranks = (int)nr;
-      if ((rc = f->d_rankmap.reserve(sizeof(int) * nr, 0, f->stream))) return cleanup(rc);
-      if (hipMemcpyAsync(f->d_rankmap.p, f->rank_map.data(), sizeof(int) * nr, hipMemcpyHostToDevice, f->stream) !=
-          hipSuccess)
-        return cleanup(fail(STREAMI_E_DEVICE, "rank map copy failed"));
-    } else {
-      f->rank_map.clear();
-    }
-  }
+  if ((rc = setup_rank_map(f))) return cleanup(rc);
   if (hipEventCreate(&f->ev0) != hipSuccess || hipEventCreate(&f->ev1) != hipSuccess)
     return cleanup(fail(STREAMI_E_DEVICE, "event creation failed"));
   if (hipStreamSynchronize(f->stream) != hipSuccess) return cleanup(fail(STREAMI_E_DEVICE, "field upload failed"));
   staging.release();
   *out = f;
   return STREAMI_OK;
+}
+
+int streami_field_create_hex(const streami_hex_desc* d, void* hip_stream, streami_field* out) {
+  if (!out) return fail(STREAMI_E_ARG, "out is NULL");
+  if (!d) return fail(STREAMI_E_ARG, "desc is NULL");
+  if (d->n_vertices < 1 || d->n_vertices >= (1LL << 31)) return fail(STREAMI_E_ARG, "n_vertices must be in [1, 2^31)");
+  if (d->n_cells < 1 || d->n_cells >= (1LL << 28)) return fail(STREAMI_E_ARG, "n_cells must be in [1, 2^28)");
+  if (!d->vertices || !d->values || !d->cells) return fail(STREAMI_E_ARG, "vertices, values and cells must not be NULL");
+  for (int a = 0; a < 3; ++a) {
+    if (!(std::isfinite(d->bounds_lo[a]) && std::isfinite(d->bounds_hi[a]) && d->bounds_lo[a] < d->bounds_hi[a]))
+      return fail(STREAMI_E_ARG, "bounds must be finite with lo < hi");
+    if (d->rank_grid[a] < 1 || d->rank_coord[a] < 0 || d->rank_coord[a] >= d->rank_grid[a])
+      return fail(STREAMI_E_ARG, "rank_grid must be >= 1 and rank_coord inside it");
+  }
+  // the builder reads host copies of the mesh
+  const long long nv = d->n_vertices, nc = d->n_cells;
+  std::vector<float> hv, hval;
+  std::vector<int> hc;
+  const float *V = d->vertices, *val = d->values;
+  const int* C = d->cells;
+  try {
+    if (d->inputs_on_device) {
+      hv.resize(3 * (size_t)nv);
+      hval.resize(3 * (size_t)nv);
+      hc.resize(8 * (size_t)nc);
+      if (hipMemcpy(hv.data(), d->vertices, hv.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(hval.data(), d->values, hval.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(hc.data(), d->cells, hc.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(STREAMI_E_DEVICE, "copy of the mesh to the host failed");
+      V = hv.data();
+      val = hval.data();
+      C = hc.data();
+    }
+    std::vector<float> blob;
+    unsigned n_nodes = 0;
+    const std::string err = build_hex_blob(V, nv, val, C, nc, 1e-4f, blob, n_nodes);
+    if (!err.empty()) return fail(STREAMI_E_ARG, "%s", err.c_str());
+    streami_field_s* f = new (std::nothrow) streami_field_s();
+    if (!f) return fail(STREAMI_E_NOMEM, "host allocation failed");
+    auto cleanup = [&](int rc) {
+      streami_field_destroy(f);
+      return rc;
+    };
+    f->fmt = STREAMI_F32;
+    f->layout = LAYOUT_HEX;
+    f->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&f->device) != hipSuccess) return cleanup(fail(STREAMI_E_DEVICE, "no HIP device"));
+    (void)hipDeviceGetAttribute(&f->n_cu, hipDeviceAttributeMultiprocessorCount, f->device);
+    // one block: its owned bounds and rank grid; the storage-coordinate fields map the
+    // bounds onto a 64^3 grid, used only to order the work spatially
+    f->blocks.resize(1);
+    HostBlock& hb = f->blocks[0];
+    std::memset(&hb.desc, 0, sizeof hb.desc);
+    BlockDev& B = hb.dev;
+    std::memset(&B, 0, sizeof B);
+    for (int a = 0; a < 3; ++a) {
+      const double lo = d->bounds_lo[a], hi = d->bounds_hi[a];
+      hb.desc.dims[a] = 64;
+      hb.desc.origin[a] = lo;
+      hb.desc.spacing[a] = (hi - lo) / 64.0;
+      hb.desc.bounds_lo[a] = lo;
+      hb.desc.bounds_hi[a] = hi;
+      hb.desc.rank_grid[a] = d->rank_grid[a];
+      hb.desc.rank_coord[a] = d->rank_coord[a];
+      B.scale[a] = (float)(64.0 / (hi - lo));
+      B.offs[a] = (float)(-lo * 64.0 / (hi - lo));
+      B.nst[a] = 64;
+      B.fn[a] = 64.0f;
+      B.inv_fn[a] = 1.0f / 64.0f;
+      B.lo[a] = (float)lo;
+      B.hi[a] = (float)hi;
+      B.inv_ext[a] = (float)(1.0 / (hi - lo));
+      B.rgrid[a] = d->rank_grid[a];
+      B.rcoord[a] = d->rank_coord[a];
+      B.nb[a] = 16;
+      B.vs[a] = NAN;  // no interior shortcut
+    }
+    hb.desc.boundary = STREAMI_BOUNDARY_BLOCK;
+    hb.desc.n_slices = 1;
+    hb.desc.slice_dt = 1.0;
+    B.n_slices = 1;
+    hb.nx = hb.ny = hb.nz = 64;
+    int rc;
+    if ((rc = f->d_nodes.reserve(blob.size() * 4, 0, f->stream))) return cleanup(rc);
+    if (hipMemcpyAsync(f->d_nodes.p, blob.data(), blob.size() * 4, hipMemcpyHostToDevice, f->stream) != hipSuccess)
+      return cleanup(fail(STREAMI_E_DEVICE, "copy of the field to the device failed"));
+    if ((rc = f->d_blocks.reserve(sizeof(BlockDev), 0, f->stream))) return cleanup(rc);
+    if (hipMemcpyAsync(f->d_blocks.p, &B, sizeof(BlockDev), hipMemcpyHostToDevice, f->stream) != hipSuccess)
+      return cleanup(fail(STREAMI_E_DEVICE, "block table copy failed"));
+    if ((rc = f->d_ctr.reserve(sizeof(unsigned long long) * N_COUNTERS, 0, f->stream))) return cleanup(rc);
+    launch_fill_u64(f->ctr(), N_COUNTERS, 0, f->stream);
+    if ((rc = setup_rank_map(f))) return cleanup(rc);
+    if (hipEventCreate(&f->ev0) != hipSuccess || hipEventCreate(&f->ev1) != hipSuccess)
+      return cleanup(fail(STREAMI_E_DEVICE, "event creation failed"));
+    // the host copies are read by the asynchronous upload: wait before they go
+    if (hipStreamSynchronize(f->stream) != hipSuccess) return cleanup(fail(STREAMI_E_DEVICE, "field upload failed"));
+    *out = f;
+    return STREAMI_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(STREAMI_E_NOMEM, "host allocation for the mesh failed");
+  }
 }
 
 int streami_field_destroy(streami_field f) {

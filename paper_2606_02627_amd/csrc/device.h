@@ -11,7 +11,8 @@ enum Fmt { FMT_F32 = 0, FMT_F16 = 1, FMT_BF16 = 2 };
 // coefficients, so a cell-cache miss is six aligned 16-byte loads and no
 // arithmetic (8x the node bytes; `base` and `slice_nodes` then count 12-byte
 // units, 8 per cell).
-enum Layout { LAYOUT_LINEAR = 1, LAYOUT_BRICK4 = 2, LAYOUT_CELL = 3 };
+// HEX (FP32 only): an unstructured hexahedral field (BVH + cell records, hex.h).
+enum Layout { LAYOUT_LINEAR = 1, LAYOUT_BRICK4 = 2, LAYOUT_CELL = 3, LAYOUT_HEX = 4 };
 enum Code { ACTIVE = 0, MAX_STEPS = 1, EXIT = 2, STAGNANT = 3, HALO_MISS = 4, NONFINITE = 5 };
 
 // One block as the kernels see it.  Storage coordinate along an axis:

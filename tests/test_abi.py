@@ -117,7 +117,7 @@ def test_probe_rejects_invalid_arguments_before_device_work():
 
 
 STRUCTS = [("streami_block_desc", "BlockDesc"), ("streami_field_opts", "FieldOpts"),
-           ("streami_seed_opts", "SeedOpts"), ("streami_seed_batch", "SeedBatch"), ("streami_shape", "Shape"),
+           ("streami_seed_opts", "SeedOpts"), ("streami_seed_batch", "SeedBatch"), ("streami_shape", "Shape"), ("streami_hex_desc", "HexDesc"),
            ("streami_advect_params", "AdvectParams"),
            ("streami_stats", "Stats")]
 
@@ -211,3 +211,21 @@ def test_missing_library_fails_loudly():
             "    raise SystemExit('loaded')\n")
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300, cwd=ROOT)
     assert r.returncode == 0 and "ImportError" in r.stdout and "build" in r.stdout, (r.stdout, r.stderr[-500:])
+
+
+def test_hex_field_create_rejects_invalid_meshes():
+    """Descriptor and mesh errors are found on the host, before any device work."""
+    import fieldgen as fg
+    import paper_2606_02627_amd as S
+    good = fg.distorted_hex_mesh(18, (2, 2, 2), jitter=0.1)
+    cases = [(dict(cells=np.where(good["cells"] == 5, 99, good["cells"]).astype(np.int32)), "names vertex"),
+             (dict(lo=(1.0, 0.0, 0.0), hi=(0.5, 2.0, 2.0)), "lo < hi"),
+             (dict(rank_coord=(0, 0, 3)), "rank_coord"),
+             (dict(cells=good["cells"][:0]), "n_cells")]
+    v = good["vertices"].copy()
+    v[3, 1] = np.nan
+    cases.append((dict(vertices=v), "not finite"))
+    for change, msg in cases:
+        with pytest.raises(S.StreamiError) as e:
+            S.streami_field_create_hex(dict(good, **change))
+        assert e.value.code == S.E_ARG and msg in str(e.value), (change, e.value)

@@ -1,0 +1,114 @@
+"""GPU tests of the hexahedral (unstructured) field: streami_field_create_hex.
+
+Voxel hexahedra (every cell of a structured grid) sample what the structured grid samples
+(pinned on the CPU for the two oracles), so their lines are checked against the structured
+FP64 oracle, which runs fast; general (jittered) hexahedra against the hexahedral oracle.
+Per-step rule at every vertex; step counts and codes from a late restart; exits, halo misses
+and destinations from the outbox."""
+import sys
+
+import numpy as np
+import pytest
+
+import fieldgen as fg
+import oracle
+from oracle import hex as ohex
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+
+def note(*a):
+    print("[gpu-case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2606_02627_amd as S
+    S._load()
+    return S
+
+
+def hex_oracle(mesh):
+    return ohex.HexField(mesh["vertices"], mesh["values"], mesh["cells"], mesh["lo"], mesh["hi"],
+                         mesh["rank_grid"], mesh["rank_coord"])
+
+
+def test_voxel_hexahedra_follow_the_structured_field(S):
+    note("hex: voxel hexahedra of a 24^3 block")
+    blk = fg.turbulence_block(15, edge=24, rank_grid=(3, 3, 3), rank_coord=(1, 1, 1))
+    mesh = fg.hex_mesh_from_block(blk)
+    F = oracle.Field.from_block(blk)
+    seeds = fg.uniform_seeds(15, 3000, (0, 0, 0), (24, 24, 24))
+    f = S.Field.hex(mesh)
+    assert S.streami_field_info(f.h)[0] == S.LAYOUT_HEX
+    f.seed(0, seeds, default_max_steps=300)
+    st = f.advect(0.5)
+    L = f.lines(0)
+    ratio, npairs = parity.local_check(F, L, 0.5, 24.0)
+    assert ratio <= 1.0 and npairs > 3000 * 20, (ratio, npairs)
+    frac, bad = parity.restart_check(F, L, 0.5, blk.lo, blk.hi, 300)
+    ref = F.trace(seeds, 0.5, 300)
+    dev, _ = parity.global_compare(L, ref, len(seeds))
+    sens = parity.boundary_sensitive(ref, L, dev, blk.lo, blk.hi, field=F)
+    note(f"hex voxels: {npairs} steps, local ratio {ratio:.3f}, restart compares {frac:.4f}, whole lines "
+         f"{(~sens).mean():.3f}, {st.gathers / max(1, st.steps):.3f} BVH walks per step")
+    assert frac >= 0.97 and len(bad) == 0, (frac, bad[:10])
+    np.testing.assert_array_equal(L["codes"][~sens], ref["code"][~sens])
+    # exits go to the outbox with the structured field's destinations
+    ob = f.outbox(cap=len(seeds))
+    assert len(ob) == st.terminated[S.EXIT] + st.terminated[S.HALO_MISS] and st.terminated[S.HALO_MISS] == 0
+    np.testing.assert_array_equal(ob["dest"], F.dest(ob["pos"].astype(np.float64)))
+    f.close()
+
+
+def test_general_hexahedra_against_the_hex_oracle(S):
+    """Jittered (non-affine) cells; owned bounds one cell inside the mesh, so particles exit
+    through the owned faces and halo misses happen where a step reaches the mesh's edge."""
+    note("hex: jittered mesh")
+    mesh = fg.distorted_hex_mesh(16, (14, 12, 10), jitter=0.25)
+    mesh.update(lo=(1.0, 1.0, 1.0), hi=(13.0, 11.0, 9.0), rank_grid=(3, 3, 3), rank_coord=(1, 1, 1))
+    H = hex_oracle(mesh)
+    seeds = fg.uniform_seeds(16, 400, (1, 1, 1), (13, 11, 9), sub=2)
+    f = S.Field.hex(mesh)
+    f.seed(0, seeds, default_max_steps=300)
+    st = f.advect(0.25)
+    L = f.lines(0)
+    ratio, npairs = parity.local_check(H, L, 0.25, 14.0)
+    assert ratio <= 1.0 and npairs > 400 * 20, (ratio, npairs)
+    frac, bad = parity.restart_check(H, L, 0.25, mesh["lo"], mesh["hi"], 300)
+    note(f"hex jittered: {npairs} steps, local ratio {ratio:.3f}, restart compares {frac:.4f}; codes "
+         f"{np.bincount(L['codes'], minlength=6).tolist()}")
+    assert frac >= 0.95 and len(bad) == 0, (frac, bad[:10])
+    assert st.terminated[S.EXIT] > 20
+    ob = f.outbox(cap=len(seeds))
+    assert len(ob) == st.terminated[S.EXIT] + st.terminated[S.HALO_MISS]
+    ex = ob["code"] == S.EXIT
+    np.testing.assert_array_equal(ob["dest"][ex], H.dest(ob["pos"][ex].astype(np.float64)))
+    f.close()
+    # a mesh without halo: steps that reach its edge miss, at the old position (outbox, steps unchanged)
+    m2 = dict(mesh, lo=(0.0, 0.0, 0.0), hi=(14.0, 12.0, 10.0))
+    H2 = hex_oracle(m2)
+    s2 = fg.uniform_seeds(16, 300, (0, 0, 0), (14, 12, 10), sub=3)
+    g = S.Field.hex(m2)
+    g.seed(0, s2, default_max_steps=120)
+    st2 = g.advect(0.6)
+    L2 = g.lines(0)
+    frac, bad = parity.restart_check(H2, L2, 0.6, m2["lo"], m2["hi"], 120)
+    assert st2.terminated[S.HALO_MISS] > 10 and frac >= 0.9 and len(bad) == 0, (st2.terminated, frac, bad)
+    g.close()
+
+
+def test_hex_refusals(S):
+    note("hex: refusals")
+    mesh = fg.distorted_hex_mesh(17, (3, 3, 3), jitter=0.1)
+    f = S.Field.hex(mesh)
+    f.seed(0, fg.uniform_seeds(17, 10, (0, 0, 0), (3, 3, 3)), default_max_steps=5)
+    with pytest.raises(S.StreamiError) as e:
+        f.advect(0.01, mode=S.MODE_SURROGATE, residual_tol_cells=1.0)
+    assert e.value.code in (S.E_UNSUPPORTED, S.E_STATE)
+    st = f.advect(0.3)
+    assert st.active == 0
+    f.close()
