@@ -191,7 +191,7 @@ typedef struct {
  * Append n particles to block `block`.  xyz: n*3 FP32 positions; ids: n
  * unique ids or NULL (then ids continue a per-handle counter from 0);
  * max_steps: n per-particle limits (>= 0) or NULL.  Each particle reserves
- * room for max_steps/record_stride + 2 vertex records (20 bytes each) in the
+ * room for max_steps/record_stride + 2 vertex records (16 bytes each) in the
  * handle's vertex log.  The seed position is vertex 0; a seed outside the
  * block's owned bounds (BLOCK boundary) terminates at once with code EXIT and
  * 0 steps and goes to the outbox.  Particles of a block keep their seed order

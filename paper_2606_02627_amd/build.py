@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libstreami.so")
 SOURCES = ["advect_f32.hip", "advect_f16.hip", "advect_bf16.hip", "layout.hip", "api.hip", "mlp.hip",
-           "probe.hip", "forward.hip", "obj.hip", "hex.hip"]
+           "probe.hip", "forward.hip", "obj.hip", "hex.hip", "fetch.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

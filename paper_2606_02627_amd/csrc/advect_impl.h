@@ -649,9 +649,7 @@ __device__ __forceinline__ void advect_body(const AdvectArgs& A) {
         const unsigned k = lanes_below(vm);
         const unsigned long long cu = uniform_u64(cpos);
         float4* vb = A.log.v + cu;
-        unsigned* jb = A.log.j + cu;
         vb[k] = make_float4(P.x, P.y, P.z, __uint_as_float((unsigned)p));
-        jb[k] = (unsigned)nv;
       }
       if (rec) {
         ++nv;
@@ -839,7 +837,6 @@ __global__ void __launch_bounds__(256) k_sur_apply(SurrogateArgs S) {
         const unsigned long long r = b + lanes_below(vm);
         if (r < (unsigned long long)A.log.cap) {
           A.log.v[r] = make_float4(P.x, P.y, P.z, __uint_as_float((unsigned)q));
-          A.log.j[r] = (unsigned)mt.w;
         }
         ++mt.w;
       }

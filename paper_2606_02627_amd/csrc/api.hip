@@ -33,8 +33,9 @@ int launch_ingest(const void* src, void* pool, const BlockDev& B, int fmt, int l
 int launch_seed(const SeedJobs& J, unsigned n_wg, const BlockDev* blocks, float4* pos, int4* meta, int4* meta2,
                 unsigned long long* pid, const VertexLog& log, OutRec* outbox, int* outbox_src,
                 unsigned long long* outbox_count, hipStream_t st);
-int launch_scatter_lines(const VertexLog& log, long long n_rec, long long n_particles, const int* row_of,
-                         const long long* offsets, float* out, hipStream_t st);
+int assemble_lines(const VertexLog& log, long long n_rec, long long n_particles, const int* row_of, long long rows,
+                   long long n_vertices, float* out, hipStream_t st, void* (*alloc)(size_t, void*),
+                   void (*release)(void*, void*), void* ctx);
 int launch_mark_rows(const long long* idx, long long count, int* row_of, hipStream_t st);
 int launch_fill_u32(unsigned* p, long long n, unsigned v, hipStream_t st);
 int launch_max_abs(const void* src, int fmt, long long n, unsigned* out, hipStream_t st);
@@ -180,7 +181,7 @@ struct streami_field_s {
   DevBuf d_rankmap, d_fwd, d_outbox2, d_obsrc2;
   // vertex log (see VertexLog): capacity in records, and the sum over all
   // particles of the vertices each may still record at most
-  DevBuf d_logv, d_logj;
+  DevBuf d_logv;
   long long log_cap = 0;
   long long vert_bound = 0;
   // host upper bound of the log records still needed (reserved + to come, with
@@ -208,7 +209,6 @@ struct streami_field_s {
   VertexLog log() {
     VertexLog l;
     l.v = (float4*)d_logv.p;
-    l.j = (unsigned*)d_logj.p;
     l.count = persist() + PER_LOG;
     l.real = persist() + PER_LOG_REAL;
     l.cap = log_cap;
@@ -355,7 +355,6 @@ int ensure_log(streami_field_s* f, long long slack) {
   const long long cap = std::max(need, f->log_cap + f->log_cap / 4);
   int rc;
   if ((rc = f->d_logv.reserve(cap * 16, count * 16, f->stream))) return rc;
-  if ((rc = f->d_logj.reserve(cap * 4, count * 4, f->stream))) return rc;
   f->log_cap = cap;
   return STREAMI_OK;
 }
@@ -735,7 +734,7 @@ int streami_field_destroy(streami_field f) {
   drop_graph(f);
   for (DevBuf* b : {&f->d_blocks, &f->d_nodes, &f->d_pos, &f->d_meta, &f->d_meta2, &f->d_ids, &f->d_outbox,
                     &f->d_obsrc, &f->d_rankmap, &f->d_fwd, &f->d_outbox2, &f->d_obsrc2,
-                    &f->d_logv, &f->d_logj, &f->d_ctr, &f->d_qctr, &f->d_key,
+                    &f->d_logv, &f->d_ctr, &f->d_qctr, &f->d_key,
                     &f->d_order, &f->d_hist, &f->d_cursor, &f->d_nwork, &f->d_dhat, &f->d_dhat2, &f->d_xh,
                     &f->d_seedred})
     b->release();
@@ -1170,7 +1169,7 @@ int streami_fetch_lines(streami_field f, int32_t block, int64_t first, int64_t c
     skip = 0;
   }
   int rc;
-  DevBuf d_idx, d_nv, d_steps, d_codes, d_ids, d_off;
+  DevBuf d_idx, d_nv, d_steps, d_codes, d_ids;
   const long long c = std::max<long long>(count, 1);
   if ((rc = d_idx.reserve(c * 8, 0, f->stream)) || (rc = d_nv.reserve(c * 8, 0, f->stream)) ||
       (rc = d_steps.reserve(c * 4, 0, f->stream)) || (rc = d_codes.reserve(c * 4, 0, f->stream)) ||
@@ -1215,9 +1214,7 @@ int streami_fetch_lines(streami_field f, int32_t block, int64_t first, int64_t c
     HIP_TRY(hipMemcpyAsync(cnt, f->persist(), sizeof cnt, hipMemcpyDeviceToHost, f->stream));
     HIP_TRY(hipStreamSynchronize(f->stream));
     const long long n_rec = (long long)std::min<unsigned long long>(cnt[PER_LOG], (unsigned long long)f->log_cap);
-    if ((rc = d_off.reserve((count + 1) * 8, 0, f->stream))) return rc;
     if ((rc = d_row.reserve(std::max<long long>(f->n_particles, 1) * 4, 0, f->stream))) return rc;
-    HIP_TRY(hipMemcpyAsync(d_off.p, off.data(), (count + 1) * 8, hipMemcpyHostToDevice, f->stream));
     launch_fill_u32((unsigned*)d_row.p, f->n_particles, 0xffffffffu, f->stream);
     launch_mark_rows((const long long*)d_idx.p, count, (int*)d_row.p, f->stream);
     const bool dev_out = is_device_ptr(xyz);
@@ -1227,9 +1224,21 @@ int streami_fetch_lines(streami_field f, int32_t block, int64_t first, int64_t c
       if ((rc = tmp.reserve(off[count] * 12, 0, f->stream))) return rc;
       dst = (float*)tmp.p;
     }
-    launch_scatter_lines(f->log(), n_rec, f->n_particles, (const int*)d_row.p, (const long long*)d_off.p, dst,
-                         f->stream);
-    HIP_TRY(hipGetLastError());
+    // the requested particles' records, stably sorted by row, are the CSR lines
+    auto alloc = [](size_t bytes, void*) -> void* {
+      void* q = nullptr;
+      if (hipMalloc(&q, std::max<size_t>(bytes, 16)) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+      }
+      return q;
+    };
+    auto release = [](void* q, void*) { (void)hipFree(q); };
+    const int arc = assemble_lines(f->log(), n_rec, f->n_particles, (const int*)d_row.p, count, off[count], dst,
+                                   f->stream, alloc, release, nullptr);
+    if (arc == 2) return fail(STREAMI_E_NOMEM, "scratch for assembling %lld vertices", (long long)off[count]);
+    if (arc == 4) return fail(STREAMI_E_DEVICE, "vertex log inconsistent with the particles' vertex counts");
+    if (arc) return fail(STREAMI_E_DEVICE, "line assembly failed");
     if (!dev_out) HIP_TRY(hipMemcpyAsync(xyz, tmp.p, off[count] * 12, hipMemcpyDeviceToHost, f->stream));
     HIP_TRY(hipStreamSynchronize(f->stream));
   }

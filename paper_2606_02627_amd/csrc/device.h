@@ -71,9 +71,10 @@ enum Persist { PER_OUTBOX = 0, PER_LOG = 1, PER_LOG_REAL = 2, PER_N = 4 };
 // Vertex log: a wave appends the vertices its lanes produce in one step as a
 // contiguous run (ballot + mbcnt) inside a chunk it reserved with one atomic,
 // so every store is part of a full, coalesced line.  A record is one 16-byte
-// (x, y, z, particle index) plus the vertex's index within that particle's
-// line in a parallel array: two stores per vertex.  Fetching scatters records
-// to their CSR rows without sorting.
+// store (x, y, z, particle index).  A particle's records enter the log in step
+// order (a particle stays in its lane for a launch, a wave's chunks come from a
+// monotonic counter, and later launches append after earlier ones), so fetching
+// sorts the requested particles' records stably by row to get their lines.
 // Records per wave reservation.  Every wave reserves from one counter, so the
 // chunk is large: at 1024 records the contended atomic cost a third of a pass.
 constexpr int LOG_CHUNK = 8192;
@@ -81,7 +82,6 @@ constexpr unsigned LOG_UNUSED = 0xffffffffu;  // particle index of an unused rec
 
 struct VertexLog {
   float4* v;                       // x, y, z, particle index (as bits)
-  unsigned* j;                     // vertex index within its line
   unsigned long long* count;       // records reserved (incl. unused chunk tails)
   unsigned long long* real;        // records written
   long long cap;                   // records the buffers hold

@@ -104,7 +104,6 @@ __global__ void __launch_bounds__(FWD_THREADS) k_fwd_write(FwdArgs a, FwdOut o) 
                                                                      __builtin_amdgcn_mbcnt_lo((unsigned)fm, 0u));
         if (lr < (unsigned long long)o.log.cap) {
           o.log.v[lr] = make_float4(rec.pos[0], rec.pos[1], rec.pos[2], __uint_as_float((unsigned)q));
-          o.log.j[lr] = 0u;
         }
       }
     }

@@ -201,7 +201,6 @@ __global__ void __launch_bounds__(SEED_THREADS) k_seed(SeedJobs J, const BlockDe
     r += __builtin_amdgcn_mbcnt_hi((unsigned)(vm >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)vm, 0u));
     if (r < (unsigned long long)log.cap) {
       log.v[r] = make_float4(x.x, x.y, x.z, __uint_as_float((unsigned)q));
-      log.j[r] = 0u;
     }
   }
   const unsigned long long em = __ballot(emit);
@@ -237,35 +236,6 @@ int launch_seed(const SeedJobs& J, unsigned n_wg, const BlockDev* blocks, float4
   if (J.n_jobs <= 0 || n_wg == 0) return 0;
   hipLaunchKernelGGL(k_seed, dim3(n_wg), dim3(SEED_THREADS), 0, st, J, blocks, pos, meta, meta2, pid, log, outbox,
                      outbox_src, outbox_count);
-  return 0;
-}
-
-// Scatter log records to CSR rows: record (p, j) of a requested particle
-// (row_of[p] = its row) lands at out[offsets[row] + j].
-__global__ void k_scatter_lines(VertexLog log, long long n_rec, long long n_particles, const int* row_of,
-                                const long long* offsets, float* out) {
-  for (long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x; r < n_rec;
-       r += (long long)gridDim.x * blockDim.x) {
-    const float4 v = log.v[r];
-    const unsigned p = __float_as_uint(v.w);
-    if ((long long)p >= n_particles) continue;  // unused tail of a chunk
-    const int row = row_of[p];
-    if (row < 0) continue;
-    const long long o = offsets[row] + log.j[r];
-    if (o >= offsets[row + 1]) continue;
-    out[o * 3 + 0] = v.x;
-    out[o * 3 + 1] = v.y;
-    out[o * 3 + 2] = v.z;
-  }
-}
-
-int launch_scatter_lines(const VertexLog& log, long long n_rec, long long n_particles, const int* row_of,
-                         const long long* offsets, float* out, hipStream_t st) {
-  if (n_rec <= 0) return 0;
-  long long grid = (n_rec + 255) / 256;
-  if (grid > 65536) grid = 65536;
-  hipLaunchKernelGGL(k_scatter_lines, dim3((unsigned)grid), dim3(256), 0, st, log, n_rec, n_particles, row_of,
-                     offsets, out);
   return 0;
 }
 

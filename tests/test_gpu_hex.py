@@ -112,3 +112,30 @@ def test_hex_refusals(S):
     st = f.advect(0.3)
     assert st.active == 0
     f.close()
+
+
+def test_hex256_full_size_sampled(S):
+    """The hexahedral workload as benchmarked: the 256^3 block's 16,974,593 cells, the 1M seeds
+    and 2000-step limits of the structured workload.  A contiguous 4096-particle sample against
+    the structured FP64 oracle (equal to the hexahedral oracle on voxel cells): per-step rule at
+    every vertex and late-restart codes and steps; invariants over all particles."""
+    note("hex 256^3 full size: building")
+    blk = fg.turbulence_block(2, edge=256)
+    seeds = fg.uniform_seeds(2, 1 << 20, (0, 0, 0), (256, 256, 256))
+    f = S.Field.hex(fg.hex_mesh_from_block(blk))
+    f.seed(0, seeds, default_max_steps=2000)
+    note("hex 256^3 full size: advecting")
+    st = f.advect(0.5)
+    first, count = 123456, 4096
+    L = f.lines(0, first, count)
+    F = oracle.Field.from_block(blk)
+    ratio, npairs = parity.local_check(F, L, 0.5, 256.0)
+    frac, bad = parity.restart_check(F, L, 0.5, blk.lo, blk.hi, 2000)
+    note(f"hex 256^3: {st.steps} steps, {st.gathers / st.steps:.4f} BVH walks per step; sample: {npairs} steps, "
+         f"local ratio {ratio:.3f}, restart compares {frac:.4f}")
+    assert ratio <= 1.0 and npairs > count * 100, (ratio, npairs)
+    assert frac >= 0.97 and len(bad) == 0, (frac, bad[:10])
+    assert st.active == 0 and sum(st.terminated) == 1 << 20 and st.terminated[S.HALO_MISS] == 0
+    ob = f.outbox(cap=1 << 21)
+    assert len(ob) == st.terminated[S.EXIT] and len(np.unique(ob["id"])) == len(ob)
+    f.close()
