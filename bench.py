@@ -511,6 +511,8 @@ def main():
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--refill", type=int, default=0)
     ap.add_argument("--no-cell-cache", action="store_true")
+    ap.add_argument("--lds-cell-cache", action="store_true",
+                    help="keep each lane's cached cell record in LDS instead of registers (cell records)")
     ap.add_argument("--graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
@@ -558,7 +560,8 @@ def main():
     torch.cuda.synchronize()
 
     kw = dict(waves_per_cu=args.waves_per_cu, refill_threshold=args.refill,
-              no_cell_cache=int(args.no_cell_cache), use_graph=int(args.graph))
+              no_cell_cache=int(args.no_cell_cache), use_graph=int(args.graph),
+              lds_cell_cache=int(args.lds_cell_cache))
 
     def one_step(stats=False):
         f.clear()
@@ -643,7 +646,8 @@ def main():
                    "particle_steps_per_step": steps_per_pass, "vertices_per_step": verts_per_pass,
                    "layout": LAYOUT_NAMES[layout] + (" (auto)" if args.layout == 0 else ""),
                    "field_bytes": field_bytes, "waves_per_cu": args.waves_per_cu,
-                   "cell_cache": not args.no_cell_cache, "graph": args.graph},
+                   "cell_cache": ("off" if args.no_cell_cache else "lds" if args.lds_cell_cache else "registers"),
+                   "graph": args.graph},
         # compulsory bytes of the cached kernel per launch (cell refills x stored refill bytes,
         # 12 B per recorded vertex, particle state and outbox records) over k_advect's mean
         # launch time, against the published HBM peak; `traffic` is the counted HBM bytes

@@ -290,6 +290,9 @@ typedef struct {
   float t_end;              /* end of the window (with use_t_end); must not be NaN */
   int32_t checked_samples;  /* 1: test every sample's domain, also for steps that start deep inside a
                                single block (A/B measurement; results are bit-identical either way) */
+  int32_t lds_cell_cache;   /* 1: keep each lane's cached cell record in LDS (24 KB per workgroup)
+                               instead of registers, for steady FP32 cell records in a one-block
+                               handle (ignored elsewhere; results are bit-identical either way) */
 } streami_advect_params;
 
 typedef struct {

@@ -81,7 +81,7 @@ class AdvectParams(ctypes.Structure):
                 ("refill_threshold", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("no_cell_cache", ctypes.c_int32), ("work_order", ctypes.c_int32),
                 ("use_t_end", ctypes.c_int32), ("t_end", ctypes.c_float),
-                ("checked_samples", ctypes.c_int32)]
+                ("checked_samples", ctypes.c_int32), ("lds_cell_cache", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

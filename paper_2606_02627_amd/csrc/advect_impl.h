@@ -36,7 +36,9 @@
 
 namespace streami {
 
-enum SampleMode { SM_CACHED = 0, SM_UNCACHED = 1, SM_UNSTEADY = 2, SM_UNSTEADY_UNCACHED = 3 };
+// SM_LDS: SM_CACHED with each lane's cell record kept in LDS instead of
+// registers (steady cell records of one block; an A/B choice, bit-identical).
+enum SampleMode { SM_CACHED = 0, SM_UNCACHED = 1, SM_UNSTEADY = 2, SM_UNSTEADY_UNCACHED = 3, SM_LDS = 4 };
 
 __device__ __forceinline__ float lerpf(float a, float b, float t) { return fmaf(t, b - a, a); }
 
@@ -245,6 +247,35 @@ struct Sampler {
         ++gathers;
       }
       v = monomial(c, fx, fy, fz);
+    } else if (MODE == SM_LDS) {
+      // slot threadIdx.x of a 256-lane workgroup: six 16-byte words, word-major,
+      // so a wave's lanes touch consecutive words (no bank conflicts)
+      __shared__ float4 g_cell_lds[6][256];
+      const unsigned tid = threadIdx.x;
+      if (ok && o000 != key) {
+        const float4* q = reinterpret_cast<const float4*>(base + o000);
+        const float4 w0 = q[0], w1 = q[1], w2 = q[2], w3 = q[3], w4 = q[4], w5 = q[5];
+        g_cell_lds[0][tid] = w0;
+        g_cell_lds[1][tid] = w1;
+        g_cell_lds[2][tid] = w2;
+        g_cell_lds[3][tid] = w3;
+        g_cell_lds[4][tid] = w4;
+        g_cell_lds[5][tid] = w5;
+        key = o000;
+        ++gathers;
+      }
+      const float4 a = g_cell_lds[0][tid], b = g_cell_lds[1][tid], cc = g_cell_lds[2][tid];
+      const float4 e = g_cell_lds[3][tid], g = g_cell_lds[4][tid], k = g_cell_lds[5][tid];
+      float3 d[8];
+      d[0] = make_float3(a.x, a.y, a.z);
+      d[1] = make_float3(a.w, b.x, b.y);
+      d[2] = make_float3(b.z, b.w, cc.x);
+      d[3] = make_float3(cc.y, cc.z, cc.w);
+      d[4] = make_float3(e.x, e.y, e.z);
+      d[5] = make_float3(e.w, g.x, g.y);
+      d[6] = make_float3(g.z, g.w, k.x);
+      d[7] = make_float3(k.y, k.z, k.w);
+      v = monomial(d, fx, fy, fz);
     } else if (MODE == SM_UNCACHED) {
       if (ok) {
         gather(B, base, o000, x0, x1, y0, y1, z0, z1, c);
@@ -896,8 +927,10 @@ int launch_surrogate_fmt(const SurrogateArgs& s, int layout, bool periodic, bool
 #undef STREAMI_S
 }
 
+// With the cell cache in LDS (24 KB per workgroup) at most 6 workgroups fit a CU:
+// those kernels are held to 6 waves per SIMD.
 template <int FMT, int LAYOUT, bool PERIODIC, int MODE, bool BATCHED>
-__global__ void __launch_bounds__(256) k_advect(AdvectArgs A) {
+__global__ void __launch_bounds__(256, MODE == SM_LDS ? 6 : 1) k_advect(AdvectArgs A) {
   advect_body<FMT, LAYOUT, PERIODIC, MODE, BATCHED>(A);
 }
 
@@ -932,6 +965,12 @@ int launch_advect_fmt(const AdvectArgs& a, int layout, bool periodic, int mode, 
   return 0;
   if (FMT == FMT_F32 && mode == SM_UNSTEADY_UNCACHED) mode = SM_UNSTEADY;  // the same sampler
   if constexpr (FMT == FMT_F32) {
+    if (layout == LAYOUT_CELL && mode == SM_LDS) {
+      if (batched) return -1;
+      if (periodic) launch_variant<FMT, LAYOUT_CELL, true, SM_LDS, false>(a, grid, st);
+      else launch_variant<FMT, LAYOUT_CELL, false, SM_LDS, false>(a, grid, st);
+      return 0;
+    }
     if (layout == LAYOUT_CELL) { STREAMI_L(LAYOUT_CELL) }
     if (layout == LAYOUT_HEX) {  // one steady block; the sampler keeps its own cell cache
       if (batched || periodic || mode >= SM_UNSTEADY) return -1;

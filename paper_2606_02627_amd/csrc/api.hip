@@ -993,6 +993,7 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
   if (p->use_t_end != 0 && p->use_t_end != 1) return fail(STREAMI_E_ARG, "use_t_end must be 0 or 1");
   if (p->checked_samples != 0 && p->checked_samples != 1)
     return fail(STREAMI_E_ARG, "checked_samples must be 0 or 1");
+  if (p->lds_cell_cache != 0 && p->lds_cell_cache != 1) return fail(STREAMI_E_ARG, "lds_cell_cache must be 0 or 1");
   if (p->use_t_end && std::isnan(p->t_end)) return fail(STREAMI_E_ARG, "t_end is NaN");
   if (p->mode == STREAMI_MODE_SURROGATE) {
     if (p->use_t_end) return fail(STREAMI_E_UNSUPPORTED, "surrogate mode takes no time window");
@@ -1053,7 +1054,8 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
   a.qctr = (unsigned long long*)f->d_qctr.p;
   a.n_queues = spatial ? MAX_QUEUES : 1;
   const bool batched = f->blocks.size() > 1;
-  const int mode = f->unsteady ? (p->no_cell_cache ? 3 : 2) : (p->no_cell_cache ? 1 : 0);
+  int mode = f->unsteady ? (p->no_cell_cache ? 3 : 2) : (p->no_cell_cache ? 1 : 0);
+  if (mode == 0 && p->lds_cell_cache && f->layout == LAYOUT_CELL && !batched) mode = 4;  // SM_LDS
   auto launch = [&](hipStream_t st) {
     if (f->fmt == STREAMI_F32) return launch_advect_f32(a, f->layout, f->periodic, mode, batched, (int)grid, st);
     if (f->fmt == STREAMI_F16) return launch_advect_f16(a, f->layout, f->periodic, mode, batched, (int)grid, st);

@@ -267,8 +267,9 @@ def test_turbulence_block_parity(S, dtype, layout):
 
 
 def test_bit_identical_variants(S):
-    """Cell cache on/off, node rows / bricks / cell records, the interior test on/off, hipGraph
-    replay and chunked resume all give bit-identical lines, steps, codes and outbox contents."""
+    """Cell cache on/off (in registers or in LDS), node rows / bricks / cell records, the
+    interior test on/off, hipGraph replay and chunked resume all give bit-identical lines, steps,
+    codes and outbox contents."""
     note("variants")
     blk = fg.turbulence_block(2, edge=32, rank_grid=(3, 3, 3), rank_coord=(1, 1, 1))
     seeds = fg.uniform_seeds(2, 2500, (0, 0, 0), (32, 32, 32), sub=9)
@@ -276,7 +277,8 @@ def test_bit_identical_variants(S):
     variants = [dict(no_cell_cache=1), dict(layout=1), dict(layout=2), dict(layout=3),
                 dict(layout=3, no_cell_cache=1), dict(checked_samples=1), dict(layout=1, checked_samples=1),
                 dict(use_graph=1), dict(chunk=37),
-                dict(waves_per_cu=8, refill_threshold=1), dict(work_order=1)]
+                dict(waves_per_cu=8, refill_threshold=1), dict(work_order=1), dict(lds_cell_cache=1),
+                dict(layout=3, lds_cell_cache=1, checked_samples=1)]
     for v in variants:
         note("variant", v)
         layout = v.pop("layout", 0)
