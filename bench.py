@@ -463,6 +463,74 @@ def hex_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def forward_bench(args):
+    """The default workload's field split into a 2 x 2 x 2 rank grid of 128^3 blocks in one handle,
+    the same 1M seeds (each seeded in the block that owns it) and limits, traced with loopback
+    forwarding (streami_trace): every exit routed on the device into the neighbouring block,
+    rounds until nothing is active.  Timed with run-to-exit rounds; one pass each with an
+    exchange every 64, 8 and 1 steps (the last is the paper's one exchange per step) shows
+    what the exchange granularity costs on one GPU."""
+    import torch
+    import fieldgen as fg
+    import paper_2606_02627_amd as S
+    edge, m, h = 256, 2000, 0.5
+    whole = fg.turbulence_block(2, edge=edge, rank_grid=(1, 1, 1), rank_coord=(0, 0, 0))
+    parts = fg.partition(whole, (2, 2, 2))
+    seeds = fg.uniform_seeds(2, 1 << 20, (0, 0, 0), (edge,) * 3)
+    owner = (np.floor(seeds / (edge // 2)).astype(int) * np.array([1, 2, 4])).sum(axis=1)
+    f = S.Field(parts, S.F32)
+    layout = S.streami_field_info(f.h)[0]
+    batches = [dict(block=b, xyz=torch.from_numpy(np.ascontiguousarray(seeds[owner == b])).cuda(),
+                    ids=torch.from_numpy(np.nonzero(owner == b)[0].astype(np.uint64)).cuda()) for b in range(8)]
+
+    def one(budget, stats=False):
+        f.clear()
+        f.seed_batches(batches, default_max_steps=m)
+        return S.streami_trace(f.h, S.advect_params(h, step_budget=budget), want_stats=stats)
+
+    r0, st0 = one(0, stats=True)
+    assert st0.active == 0
+    for _ in range(max(0, args.warmup - 1)):
+        one(0)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        one(0)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t) / args.steps
+    steps = int(st0.steps)
+    gran = []
+    for budget in (64, 8, 1):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rk, stk = one(budget, stats=True)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t
+        assert int(stk.steps) == steps and stk.active == 0
+        gran.append(dict(steps_per_exchange=budget, rounds=rk, seconds=sec, steps_per_s=steps / sec,
+                         advect_device_ms=stk.device_ms))
+        log(f"exchange every {budget} steps: {rk} rounds, {sec * 1e3:.1f} ms, {steps / sec:.3g} steps/s")
+    f.close()
+    comp = compulsory_bytes(int(st0.gathers), 96 if layout == S.LAYOUT_CELL else 96, int(st0.vertices), len(seeds),
+                            int(st0.outbox))
+    achieved = comp["total"] / (st0.device_ms * 1e-3) / 1e9
+    out = {
+        "metric": "RK4 particle-steps/s + HBM GB/s; surrogate vs plain at fixed endpoint error",
+        "value": steps / wall, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "forward256-f32", "field": "256^3 turbulence split into 2x2x2 blocks of 128^3 + ghost",
+                   "seeds": len(seeds), "max_steps": m, "h": h, "rounds": r0, "particle_steps_per_step": steps,
+                   "layout": LAYOUT_NAMES[layout]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_advect (8 blocks, forwarding)",
+                     "advect_device_ms_per_step": st0.device_ms, "compulsory_bytes_per_launch": comp,
+                     "kernel_hash": kernel_source_hash()},
+        "exchange_granularity": gran,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def memory_probe(S, field_bytes, record_bytes):
     """Measured peaks of the memory levels for the kernel's access: a plain device copy (HBM
     stream rate) and random record reads (streami_probe_gather) over footprints that live in
@@ -504,7 +572,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="turb256-f32",
                     choices=sorted(WORKLOADS) + ["surrogate-abc", "batched96-f16", "batched96-f16-streaklines",
-                                                 "hex256-f32"])
+                                                 "hex256-f32", "forward256-f32"])
     ap.add_argument("--window-steps", type=int, default=0,
                     help="streaklines: advance in global-time windows of this many steps (0: one launch)")
     ap.add_argument("--layout", type=int, default=0, help="0 auto, 1 linear, 2 brick4, 3 cell records (FP32)")
@@ -534,6 +602,8 @@ def main():
         return batched_bench(args, unsteady=args.workload.endswith("streaklines"))
     if args.workload == "hex256-f32":
         return hex_bench(args)
+    if args.workload == "forward256-f32":
+        return forward_bench(args)
     dev = torch.device("cuda:0")
     log("building inputs", args.workload)
     t0 = time.perf_counter()

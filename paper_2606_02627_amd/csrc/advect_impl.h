@@ -666,14 +666,14 @@ __device__ __forceinline__ void advect_body(const AdvectArgs& A) {
         // mark the unused tail of the old chunk (< 64 records) so fetches skip it
         if (log_ok && cpos + lane < cend) A.log.v[cpos + lane] = make_float4(0.f, 0.f, 0.f, __uint_as_float(LOG_UNUSED));
         unsigned long long nb = 0;
-        if (lane == 0) nb = atomicAdd(A.ctr + CTR_N + PER_LOG, (unsigned long long)LOG_CHUNK);
+        if (lane == 0) nb = atomicAdd(A.ctr + CTR_N + PER_LOG, (unsigned long long)A.log_chunk);
         nb = uniform_u64(__shfl(nb, 0, 64));
-        if (nb + LOG_CHUNK > (unsigned long long)A.log.cap) {
+        if (nb + A.log_chunk > (unsigned long long)A.log.cap) {
           log_ok = false;  // cannot happen when the host sized the log; never write past it
           if (lane == 0) atomicOr(&A.ctr[CTR_OVERFLOW], 1ull);
         }
         cpos = nb;
-        cend = nb + LOG_CHUNK;
+        cend = nb + A.log_chunk;
       }
       if (rec && log_ok) {
         // wave-uniform chunk base (scalar address) + a 32-bit lane offset

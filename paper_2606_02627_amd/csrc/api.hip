@@ -196,6 +196,7 @@ struct streami_field_s {
   DevBuf d_dhat, d_dhat2, d_xh;                      // surrogate jumps
   bool strides_mult16 = true;                        // every seed batch's record stride % 16 == 0
   int max_m = 0;                                     // largest per-particle step limit seeded
+  long long active_hint = -1;  // particles known ACTIVE (after an exchange), -1: not known
   unsigned long long next_auto_id = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipGraphExec_t graph = nullptr;
@@ -340,15 +341,17 @@ int ensure_particles(streami_field_s* f, long long need) {
 // Make the vertex log hold every record still to come: the records reserved so
 // far, the vertices particles may still record, and `slack` more (unused chunk
 // tails of one launch).  Grows by reallocation, keeping the reserved records.
-int ensure_log(streami_field_s* f, long long slack) {
+int ensure_log(streami_field_s* f, long long slack, long long chunk = LOG_CHUNK) {
   unsigned long long c[PER_N];
   HIP_TRY(hipMemcpyAsync(c, f->persist(), sizeof c, hipMemcpyDeviceToHost, f->stream));
   HIP_TRY(hipStreamSynchronize(f->stream));
   const long long count = (long long)std::min<unsigned long long>(c[PER_LOG], (unsigned long long)f->log_cap);
   // a wave abandons < 64 records of a chunk when it switches chunks: reserve
-  // the remaining bound plus 1/8 for those tails, plus `slack` for last chunks
+  // the remaining bound plus 64/chunk of it (at least 1/8) for those tails,
+  // plus `slack` for last chunks
   const long long remaining = std::max<long long>(f->vert_bound - (long long)c[PER_LOG_REAL], 0);
-  const long long need = (long long)c[PER_LOG] + remaining + remaining / 8 + slack;
+  const long long den = std::max<long long>(1, std::min<long long>(8, chunk / 64));
+  const long long need = (long long)c[PER_LOG] + remaining + remaining / den + slack;
   f->log_need_known = true;
   f->log_need_hi = need - slack;
   if (need <= f->log_cap) return STREAMI_OK;
@@ -892,6 +895,7 @@ int seed_batches(streami_field_s* f, const streami_seed_batch* bt, int nb, const
   }
   if (!dev_in) HIP_TRY(hipStreamSynchronize(f->stream));  // staging buffers are freed on return
   f->max_m = std::max(f->max_m, batch_max);
+  f->active_hint = -1;  // new particles: the active count is no longer known
   if (opts->record_stride % 16 != 0) f->strides_mult16 = false;
   return STREAMI_OK;
 }
@@ -1030,7 +1034,17 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
   grid = std::min(grid, (f->n_particles + 255) / 256);
   grid = std::max(grid, 1LL);
   {
-    int rc = ensure_log(f, grid * 4 * (long long)LOG_CHUNK);
+    // chunk size: a quarter of the records a wave may write in this call (every active particle
+    // steps at most the budget or its largest limit), as a power of two in [LOG_CHUNK_MIN,
+    // LOG_CHUNK], so the tails abandoned at chunk switches and at the end stay near a quarter of
+    // what is written even when calls are short (exchange rounds of a few steps)
+    const long long steps_bound = p->step_budget > 0 ? std::min<long long>(p->step_budget, f->max_m) : f->max_m;
+    const long long n_est = f->active_hint >= 0 ? std::min(f->active_hint, f->n_particles) : f->n_particles;
+    const long long per_wave = (n_est * (steps_bound + 1) + grid * 4 - 1) / (grid * 4);
+    long long chunk = LOG_CHUNK_MIN;
+    while (4 * chunk < per_wave && chunk < LOG_CHUNK) chunk <<= 1;
+    a.log_chunk = (unsigned)chunk;
+    int rc = ensure_log(f, grid * 4 * chunk, chunk);
     if (rc) return rc;
   }
   a.log = f->log();
@@ -1112,6 +1126,7 @@ int streami_clear(streami_field f) {
   if (!f) return fail(STREAMI_E_ARG, "field handle is NULL");
   drop_graph(f);
   f->n_particles = 0;
+  f->active_hint = -1;
   f->vert_bound = 0;
   f->max_m = 0;
   f->strides_mult16 = true;
@@ -1363,6 +1378,7 @@ int streami_forward(streami_field f, int64_t* n_forwarded, int64_t* n_active) {
     HIP_TRY(hipMemcpyAsync(&c, f->code_counts() + ACTIVE, 8, hipMemcpyDeviceToHost, f->stream));
     HIP_TRY(hipStreamSynchronize(f->stream));
     *n_active = (int64_t)c;
+    f->active_hint = (long long)c;
   }
   return STREAMI_OK;
 }

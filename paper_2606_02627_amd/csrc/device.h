@@ -77,7 +77,11 @@ enum Persist { PER_OUTBOX = 0, PER_LOG = 1, PER_LOG_REAL = 2, PER_N = 4 };
 // sorts the requested particles' records stably by row to get their lines.
 // Records per wave reservation.  Every wave reserves from one counter, so the
 // chunk is large: at 1024 records the contended atomic cost a third of a pass.
+// A launch sizes its chunks to the records a wave is expected to write (at most
+// LOG_CHUNK): short launches (a step budget of a few steps) would otherwise
+// abandon most of every chunk.
 constexpr int LOG_CHUNK = 8192;
+constexpr int LOG_CHUNK_MIN = 64;
 constexpr unsigned LOG_UNUSED = 0xffffffffu;  // particle index of an unused record
 
 struct VertexLog {
@@ -116,6 +120,7 @@ struct AdvectArgs {
   float t_end;              // with `windowed`, a step starts only at t < t_end
   int windowed;             // 0: no time window (the time is then only the sampler's)
   int checked;              // 1: test every sample's domain even deep inside the block
+  unsigned log_chunk;       // records per log reservation of a wave (LOG_CHUNK_MIN .. LOG_CHUNK)
 };
 
 // One surrogate jump (16 plain steps) for every active particle of a single

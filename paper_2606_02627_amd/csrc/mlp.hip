@@ -309,10 +309,11 @@ __global__ void __launch_bounds__(64 * INFER_WAVES) k_mlp_infer(InferArgs a) {
     for (int i = tid; i < tiles * ks * 64; i += 64 * INFER_WAVES) wl[i] = a.frag[FR_OFF[l] + i];
     for (int i = tid; i < 256; i += 64 * INFER_WAVES) bl[i] = i < WID[l + 1] ? a.b[l][i] : 0.0f;
     __syncthreads();
+    // the accumulators start at the bias of the feature each register holds
 #pragma unroll
     for (int t = 0; t < tiles; ++t)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[t][r] = 0.0f;
+      for (int r = 0; r < 16; ++r) acc[t][r] = bl[32 * t + 8 * (r / 4) + 4 * hi + r % 4];
 #pragma unroll
     for (int s = 0; s < ks; ++s)
 #pragma unroll
@@ -329,12 +330,12 @@ __global__ void __launch_bounds__(64 * INFER_WAVES) k_mlp_infer(InferArgs a) {
 #pragma unroll
           for (int j = 0; j < 8; ++j) {
             const int r = 8 * q + j;
-            h[j] = silu_fast(acc[t][r] + bl[32 * t + 8 * (r / 4) + 4 * hi + r % 4]);
+            h[j] = silu_fast(acc[t][r]);
           }
           B[2 * t + q] = __builtin_convertvector(h, bf16x8);
         }
     } else if (live && hi == 0) {
-      for (int c = 0; c < 3; ++c) a.out[p * 3 + c] = a.sigma[c] * (acc[0][c] + bl[c]);
+      for (int c = 0; c < 3; ++c) a.out[p * 3 + c] = a.sigma[c] * acc[0][c];
     }
   }
 }

@@ -16,7 +16,7 @@ import pytest
 
 import fieldgen as fg
 import oracle
-from tests.parity import boundary_sensitive, global_compare, local_check
+from tests.parity import boundary_sensitive, global_compare, local_check, restart_check
 
 pytestmark = pytest.mark.gpu
 
@@ -152,4 +152,80 @@ def test_forward_without_a_common_rank_grid_is_refused(S):
     with pytest.raises(S.StreamiError) as e:
         f.forward()
     assert e.value.code == S.E_UNSUPPORTED
+    f.close()
+
+
+def test_forward256_full_size_sampled(S):
+    """The forwarding workload as benchmarked: the 256^3 field split into 2 x 2 x 2 blocks of 128^3
+    in one handle, 1M seeds each in the block that owns it, limits of 2000 steps, traced with
+    run-to-exit rounds.  4096 sample seeds record every vertex (the rest their seed and last
+    vertex of each segment, which forwarding preserves per particle); their stitched lines pass
+    the per-step rule against the oracle of the whole, unsplit field, and their codes and step
+    counts equal its late restarts.  Every id ends exactly once, in one block, after at most one
+    segment per block visited."""
+    import torch
+    note("forwarding at full size: 2x2x2 blocks of 128^3, 1M seeds")
+    edge, m = 256, 2000
+    whole = fg.turbulence_block(2, edge=edge, rank_grid=(1, 1, 1), rank_coord=(0, 0, 0))
+    parts = fg.partition(whole, (2, 2, 2))
+    seeds = fg.uniform_seeds(2, 1 << 20, (0, 0, 0), (edge,) * 3)
+    owner = (np.floor(seeds / (edge // 2)).astype(int) * np.array([1, 2, 4])).sum(axis=1)
+    sample = np.zeros(len(seeds), bool)
+    sample[123456:123456 + 4096] = True
+    f = S.Field(parts, S.F32)
+    for stride, sel in ((1 << 20, ~sample), (1, sample)):
+        f.seed_batches([dict(block=b, xyz=torch.from_numpy(np.ascontiguousarray(seeds[(owner == b) & sel])).cuda(),
+                             ids=torch.from_numpy(np.nonzero((owner == b) & sel)[0].astype(np.uint64)).cuda())
+                        for b in range(8)], default_max_steps=m, record_stride=stride)
+    rounds, st = f.trace(H)
+    assert st.active == 0
+    # segments of every id, ordered by their step counts (any record stride): a segment that
+    # hands the particle on ends with EXIT at the vertex the next one, in another block, starts
+    segs = {}
+    for b in range(8):
+        Lb = f.lines(b)
+        off = Lb["offsets"]
+        for i, pid in enumerate(Lb["ids"].tolist()):
+            segs.setdefault(pid, []).append((int(Lb["steps"][i]), Lb["xyz"][off[i]:off[i + 1]], int(Lb["codes"][i]), b))
+    assert sorted(segs) == list(range(len(seeds)))
+    lines = {}
+    for pid, ss in segs.items():
+        # chained by their joints: a particle that leaves exactly at its step limit is handed on
+        # and ends at once in the next block, so step counts alone can tie
+        ss.sort(key=lambda q: q[0])
+        chain = [next((q for q in ss if np.array_equal(q[1][0], seeds[pid])), ss[0])]
+        rest = [q for q in ss if q is not chain[0]]
+        while rest:
+            nxt = [q for q in rest if np.array_equal(q[1][0], chain[-1][1][-1]) and q[0] >= chain[-1][0]]
+            if not nxt:
+                break
+            chain.append(nxt[0])
+            rest = [q for q in rest if q is not nxt[0]]
+        ok = not rest and np.array_equal(chain[0][1][0], seeds[pid])
+        ss = chain
+        for a, c in zip(ss[:-1], ss[1:]):
+            ok = ok and a[2] in (S.EXIT, S.HALO_MISS) and c[3] != a[3] and np.array_equal(c[1][0], a[1][-1])
+        if not ok:
+            note(f"id {pid} seed {seeds[pid].tolist()} owner {owner[pid]}: segments (steps, code, block, first, last): "
+                 + "; ".join(f"({q[0]}, {q[2]}, {q[3]}, {q[1][0].tolist()}, {q[1][-1].tolist()})" for q in ss))
+            raise AssertionError(f"segments of id {pid} do not chain")
+        if sample[pid]:
+            lines[pid] = (np.concatenate([ss[0][1]] + [q[1][1:] for q in ss[1:]]), ss[-1][0], ss[-1][2], len(ss))
+    ids = np.nonzero(sample)[0]
+    note(f"{rounds} rounds, {st.steps} steps; checking {len(ids)} stitched lines")
+    xyz = [lines[i][0] for i in ids]
+    assert all(len(v) == lines[i][1] + 1 for v, i in zip(xyz, ids))  # stride 1: one vertex per step
+    L = dict(offsets=np.concatenate([[0], np.cumsum([len(v) for v in xyz])]), xyz=np.concatenate(xyz),
+             steps=np.array([lines[i][1] for i in ids], np.int32), codes=np.array([lines[i][2] for i in ids], np.int32))
+    W = oracle.Field.from_block(whole)
+    worst, cnt = local_check(W, L, H, edge)
+    frac, bad = restart_check(W, L, H, whole.lo, whole.hi, m)
+    segs = np.array([lines[i][3] for i in ids])
+    note(f"local rule: worst ratio {worst:.3f} over {cnt} steps; late restart compares {frac:.4f}; "
+         f"{(segs > 1).mean():.2f} of the sampled lines cross a block face (max {segs.max()} segments)")
+    assert worst <= 1.0 and cnt > 4096 * 100
+    assert frac >= 0.97 and len(bad) == 0, (frac, bad[:10])
+    assert (segs > 1).mean() > 0.3
+    ob = f.outbox(cap=len(seeds))
+    assert (ob["dest"] == -1).all() and len(np.unique(ob["id"])) == len(ob)
     f.close()
