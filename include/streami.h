@@ -243,7 +243,7 @@ int streami_seed_shape(streami_field f, int32_t block, const streami_shape* shap
  * emitters' particles' final positions ordered by release time.
  */
 
-/* One seed batch of streami_seed_batches(): the arguments of one/* One seed batch of streami_seed_batches(): the arguments of one
+/* One seed batch of streami_seed_batches(): the arguments of one
  * streami_seed() call (birth times per batch instead of in the options). */
 typedef struct {
   int32_t block;
