@@ -577,18 +577,22 @@ __device__ __forceinline__ void advect_body(const AdvectArgs& A) {
     if (!queue_done && dead != 0 && (__popcll(dead) >= A.refill || dead == all)) {
       const int cnt = __popcll(dead);
       const int leader = __ffsll((long long)dead) - 1;
-      const long long qlo = n_work * q / A.n_queues, qhi = n_work * (q + 1) / A.n_queues;
+      // queue q: positions q, q + n_queues, ... of the order (qn of them); the slots
+      // claimed here belong to this queue even when q moves on below
+      const int qc = q;
+      const long long qn = (n_work - qc + A.n_queues - 1) / A.n_queues;
       unsigned long long qbase = 0;
       if (lane == leader) qbase = atomicAdd(&A.qctr[q * QCTR_STRIDE], (unsigned long long)cnt);
       qbase = __shfl(qbase, leader, 64);
-      const long long first = qlo + (long long)qbase;
-      if (first + cnt >= qhi) {  // this range is used up: continue with the next one
+      const long long first = (long long)qbase;
+      if (first + cnt >= qn) {  // this queue is used up: continue with the next one
         q = (q + 1 == A.n_queues) ? 0 : q + 1;
         if (++tries == A.n_queues) queue_done = true;
       }
       if (p < 0) {
-        const long long slot = first + (long long)lanes_below(dead);
-        if (slot < qhi) {
+        const long long k = first + (long long)lanes_below(dead);
+        if (k < qn) {
+          const long long slot = k * A.n_queues + qc;
           const long long my = A.order ? (long long)A.order[slot] : slot;
           const int4 mt = A.meta[my];
           const float4 ps = A.pos[my];

@@ -40,8 +40,8 @@ int launch_mark_rows(const long long* idx, long long count, int* row_of, hipStre
 int launch_fill_u32(unsigned* p, long long n, unsigned v, hipStream_t st);
 int launch_max_abs(const void* src, int fmt, long long n, unsigned* out, hipStream_t st);
 int launch_work_order(const float4* pos, const int4* meta, const int4* meta2, const BlockDev* blocks, long long n,
-                      int bits, unsigned n_buckets, float h, float t_end, unsigned* key, unsigned* hist,
-                      unsigned* cursor, int* order, unsigned* n_work, hipStream_t st);
+                      int bits, unsigned n_buckets, int n_classes, int span, float h, float t_end, unsigned* key,
+                      unsigned* hist, unsigned* cursor, int* order, unsigned* n_work, hipStream_t st);
 int launch_fill_u64(unsigned long long* p, long long n, unsigned long long v, hipStream_t st);
 int launch_seed_bound(const SeedJobs& J, long long total, unsigned long long* out, hipStream_t st);
 std::string build_hex_blob(const float* V, long long nv, const float* val, const int* cells, long long nc, float tol,
@@ -1050,8 +1050,11 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
   a.log = f->log();
   // spatial work order (bucket sort by block and Morton brick) over per-XCD queues
   const bool spatial = p->work_order == 0;
+  // spatial work order: classes of remaining steps (longest first), then block and Morton brick
   const int bits = f->blocks.size() == 1 ? 5 : 3;
-  const unsigned n_buckets = (unsigned)f->blocks.size() * (1u << (3 * bits)) + 1;
+  const int n_classes = ORDER_CLASSES;
+  const int span = (int)std::max<long long>(1, p->step_budget > 0 ? std::min<long long>(p->step_budget, f->max_m) : f->max_m);
+  const unsigned n_buckets = (unsigned)n_classes * (unsigned)f->blocks.size() * (1u << (3 * bits)) + 1;
   {
     int rc;
     if ((rc = f->d_qctr.reserve(sizeof(unsigned long long) * MAX_QUEUES * QCTR_STRIDE, 0, f->stream))) return rc;
@@ -1095,7 +1098,7 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
       launch_fill_u64(a.qctr, MAX_QUEUES * QCTR_STRIDE, 0, cs);
       if (spatial)
         launch_work_order((const float4*)f->d_pos.p, (const int4*)f->d_meta.p, (const int4*)f->d_meta2.p,
-                          (const BlockDev*)f->d_blocks.p, f->n_particles, bits, n_buckets, a.h, a.t_end, (unsigned*)f->d_key.p,
+                          (const BlockDev*)f->d_blocks.p, f->n_particles, bits, n_buckets, n_classes, span, a.h, a.t_end, (unsigned*)f->d_key.p,
                           (unsigned*)f->d_hist.p, (unsigned*)f->d_cursor.p, (int*)f->d_order.p,
                           (unsigned*)f->d_nwork.p, cs);
       launch(cs);
@@ -1111,7 +1114,7 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
     launch_fill_u64(a.qctr, MAX_QUEUES * QCTR_STRIDE, 0, f->stream);
     if (spatial)
       launch_work_order((const float4*)f->d_pos.p, (const int4*)f->d_meta.p, (const int4*)f->d_meta2.p,
-                        (const BlockDev*)f->d_blocks.p, f->n_particles, bits, n_buckets, a.h, a.t_end, (unsigned*)f->d_key.p,
+                        (const BlockDev*)f->d_blocks.p, f->n_particles, bits, n_buckets, n_classes, span, a.h, a.t_end, (unsigned*)f->d_key.p,
                         (unsigned*)f->d_hist.p, (unsigned*)f->d_cursor.p, (int*)f->d_order.p,
                         (unsigned*)f->d_nwork.p, f->stream);
     launch(f->stream);

@@ -106,9 +106,11 @@ struct AdvectArgs {
   unsigned long long* ctr;           // per-call counters
   long long n_particles;
   // work order: particles are claimed in the order of `order` (NULL: index
-  // order), the first *n_work entries only; the order is split into
-  // n_queues contiguous ranges, one per XCD (workgroups are dispatched to the
-  // XCDs round-robin), and a wave that empties its range steals from the next
+  // order), the first *n_work entries only; the order is dealt to n_queues
+  // queues, one per XCD (workgroups are dispatched to the XCDs round-robin):
+  // queue q holds positions q, q + n_queues, q + 2 n_queues, ..., so every
+  // queue starts with the longest work; a wave that empties its queue steals
+  // from the next
   const int* order;
   const unsigned* n_work;
   unsigned long long* qctr;  // n_queues counters, QCTR_STRIDE apart
@@ -155,6 +157,7 @@ __device__ __forceinline__ void to_monomial(float3 c[8]) {
 
 constexpr int QCTR_STRIDE = 16;  // one 128-byte line per queue counter
 constexpr int MAX_QUEUES = 8;
+constexpr int ORDER_CLASSES = 8;  // classes of remaining steps in the spatial work order
 
 // Per-axis offsets of node i within a slice of a block.
 template <int LAYOUT>

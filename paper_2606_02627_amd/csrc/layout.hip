@@ -404,8 +404,10 @@ namespace streami {
 
 // ---------------------------------------------------------------- work order
 // Active particles whose next step lies inside the time window are bucketed by
-// (block, Morton index of a coarse brick of their position) so that lanes of a
-// wave and waves of an XCD work on nearby cells; the others (terminated, or
+// (class of the steps they may still take, longest first; block; Morton index
+// of a coarse brick of their position): particles that may run longest start
+// first, so that the launch does not end waiting for a long trajectory started
+// late, and lanes of a wave work on nearby cells.  The others (terminated, or
 // waiting for a later window) get the last key and no slot in the order.
 // The order only decides which lane advances which particle, never what is
 // computed, so results do not depend on it.
@@ -418,9 +420,11 @@ __device__ __forceinline__ unsigned spread3(unsigned v) {  // 5 bits -> every th
   return v;
 }
 
+// n_classes classes of the remaining steps min(max_steps - steps, span) in [0, span]
 __global__ void k_order_keys(const float4* pos, const int4* meta, const int4* meta2, const BlockDev* blocks,
-                             long long n, int bits, unsigned n_buckets, float h, float t_end, unsigned* key,
-                             unsigned* hist) {
+                             long long n, int bits, unsigned n_buckets, int n_classes, int span, float h, float t_end,
+                             unsigned* key, unsigned* hist) {
+  const unsigned n_spatial = (n_buckets - 1) / (unsigned)n_classes;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
     unsigned k = n_buckets - 1;
     const int4 mt = meta[i];
@@ -438,7 +442,10 @@ __global__ void k_order_keys(const float4* pos, const int4* meta, const int4* me
         if (B.periodic) w -= side * floorf(w / side);
         c[a] = (unsigned)__builtin_amdgcn_fmed3f(w, 0.0f, side - 1.0f);
       }
-      k = (unsigned)blk * (1u << (3 * bits)) + (spread3(c[0]) | (spread3(c[1]) << 1) | (spread3(c[2]) << 2));
+      const int rem = min(mt.y - mt.x, span);
+      const int cls = min(n_classes - 1, (int)((long long)max(rem, 0) * n_classes / ((long long)span + 1)));
+      k = (unsigned)(n_classes - 1 - cls) * n_spatial + (unsigned)blk * (1u << (3 * bits)) +
+          (spread3(c[0]) | (spread3(c[1]) << 1) | (spread3(c[2]) << 2));
     }
     key[i] = k;
     // idle particles (terminated, or outside the window) take no slot: only the
@@ -484,14 +491,14 @@ __global__ void k_order_scatter(const unsigned* key, long long n, unsigned idle,
 }
 
 int launch_work_order(const float4* pos, const int4* meta, const int4* meta2, const BlockDev* blocks, long long n,
-                      int bits, unsigned n_buckets, float h, float t_end, unsigned* key, unsigned* hist,
-                      unsigned* cursor, int* order, unsigned* n_work, hipStream_t st) {
+                      int bits, unsigned n_buckets, int n_classes, int span, float h, float t_end, unsigned* key,
+                      unsigned* hist, unsigned* cursor, int* order, unsigned* n_work, hipStream_t st) {
   if (n <= 0) return 0;
   long long grid = (n + 255) / 256;
   if (grid > 16384) grid = 16384;
   launch_fill_u32(hist, n_buckets, 0u, st);
   hipLaunchKernelGGL(k_order_keys, dim3((unsigned)grid), dim3(256), 0, st, pos, meta, meta2, blocks, n, bits,
-                     n_buckets, h, t_end, key, hist);
+                     n_buckets, n_classes, span, h, t_end, key, hist);
   hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(1024), 0, st, hist, n_buckets, cursor, n_work);
   hipLaunchKernelGGL(k_order_scatter, dim3((unsigned)grid), dim3(256), 0, st, key, n, n_buckets - 1, cursor, order);
   return 0;
