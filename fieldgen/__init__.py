@@ -446,6 +446,69 @@ def hex_mesh_from_block(blk: Block) -> dict:
                 rank_grid=tuple(blk.rank_grid), rank_coord=tuple(blk.rank_coord))
 
 
+# VTK cell type codes of the unstructured meshes
+VTK_TETRA, VTK_HEXAHEDRON, VTK_WEDGE, VTK_PYRAMID = 10, 12, 13, 14
+_VTK_HEX_INDEX = {c: i for i, c in enumerate(VTK_HEX_CORNERS)}  # corner bits (x, y, z) -> VTK vertex
+# six tetrahedra around the diagonal (0,0,0)-(1,1,1) of a cube, one per order of the axes
+# (the Kuhn / Freudenthal subdivision: neighbouring cubes split shared faces alike)
+_KUHN = []
+for _ax in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
+    _p = [0, 0, 0]
+    _path = [tuple(_p)]
+    for _a in _ax:
+        _p[_a] = 1
+        _path.append(tuple(_p))
+    _KUHN.append([_VTK_HEX_INDEX[q] for q in _path])
+# two wedges: bottom and top quads split along the diagonal (0,0)-(1,1)
+_WEDGES = [[0, 1, 2, 4, 5, 6], [0, 2, 3, 4, 6, 7]]
+# six faces of a cube (VTK vertex indices, each in cyclic order) as pyramid bases around the centre
+_FACES = [[0, 1, 2, 3], [4, 7, 6, 5], [0, 4, 5, 1], [3, 2, 6, 7], [0, 3, 7, 4], [1, 5, 6, 2]]
+
+
+def split_hex_mesh(mesh: dict, kind: str) -> dict:
+    """Every hexahedron of a lattice mesh (hex_mesh_from_block, distorted_hex_mesh) split into
+    conforming cells of other kinds: "tetra" (6 per cube, Kuhn subdivision), "wedge" (2 per
+    cube), "pyramid" (6 per cube around a new centre vertex: the mean of the cube's corners,
+    value the mean of their values, FP32), "hex+pyramid" (a checkerboard of whole cubes and
+    cubes of 6 pyramids; a pyramid base is a whole cube face, so neighbours interpolate
+    alike on it).  cells: [n, 8] int32, each row the cell's vertices in VTK order and -1 after
+    them; cell_types: [n] uint8 VTK codes.  Same bounds and rank grid."""
+    cells = np.asarray(mesh["cells"], np.int64)
+    V = np.asarray(mesh["vertices"], np.float64)
+    W = np.asarray(mesh["values"], np.float64)
+    out_cells, out_types = [], []
+    verts, vals = [mesh["vertices"]], [mesh["values"]]
+    n_v = len(V)
+    if kind == "hex+pyramid":
+        c0 = V[cells[:, 0]]
+        parity = np.floor(c0 + 0.5).astype(np.int64).sum(axis=1) % 2 if len(cells) else np.zeros(0, np.int64)
+    for c, row in enumerate(cells):
+        if kind == "tetra":
+            for t in _KUHN:
+                out_cells.append(list(row[t]) + [-1] * 4)
+                out_types.append(VTK_TETRA)
+        elif kind == "wedge":
+            for w in _WEDGES:
+                out_cells.append(list(row[w]) + [-1] * 2)
+                out_types.append(VTK_WEDGE)
+        elif kind == "pyramid" or (kind == "hex+pyramid" and parity[c] == 1):
+            centre = n_v + len(verts) - 1
+            verts.append(V[row].mean(axis=0, keepdims=True).astype(np.float32))
+            vals.append(W[row].mean(axis=0, keepdims=True).astype(np.float32))
+            for f in _FACES:
+                out_cells.append(list(row[f]) + [centre] + [-1] * 3)
+                out_types.append(VTK_PYRAMID)
+        elif kind == "hex+pyramid":
+            out_cells.append(list(row))
+            out_types.append(VTK_HEXAHEDRON)
+        else:
+            raise ValueError(kind)
+    return dict(mesh, vertices=np.ascontiguousarray(np.concatenate(verts), np.float32),
+                values=np.ascontiguousarray(np.concatenate(vals), np.float32),
+                cells=np.asarray(out_cells, np.int32).reshape(-1, 8),
+                cell_types=np.asarray(out_types, np.uint8))
+
+
 def distorted_hex_mesh(config: int, dims, jitter: float = 0.2, sub: int = 0, field=None) -> dict:
     """A conforming mesh of dims = (cx, cy, cz) hexahedra over [0, cx] x [0, cy] x [0, cz]: a unit
     lattice whose vertices move by up to `jitter` (uniform, per coordinate; vertices on the

@@ -1,24 +1,30 @@
-"""FP64 oracle of an unstructured hexahedral field -- TEST INFRASTRUCTURE.
+"""FP64 oracle of an unstructured field -- TEST INFRASTRUCTURE.
 
 Only tests/ may import it.  It shares no code with the GPU library.
 
-The paper's second field type (Sec. 3.3) is an unstructured grid located by point
-containment; its benchmark converts every voxel of a structured data set to a
-hexahedron (Sec. 5).  Definitions, written out plainly (no acceleration structure:
-every cell is tested):
+The paper's second field type (Sec. 3.3) is an unstructured grid of tetrahedra, pyramids,
+wedges (prisms) and hexahedra located by point containment; its benchmark converts every
+voxel of a structured data set to a hexahedron (Sec. 5).  Definitions, written out plainly
+(no acceleration structure: every cell whose vertex box holds the point is tested):
 
-  * cell c has 8 vertices in VTK hexahedron order; the corner with parametric
-    coordinates (r, s, u) in {0,1}^3 is vertex VTK_OF_CORNER[r + 2s + 4u];
-  * its trilinear map  X(r,s,u) = sum_corners w(r) w(s) w(u) X_corner  with
-    w(0) = 1 - r, w(1) = r (and likewise for s, u);
-  * x lies in c iff X(r,s,u) = x has a solution with r, s, u in [0, 1]
-    (found by Newton's method from the cell centre, to FP64 convergence);
-  * sample(x) = the same trilinear weights applied to the vertex values of the
-    first such cell in cell order (every containing cell gives the same value
-    on a conforming mesh: the interpolant is continuous across shared faces);
-    undefined (False) when no cell contains x (Sec. 3.1.1: sample() fails);
-  * destinationID, the owned bounds and the RK4 update with its termination
-    rules are those of the structured oracle (Sec. 3.1.1, Sec. 3.1.2).
+  * each cell lists its vertices in VTK order (VTK_TETRA 4, VTK_PYRAMID 5, VTK_WEDGE 6,
+    VTK_HEXAHEDRON 8 vertices) and maps parametric coordinates (r, s, t) to space with the
+    VTK linear shape functions N_i:
+      hexahedron  the trilinear weights w(r) w(s) w(t), w(0) = 1 - r, w(1) = r, of the corner
+                  with parametric coordinates in {0,1}^3; the corner r + 2s + 4t is vertex
+                  VTK_OF_CORNER[r + 2s + 4t]; domain [0,1]^3;
+      tetra       1 - r - s - t, r, s, t;  domain r, s, t >= 0, r + s + t <= 1;
+      wedge       (1-r-s)(1-t), r(1-t), s(1-t), (1-r-s)t, r t, s t;
+                  domain r, s >= 0, r + s <= 1, 0 <= t <= 1;
+      pyramid     (1-r)(1-s)(1-t), r(1-s)(1-t), r s (1-t), (1-r) s (1-t), t;  domain [0,1]^3
+                  (the base quad in order, the apex last);
+  * x lies in a cell iff X(r,s,t) = sum N_i X_i = x has a solution in the cell's domain (found
+    by Newton's method to FP64 convergence; a tetrahedron's map is affine);
+  * sample(x) = sum N_i V_i at that solution in the first such cell in cell order (on a mesh
+    whose neighbouring cells interpolate alike on shared faces every containing cell gives
+    the same value); undefined (False) when no cell contains x (Sec. 3.1.1: sample() fails);
+  * destinationID, the owned bounds and the RK4 update with its termination rules are those
+    of the structured oracle (Sec. 3.1.1, Sec. 3.1.2).
 """
 from __future__ import annotations
 
@@ -31,6 +37,46 @@ from . import ACTIVE, EXIT, HALO_MISS, MAX_STEPS, NONFINITE, STAGNANT
 VTK_OF_CORNER = np.array([0, 1, 3, 2, 4, 5, 7, 6])
 CORNER_BITS = np.array([[i & 1, (i >> 1) & 1, (i >> 2) & 1] for i in range(8)], np.float64)
 INSIDE_TOL = 1e-12  # parametric slack for points on a cell face
+
+# VTK cell type codes and vertex counts
+VTK_TETRA, VTK_HEXAHEDRON, VTK_WEDGE, VTK_PYRAMID = 10, 12, 13, 14
+N_VERTS = {VTK_TETRA: 4, VTK_HEXAHEDRON: 8, VTK_WEDGE: 6, VTK_PYRAMID: 5}
+START = {VTK_TETRA: (0.25, 0.25, 0.25), VTK_WEDGE: (1 / 3, 1 / 3, 0.5), VTK_PYRAMID: (0.5, 0.5, 0.5)}
+
+
+def shape(kind, rst):
+    """VTK shape functions of a tetra, wedge or pyramid at parametric points rst [n, 3]:
+    (N [n, k], dN/d(r,s,t) [n, k, 3])."""
+    rst = np.asarray(rst, np.float64)
+    r, s, t = rst[:, 0], rst[:, 1], rst[:, 2]
+    o, z = np.ones_like(r), np.zeros_like(r)
+    if kind == VTK_TETRA:
+        N = [1 - r - s - t, r, s, t]
+        dN = [(-o, -o, -o), (o, z, z), (z, o, z), (z, z, o)]
+    elif kind == VTK_WEDGE:
+        a = 1 - r - s
+        N = [a * (1 - t), r * (1 - t), s * (1 - t), a * t, r * t, s * t]
+        dN = [(-(1 - t), -(1 - t), -a), (1 - t, z, -r), (z, 1 - t, -s), (-t, -t, a), (t, z, r), (z, t, s)]
+    elif kind == VTK_PYRAMID:
+        N = [(1 - r) * (1 - s) * (1 - t), r * (1 - s) * (1 - t), r * s * (1 - t), (1 - r) * s * (1 - t), t]
+        dN = [(-(1 - s) * (1 - t), -(1 - r) * (1 - t), -(1 - r) * (1 - s)),
+              ((1 - s) * (1 - t), -r * (1 - t), -r * (1 - s)),
+              (s * (1 - t), r * (1 - t), -r * s),
+              (-s * (1 - t), (1 - r) * (1 - t), -(1 - r) * s),
+              (z, z, o)]
+    else:
+        raise ValueError(kind)
+    return np.stack(N, 1), np.stack([np.stack(d, 1) for d in dN], 1)
+
+
+def in_domain(kind, rst, tol):
+    """Parametric points [n, 3] inside a cell kind's domain, with slack tol."""
+    r, s, t = rst[:, 0], rst[:, 1], rst[:, 2]
+    if kind == VTK_TETRA:
+        return (r >= -tol) & (s >= -tol) & (t >= -tol) & (r + s + t <= 1 + tol)
+    if kind == VTK_WEDGE:
+        return (r >= -tol) & (s >= -tol) & (r + s <= 1 + tol) & (t >= -tol) & (t <= 1 + tol)
+    return np.all((rst >= -tol) & (rst <= 1 + tol), axis=1)
 
 
 def weights(rsu):
@@ -59,17 +105,34 @@ def weight_derivs(rsu):
 
 
 class HexField:
-    """A steady hexahedral field: vertices [nv, 3], values [nv, 3], cells [nc, 8] (VTK order),
-    owned bounds [lo, hi) and a rank grid for destinationID."""
+    """A steady unstructured field: vertices [nv, 3], values [nv, 3], cells [nc, 8] (each row
+    the cell's vertices in VTK order, unused trailing entries ignored), cell_types [nc] (VTK
+    codes; None: all hexahedra), owned bounds [lo, hi) and a rank grid for destinationID."""
 
-    def __init__(self, vertices, values, cells, lo, hi, rank_grid=(1, 1, 1), rank_coord=(0, 0, 0)):
+    def __init__(self, vertices, values, cells, lo, hi, rank_grid=(1, 1, 1), rank_coord=(0, 0, 0),
+                 cell_types=None):
         vertices = np.asarray(vertices, np.float64)
         values = np.asarray(values, np.float64)
         cells = np.asarray(cells, np.int64)
-        self.X = vertices[cells[:, VTK_OF_CORNER]]  # [nc, 8, 3] corners by parametric index
-        self.V = values[cells[:, VTK_OF_CORNER]]
-        self.box_lo = self.X.min(axis=1)
-        self.box_hi = self.X.max(axis=1)
+        nc = len(cells)
+        self.types = (np.full(nc, VTK_HEXAHEDRON, np.int64) if cell_types is None
+                      else np.asarray(cell_types, np.int64).reshape(nc))
+        assert set(np.unique(self.types).tolist()) <= set(N_VERTS), "unknown cell type"
+        self.cells = cells
+        self.P = vertices
+        self.Vv = values
+        hexes = self.types == VTK_HEXAHEDRON
+        safe = np.where(hexes[:, None], cells, 0)
+        self.X = vertices[safe[:, VTK_OF_CORNER]]  # [nc, 8, 3] hexahedron corners by parametric index
+        self.V = values[safe[:, VTK_OF_CORNER]]
+        self.box_lo = np.empty((nc, 3))
+        self.box_hi = np.empty((nc, 3))
+        for kind, k in N_VERTS.items():
+            sel = self.types == kind
+            if sel.any():
+                pts = vertices[cells[sel, :k]]
+                self.box_lo[sel] = pts.min(axis=1)
+                self.box_hi[sel] = pts.max(axis=1)
         self.lo = np.asarray(lo, np.float64)
         self.hi = np.asarray(hi, np.float64)
         self.rank_grid = np.asarray(rank_grid, np.int64)
@@ -101,6 +164,33 @@ class HexField:
         rsu[~done | ~np.isfinite(rsu).all(axis=1)] = np.nan
         return rsu
 
+    def invert_kind(self, kind, cell, x, iters=60):
+        """Parametric coordinates of x in tetra, wedge or pyramid cells of one kind (Newton from
+        the domain's centre; one step for a tetrahedron); NaN rows where it does not converge."""
+        P = self.P[self.cells[cell, :N_VERTS[kind]]]  # [m, k, 3]
+        rst = np.tile(np.array(START[kind]), (len(cell), 1))
+        done = np.zeros(len(cell), bool)
+        for _ in range(iters):
+            N, dN = shape(kind, rst)
+            F = np.einsum("nk,nkc->nc", N, P) - x
+            J = np.einsum("nka,nkc->nca", dN, P)
+            with np.errstate(all="ignore"):
+                det = np.linalg.det(J)
+                sing = ~(np.abs(det) > 1e-300) | ~np.isfinite(det)
+                J[sing] = np.eye(3)
+                delta = np.linalg.solve(J, F[:, :, None])[:, :, 0]
+            delta[sing] = np.nan
+            delta[done] = 0.0
+            rst = rst - delta
+            step = np.abs(delta)
+            if kind == VTK_PYRAMID:  # r and s move a point by (1 - t) times their step
+                step[:, :2] *= np.abs(1.0 - rst[:, 2:3])
+            done |= step.max(axis=1) <= 1e-12
+            if done.all():
+                break
+        rst[~done | ~np.isfinite(rst).all(axis=1)] = np.nan
+        return rst
+
     def locate(self, x):
         """(cell, rsu) of the first cell (in cell order) containing each point; cell -1 if none."""
         x = np.asarray(x, np.float64).reshape(-1, 3)
@@ -112,12 +202,22 @@ class HexField:
                                      & (x[:, None, :] <= self.box_hi[None] + 1e-12), axis=2)
         pi, ci = np.nonzero(cand)  # candidate pairs, cells in increasing order per point
         if len(pi):
-            r = self.invert(ci, x[pi])
-            ok = np.all((r >= -INSIDE_TOL) & (r <= 1 + INSIDE_TOL), axis=1)
+            r = np.full((len(pi), 3), np.nan)
+            kinds = self.types[ci]
+            for kind in np.unique(kinds).tolist():
+                sel = kinds == kind
+                r[sel] = (self.invert(ci[sel], x[pi[sel]]) if kind == VTK_HEXAHEDRON
+                          else self.invert_kind(kind, ci[sel], x[pi[sel]]))
+            ok = np.zeros(len(pi), bool)
+            for kind in np.unique(kinds).tolist():
+                sel = kinds == kind
+                with np.errstate(invalid="ignore"):
+                    ok[sel] = in_domain(kind, r[sel], INSIDE_TOL)
             pi, ci, r = pi[ok], ci[ok], r[ok]
             first = np.unique(pi, return_index=True)[1]  # first containing cell per point
             cell[pi[first]] = ci[first]
-            rsu[pi[first]] = np.clip(r[first], 0.0, 1.0)
+            hexa = self.types[ci[first]] == VTK_HEXAHEDRON
+            rsu[pi[first]] = np.where(hexa[:, None], np.clip(r[first], 0.0, 1.0), r[first])
         return cell, rsu
 
     def sample(self, x, t=None):
@@ -125,8 +225,14 @@ class HexField:
         cell, rsu = self.locate(x)
         ok = cell >= 0
         v = np.zeros((len(cell), 3))
-        if ok.any():
-            v[ok] = np.einsum("nk,nkc->nc", weights(rsu[ok]), self.V[cell[ok]])
+        kinds = np.where(ok, self.types[np.maximum(cell, 0)], -1)
+        for kind in np.unique(kinds[ok]).tolist():
+            sel = kinds == kind
+            if kind == VTK_HEXAHEDRON:
+                v[sel] = np.einsum("nk,nkc->nc", weights(rsu[sel]), self.V[cell[sel]])
+            else:
+                N, _ = shape(kind, rsu[sel])
+                v[sel] = np.einsum("nk,nkc->nc", N, self.Vv[self.cells[cell[sel], :N_VERTS[kind]]])
         return v, ok
 
     def dest(self, x):

@@ -9,7 +9,12 @@
   * general cells (a jittered lattice): a point built from a cell's own parametric
     coordinates is located in that cell at those coordinates, and vertex values are
     reproduced at the vertices;
-  * a plausible slip (a wrong VTK vertex order) is caught by these pins.
+  * a plausible slip (a wrong VTK vertex order) is caught by these pins;
+  * tetrahedra, wedges and pyramids (cubes of a jittered lattice split into conforming cells):
+    every point of the box lies in exactly one cell (a folded map leaves gaps and overlaps, and
+    a wrongly ordered pyramid base or wedge triangle is caught), a tetrahedron's coordinates
+    are its volume ratios, and a pyramid base or wedge side face interpolates as the
+    hexahedron's face does, with vertex values reproduced (a pyramid's apex: near it).
 """
 import numpy as np
 import pytest
@@ -130,3 +135,111 @@ def test_pins_catch_a_wrong_vertex_order(monkeypatch, voxels):
     xs = (rng.uniform(0.1, 0.9, size=(300, 3)) * np.array([5, 4, 6])) @ A.T + np.array([2.0, -1.0, 0.5])
     v, ok = bad.sample(xs)
     assert not (ok.all() and np.abs(v - (xs @ M.T + c)).max() < 1e-5)
+
+
+# ---------------------------------------------------------------- tetrahedra, wedges, pyramids
+def mixedfield(mesh):
+    return ohex.HexField(mesh["vertices"], mesh["values"], mesh["cells"], mesh["lo"], mesh["hi"],
+                         mesh["rank_grid"], mesh["rank_coord"], cell_types=mesh.get("cell_types"))
+
+
+def containing_cells(H, x, tol=1e-9):
+    """How many cells hold each point (every cell tested, no box culling)."""
+    count = np.zeros(len(x), np.int64)
+    for kind in np.unique(H.types).tolist():
+        cells = np.nonzero(H.types == kind)[0]
+        for c in cells:
+            ci = np.full(len(x), c)
+            r = H.invert(ci, x) if kind == ohex.VTK_HEXAHEDRON else H.invert_kind(kind, ci, x)
+            with np.errstate(invalid="ignore"):
+                count += ohex.in_domain(kind, r, tol)
+    return count
+
+
+@pytest.mark.parametrize("kind", ["tetra", "wedge", "pyramid", "hex+pyramid"])
+def test_split_cubes_hold_each_point_once(kind):
+    """Cubes of a jittered lattice split into tetrahedra, wedges or pyramids: every point of the
+    box lies in exactly one cell and a point outside in none.  A folded map (a vertex order the
+    shape functions do not expect) leaves gaps and overlaps, so this pins each kind's shape
+    functions, parametric domain and inversion."""
+    mesh = fg.split_hex_mesh(fg.distorted_hex_mesh(18, (2, 2, 2), jitter=0.2), kind)
+    H = mixedfield(mesh)
+    rng = np.random.default_rng(5)
+    x = rng.uniform(0.02, 1.98, size=(400, 3))
+    np.testing.assert_array_equal(containing_cells(H, x), 1)
+    out = np.array([[-0.1, 1, 1], [1, 2.1, 1], [1, 1, -0.05]])
+    np.testing.assert_array_equal(containing_cells(H, out), 0)
+    cell, _ = H.locate(x)
+    assert (cell >= 0).all()
+
+
+def test_tetra_coordinates_are_volume_ratios():
+    """A tetrahedron's parametric coordinates are its barycentric coordinates: the volume of
+    the tetrahedron with the point in place of a vertex over the whole volume."""
+    mesh = fg.split_hex_mesh(fg.distorted_hex_mesh(19, (2, 1, 1), jitter=0.25), "tetra")
+    H = mixedfield(mesh)
+    rng = np.random.default_rng(6)
+    x = rng.uniform(0.05, 0.95, size=(300, 3)) * np.array([2, 1, 1])
+    cell, rst = H.locate(x)
+    assert (cell >= 0).all()
+    P = H.P[H.cells[cell, :4]]
+
+    def vol(a, b, c, d):
+        return np.linalg.det(np.stack([b - a, c - a, d - a], 1))
+
+    whole = vol(P[:, 0], P[:, 1], P[:, 2], P[:, 3])
+    lam = np.stack([vol(P[:, 0], x, P[:, 2], P[:, 3]), vol(P[:, 0], P[:, 1], x, P[:, 3]),
+                    vol(P[:, 0], P[:, 1], P[:, 2], x)], 1) / whole[:, None]
+    np.testing.assert_allclose(rst, lam, rtol=0, atol=1e-12)
+
+
+def test_split_cells_interpolate_like_the_hexahedron_on_quad_faces():
+    """A pyramid's base and a wedge's side faces are whole faces of the cube: there each
+    interpolates its four vertices bilinearly, as the hexahedron does, so on those faces the
+    split cube samples what the whole cube samples; at the pyramids' apex it samples the centre
+    vertex's value, and every kind reproduces its vertex values at its vertices."""
+    mesh = fg.distorted_hex_mesh(20, (1, 1, 1), jitter=0.0)
+    rng = np.random.default_rng(7)
+    mesh["values"] = rng.normal(size=mesh["values"].shape).astype(np.float32)
+    Hh = mixedfield(mesh)
+    u = rng.uniform(0.05, 0.95, size=(200, 2))
+    # points on the faces x = 0, x = 1, y = 0, y = 1 (wedges and pyramids) and z = 0, z = 1 (pyramids)
+    faces = {}
+    for a in range(3):
+        for side in (0.0, 1.0):
+            p = np.insert(u, a, side, axis=1)
+            p[:, a] = np.clip(p[:, a], 1e-9, 1 - 1e-9)  # just inside the cube
+            faces[(a, side)] = p
+    want = {k: Hh.sample(p)[0] for k, p in faces.items()}
+    Hp = mixedfield(fg.split_hex_mesh(mesh, "pyramid"))
+    Hw = mixedfield(fg.split_hex_mesh(mesh, "wedge"))
+    for k, p in faces.items():
+        np.testing.assert_allclose(Hp.sample(p)[0], want[k], rtol=0, atol=1e-7)
+        if k[0] < 2:
+            np.testing.assert_allclose(Hw.sample(p)[0], want[k], rtol=0, atol=1e-7)
+    pm = fg.split_hex_mesh(mesh, "pyramid")
+    apex = pm["vertices"][-1].astype(np.float64)
+    near = apex + np.array([[1e-9, 2e-9, -1e-9], [1e-7, 0, 0], [0, 0, 1e-6]])
+    v, ok = Hp.sample(near)
+    assert ok.all()
+    np.testing.assert_allclose(v, np.repeat(pm["values"][-1:], 3, 0), rtol=0, atol=1e-5)
+    for kind in ("tetra", "wedge", "pyramid"):
+        m = fg.split_hex_mesh(mesh, kind)
+        H = mixedfield(m)
+        corners = len(mesh["vertices"])  # a pyramid's map is singular at its apex: tested near it above
+        vv, ok = H.sample(np.clip(m["vertices"][:corners].astype(np.float64), 1e-12, 1 - 1e-12))
+        assert ok.all()
+        np.testing.assert_allclose(vv, m["values"][:corners], rtol=0, atol=1e-9)
+
+
+def test_pins_catch_a_folded_pyramid_or_wedge(monkeypatch):
+    """The cover pin fails when the pyramid base or a wedge triangle is read in the wrong order."""
+    mesh = fg.distorted_hex_mesh(18, (2, 2, 2), jitter=0.2)
+    x = np.random.default_rng(5).uniform(0.02, 1.98, size=(200, 3))
+    for kind, swap in (("pyramid", [0, 1, 3, 2, 4]), ("wedge", [0, 1, 2, 3, 5, 4])):
+        m = fg.split_hex_mesh(mesh, kind)
+        cells = m["cells"].copy()
+        k = len(swap)
+        cells[:, :k] = cells[:, swap]
+        H = mixedfield(dict(m, cells=cells))
+        assert not (containing_cells(H, x) == 1).all(), kind
