@@ -142,37 +142,53 @@ int streami_field_create(const streami_block_desc* blocks, int32_t n_blocks, int
 
 int streami_field_destroy(streami_field f);
 
-/* An unstructured field of hexahedral cells (Sec. 3.3: the paper's second
- * field type, located by a bounding volume hierarchy and point containment;
- * Sec. 5 converts every voxel of a structured data set to a hexahedron). */
+/* An unstructured field (Sec. 3.3: the paper's second field type, of
+ * tetrahedra, pyramids, prisms and hexahedra, located by a bounding volume
+ * hierarchy and point containment; Sec. 5 converts every voxel of a structured
+ * data set to a hexahedron). */
+#define STREAMI_CELL_TETRA 10      /* VTK cell type codes */
+#define STREAMI_CELL_HEXAHEDRON 12
+#define STREAMI_CELL_WEDGE 13
+#define STREAMI_CELL_PYRAMID 14
 typedef struct {
   int64_t n_vertices;
   const float* vertices;   /* [n_vertices][3] world positions */
   const float* values;     /* [n_vertices][3] FP32 vector values at the vertices */
   int64_t n_cells;         /* 1 .. 2^28 - 1 */
-  const int32_t* cells;    /* [n_cells][8] vertex indices in VTK hexahedron order:
-                              (0,0,0) (1,0,0) (1,1,0) (0,1,0) (0,0,1) (1,0,1) (1,1,1) (0,1,1) */
+  const int32_t* cells;    /* [n_cells][8]: each row the cell's vertex indices in VTK order, entries
+                              after the cell's vertices ignored.  Hexahedron (0,0,0) (1,0,0) (1,1,0)
+                              (0,1,0) (0,0,1) (1,0,1) (1,1,1) (0,1,1); tetra 4 vertices; wedge the
+                              bottom triangle then the top one (vertex 3 above 0, 4 above 1, 5 above
+                              2); pyramid the base quad in cyclic order then the apex */
   double bounds_lo[3];     /* owned macrocell, half-open [lo, hi) (Sec. 3.1.1) */
   double bounds_hi[3];
   int32_t rank_grid[3];    /* macrocell grid for destinationID() */
   int32_t rank_coord[3];
-  int32_t inputs_on_device;/* 1: the three arrays are device pointers, 0: host memory */
+  int32_t inputs_on_device;/* 1: the arrays are device pointers, 0: host memory */
+  const uint8_t* cell_types; /* [n_cells] STREAMI_CELL_* codes, or NULL: every cell a hexahedron */
 } streami_hex_desc;
 
 /*
- * Create a handle over one hexahedral field.  sample(x) is defined where a
- * cell holds x: the cell's trilinear map X(r,s,u) (corners as listed above)
- * is inverted by Newton's method in FP32 and x is accepted when (r,s,u) lies
- * in [-1e-4, 1 + 1e-4]^3 (slack for points on shared faces); the value is the
- * same trilinear interpolation of the vertex values.  The library builds, on
- * the host, a depth-first BVH over the cells' boxes and one 192-byte record per
- * cell (both maps in monomial form) and keeps them on the device; the caller
- * keeps ownership of the arrays (read during the call only).  The handle takes
- * the same seeding, advection (PLAIN mode, steady), fetch, outbox, forwarding
- * and OBJ calls as a structured one; streami_field_info reports
- * STREAMI_LAYOUT_HEX.  Errors: E_ARG (NULL arrays, counts out of range, a cell
- * index outside the vertices, a non-finite vertex, bounds with lo >= hi, a
- * rank grid < 1 or coordinate outside it), E_NOMEM, E_DEVICE.
+ * Create a handle over one unstructured field.  sample(x) is defined where a
+ * cell holds x.  Each cell maps parametric coordinates (r,s,u) to space with
+ * its kind's VTK linear shape functions: hexahedron trilinear over [0,1]^3;
+ * tetra 1-r-s-u, r, s, u over the simplex r,s,u >= 0, r+s+u <= 1; wedge
+ * (1-r-s)(1-u), r(1-u), s(1-u), (1-r-s)u, ru, su over r,s >= 0, r+s <= 1,
+ * 0 <= u <= 1; pyramid (1-r)(1-s)(1-u), r(1-s)(1-u), rs(1-u), (1-r)s(1-u), u
+ * over [0,1]^3.  The map is inverted by Newton's method in FP32 and x is
+ * accepted when (r,s,u) lies in the domain widened by 1e-4 (slack for points on
+ * shared faces); the value is the same combination of the vertex values.  A
+ * pyramid's map is singular at its apex: points within about 1e-5 of a cell
+ * size of it may be found in no cell.  The library builds, on the host, a
+ * depth-first BVH over the cells' boxes and one 192-byte record per cell (both
+ * maps in monomial form) and keeps them on the device; the caller keeps
+ * ownership of the arrays (read during the call only).  The handle takes the
+ * same seeding, advection (PLAIN mode, steady), fetch, outbox, forwarding and
+ * OBJ calls as a structured one; streami_field_info reports
+ * STREAMI_LAYOUT_HEX.  Errors: E_ARG (NULL arrays, counts out of range, an
+ * unknown cell type, a cell index outside the vertices, a non-finite vertex,
+ * bounds with lo >= hi, a rank grid < 1 or coordinate outside it), E_NOMEM,
+ * E_DEVICE.
  */
 int streami_field_create_hex(const streami_hex_desc* desc, void* hip_stream, streami_field* out);
 

@@ -19,7 +19,11 @@ voxel of a structured data set to a hexahedron (Sec. 5).  Definitions, written o
       pyramid     (1-r)(1-s)(1-t), r(1-s)(1-t), r s (1-t), (1-r) s (1-t), t;  domain [0,1]^3
                   (the base quad in order, the apex last);
   * x lies in a cell iff X(r,s,t) = sum N_i X_i = x has a solution in the cell's domain (found
-    by Newton's method to FP64 convergence; a tetrahedron's map is affine);
+    by Newton's method to FP64 convergence; a tetrahedron's map is affine).  A non-affine map
+    can have a second root outside the domain, which Newton from the domain's centre may
+    reach when x lies near a vertex of a warped cell: a start that does not end inside the
+    domain is retried once from the parametric point of the cell vertex nearest to x, moved a
+    fifth of the way to the centre;
   * sample(x) = sum N_i V_i at that solution in the first such cell in cell order (on a mesh
     whose neighbouring cells interpolate alike on shared faces every containing cell gives
     the same value); undefined (False) when no cell contains x (Sec. 3.1.1: sample() fails);
@@ -41,7 +45,14 @@ INSIDE_TOL = 1e-12  # parametric slack for points on a cell face
 # VTK cell type codes and vertex counts
 VTK_TETRA, VTK_HEXAHEDRON, VTK_WEDGE, VTK_PYRAMID = 10, 12, 13, 14
 N_VERTS = {VTK_TETRA: 4, VTK_HEXAHEDRON: 8, VTK_WEDGE: 6, VTK_PYRAMID: 5}
-START = {VTK_TETRA: (0.25, 0.25, 0.25), VTK_WEDGE: (1 / 3, 1 / 3, 0.5), VTK_PYRAMID: (0.5, 0.5, 0.5)}
+START = {VTK_TETRA: (0.25, 0.25, 0.25), VTK_WEDGE: (1 / 3, 1 / 3, 0.5), VTK_PYRAMID: (0.5, 0.5, 0.5),
+         VTK_HEXAHEDRON: (0.5, 0.5, 0.5)}
+# parametric points of each kind's vertices (VTK order; a pyramid's apex at r = s = 1/2)
+VERTEX_PARAM = {VTK_TETRA: [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)],
+                VTK_WEDGE: [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 0, 1), (0, 1, 1)],
+                VTK_PYRAMID: [(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0), (0.5, 0.5, 1)],
+                VTK_HEXAHEDRON: [(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0), (0, 0, 1), (1, 0, 1), (1, 1, 1),
+                                 (0, 1, 1)]}
 
 
 def shape(kind, rst):
@@ -140,11 +151,18 @@ class HexField:
         self.periodic = False
 
     # ------------------------------------------------------------ location
-    def invert(self, cell, x, iters=60):
-        """Parametric coordinates of x in each given cell (Newton from the centre); NaN rows
-        where the iteration does not converge."""
+    def retry_start(self, kind, cell, x):
+        """The second Newton start: the parametric point of the cell vertex nearest to x, a fifth
+        of the way towards the domain's centre."""
+        P = self.P[self.cells[cell, :N_VERTS[kind]]]
+        near = np.argmin(((P - x[:, None, :]) ** 2).sum(axis=2), axis=1)
+        return 0.8 * np.asarray(VERTEX_PARAM[kind], np.float64)[near] + 0.2 * np.asarray(START[kind])
+
+    def invert(self, cell, x, iters=60, start=None):
+        """Parametric coordinates of x in each given hexahedron (Newton from the centre or from
+        `start`); NaN rows where the iteration does not converge."""
         X = self.X[cell]
-        rsu = np.full((len(cell), 3), 0.5)
+        rsu = np.full((len(cell), 3), 0.5) if start is None else np.array(start, np.float64)
         done = np.zeros(len(cell), bool)
         for _ in range(iters):
             F = np.einsum("nk,nkc->nc", weights(rsu), X) - x
@@ -164,11 +182,12 @@ class HexField:
         rsu[~done | ~np.isfinite(rsu).all(axis=1)] = np.nan
         return rsu
 
-    def invert_kind(self, kind, cell, x, iters=60):
+    def invert_kind(self, kind, cell, x, iters=60, start=None):
         """Parametric coordinates of x in tetra, wedge or pyramid cells of one kind (Newton from
-        the domain's centre; one step for a tetrahedron); NaN rows where it does not converge."""
+        the domain's centre or from `start`; one step for a tetrahedron); NaN rows where it does
+        not converge."""
         P = self.P[self.cells[cell, :N_VERTS[kind]]]  # [m, k, 3]
-        rst = np.tile(np.array(START[kind]), (len(cell), 1))
+        rst = np.tile(np.array(START[kind]), (len(cell), 1)) if start is None else np.array(start, np.float64)
         done = np.zeros(len(cell), bool)
         for _ in range(iters):
             N, dN = shape(kind, rst)
@@ -213,6 +232,17 @@ class HexField:
                 sel = kinds == kind
                 with np.errstate(invalid="ignore"):
                     ok[sel] = in_domain(kind, r[sel], INSIDE_TOL)
+                if kind == VTK_TETRA:
+                    continue
+                again = np.nonzero(sel & ~ok)[0]  # the second start
+                if len(again):
+                    st = self.retry_start(kind, ci[again], x[pi[again]])
+                    r2 = (self.invert(ci[again], x[pi[again]], start=st) if kind == VTK_HEXAHEDRON
+                          else self.invert_kind(kind, ci[again], x[pi[again]], start=st))
+                    with np.errstate(invalid="ignore"):
+                        ok2 = in_domain(kind, r2, INSIDE_TOL)
+                    r[again[ok2]] = r2[ok2]
+                    ok[again[ok2]] = True
             pi, ci, r = pi[ok], ci[ok], r[ok]
             first = np.unique(pi, return_index=True)[1]  # first containing cell per point
             cell[pi[first]] = ci[first]

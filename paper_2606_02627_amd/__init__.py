@@ -50,7 +50,8 @@ class HexDesc(ctypes.Structure):
     _fields_ = [("n_vertices", ctypes.c_int64), ("vertices", ctypes.c_void_p), ("values", ctypes.c_void_p),
                 ("n_cells", ctypes.c_int64), ("cells", ctypes.c_void_p), ("bounds_lo", ctypes.c_double * 3),
                 ("bounds_hi", ctypes.c_double * 3), ("rank_grid", ctypes.c_int32 * 3),
-                ("rank_coord", ctypes.c_int32 * 3), ("inputs_on_device", ctypes.c_int32)]
+                ("rank_coord", ctypes.c_int32 * 3), ("inputs_on_device", ctypes.c_int32),
+                ("cell_types", ctypes.c_void_p)]
 
 
 class FieldOpts(ctypes.Structure):
@@ -213,18 +214,23 @@ def streami_field_create(descs, dtype, layout=LAYOUT_AUTO, stream=None):
 
 
 def streami_field_create_hex(mesh, stream=None):
-    """Handle over a hexahedral field: mesh = dict(vertices [nv,3] f32, values [nv,3] f32, cells
-    [nc,8] int32 (VTK order), lo, hi, rank_grid, rank_coord), all host or all device arrays."""
+    """Handle over an unstructured field: mesh = dict(vertices [nv,3] f32, values [nv,3] f32, cells
+    [nc,8] int32 (VTK order), optional cell_types [nc] uint8 (VTK codes; absent: hexahedra), lo,
+    hi, rank_grid, rank_coord), all host or all device arrays."""
     arrs = [mesh["vertices"], mesh["values"], mesh["cells"]]
+    types = mesh.get("cell_types")
+    if types is not None:
+        arrs.append(types)
     if isinstance(arrs[0], np.ndarray):
-        arrs = [np.ascontiguousarray(arrs[0], np.float32), np.ascontiguousarray(arrs[1], np.float32),
-                np.ascontiguousarray(arrs[2], np.int32)]
+        conv = [np.float32, np.float32, np.int32, np.uint8]
+        arrs = [np.ascontiguousarray(a, t) for a, t in zip(arrs, conv)]
     ptrs = [_addr(a) for a in arrs]
     if len({d for _, d in ptrs}) != 1:
-        raise ValueError("vertices, values and cells must all be host or all device arrays")
+        raise ValueError("vertices, values, cells and cell_types must all be host or all device arrays")
     d = HexDesc(n_vertices=int(arrs[0].shape[0]), n_cells=int(arrs[2].shape[0]),
                 inputs_on_device=int(ptrs[0][1]))
-    d.vertices, d.values, d.cells = (p.value for p, _ in ptrs)
+    d.vertices, d.values, d.cells = (p.value for p, _ in ptrs[:3])
+    d.cell_types = ptrs[3][0].value if types is not None else None
     d.bounds_lo[:] = [float(v) for v in mesh["lo"]]
     d.bounds_hi[:] = [float(v) for v in mesh["hi"]]
     d.rank_grid[:] = [int(v) for v in mesh.get("rank_grid", (1, 1, 1))]

@@ -44,8 +44,9 @@ int launch_work_order(const float4* pos, const int4* meta, const int4* meta2, co
                       unsigned* hist, unsigned* cursor, int* order, unsigned* n_work, hipStream_t st);
 int launch_fill_u64(unsigned long long* p, long long n, unsigned long long v, hipStream_t st);
 int launch_seed_bound(const SeedJobs& J, long long total, unsigned long long* out, hipStream_t st);
-std::string build_hex_blob(const float* V, long long nv, const float* val, const int* cells, long long nc, float tol,
-                           std::vector<float>& blob, unsigned& n_nodes);
+std::string build_hex_blob(const float* V, long long nv, const float* val, const int* cells,
+                           const unsigned char* types, long long nc, float tol, std::vector<float>& blob,
+                           unsigned& n_nodes);
 int launch_seed_shape(const double o[3], const double u[3], const double v[3], long long nu, long long nv, float* out,
                       hipStream_t st);
 int launch_gather_meta(const long long* idx, long long count, const int4* meta, const int4* meta2,
@@ -646,8 +647,10 @@ int streami_field_create_hex(const streami_hex_desc* d, void* hip_stream, stream
   const long long nv = d->n_vertices, nc = d->n_cells;
   std::vector<float> hv, hval;
   std::vector<int> hc;
+  std::vector<unsigned char> ht;
   const float *V = d->vertices, *val = d->values;
   const int* C = d->cells;
+  const unsigned char* T = d->cell_types;
   try {
     if (d->inputs_on_device) {
       hv.resize(3 * (size_t)nv);
@@ -657,13 +660,19 @@ int streami_field_create_hex(const streami_hex_desc* d, void* hip_stream, stream
           hipMemcpy(hval.data(), d->values, hval.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
           hipMemcpy(hc.data(), d->cells, hc.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
         return fail(STREAMI_E_DEVICE, "copy of the mesh to the host failed");
+      if (T) {
+        ht.resize((size_t)nc);
+        if (hipMemcpy(ht.data(), d->cell_types, ht.size(), hipMemcpyDeviceToHost) != hipSuccess)
+          return fail(STREAMI_E_DEVICE, "copy of the cell types to the host failed");
+        T = ht.data();
+      }
       V = hv.data();
       val = hval.data();
       C = hc.data();
     }
     std::vector<float> blob;
     unsigned n_nodes = 0;
-    const std::string err = build_hex_blob(V, nv, val, C, nc, 1e-4f, blob, n_nodes);
+    const std::string err = build_hex_blob(V, nv, val, C, T, nc, 1e-4f, blob, n_nodes);
     if (!err.empty()) return fail(STREAMI_E_ARG, "%s", err.c_str());
     streami_field_s* f = new (std::nothrow) streami_field_s();
     if (!f) return fail(STREAMI_E_NOMEM, "host allocation failed");

@@ -1,6 +1,16 @@
-// Unstructured hexahedral field: point location and interpolation (Sec. 3.3:
-// an unstructured grid located by a bounding volume hierarchy and point
-// containment tests; Sec. 5 converts every voxel to a hexahedron).
+// Unstructured field of hexahedra, tetrahedra, wedges and pyramids: point
+// location and interpolation (Sec. 3.3: an unstructured grid located by a
+// bounding volume hierarchy and point containment tests; Sec. 5 converts every
+// voxel to a hexahedron).
+//
+// Every kind of cell maps parametric coordinates (r, s, u) to space with a
+// polynomial in the monomials 1, r, s, rs, u, ru, su, rsu (its VTK linear
+// shape functions written out): a tetrahedron's map is affine and its domain
+// the simplex r, s, u >= 0, r + s + u <= 1; a wedge's has no rs and rsu terms
+// and its domain is the triangle r, s >= 0, r + s <= 1 times 0 <= u <= 1; a
+// pyramid's is the hexahedron's with the top face collapsed into the apex
+// (domain [0,1]^3, singular at u = 1); a hexahedron's is trilinear.  The value
+// map uses the same polynomial of the vertex values.
 //
 // Device blob of one field, addressed in 16-byte units from its start:
 //   HexHeader (2 units) | BVH nodes (2 units each) | cell records (12 units each)
@@ -28,81 +38,151 @@ struct alignas(16) HexHeader {
   unsigned node_off;   // 16-byte units from the blob start
   unsigned cell_off;
   float tol;           // parametric slack of the containment test
-  unsigned neigh_off;  // face neighbours: 2 units per record, record indices of the cells across
-                       // faces r=0, r=1, s=0, s=1, u=0, u=1 (-1: none), then 2 unused
+  unsigned neigh_off;  // face neighbours: 2 units per record, 8 ints: the cells across the
+                       // record's faces (hex_exit_face order; -1: none), each as
+                       // (kind << 28) | record, then the record's own kind, then unused
   unsigned pad[2];
 };
 static_assert(sizeof(HexHeader) == 32, "hex header is two 16-byte units");
 
 constexpr int HEX_REC_UNITS = 12;  // 16-byte units per cell record
 constexpr int HEX_LEAF_MAX = 8;    // cells per BVH leaf
+// kinds of cell (the record's own kind sits in slot 6 of its neighbour entry)
+enum HexKind { HK_HEX = 0, HK_TETRA = 1, HK_WEDGE = 2, HK_PYRAMID = 3 };
+constexpr int HEX_KIND_SHIFT = 28;
+constexpr int HEX_REC_MASK = (1 << HEX_KIND_SHIFT) - 1;
 
-// Containment of x in one cell: Newton's method on the position map from the
-// cell centre, in FP32 relative to the first corner.  Returns 1 when it
-// converges inside [-tol, 1 + tol]^3, 0 when it converges outside (rsu then
-// locates x beyond the cell's faces), -1 when it does not converge.
-__device__ __forceinline__ int hex_contains(const float4* rec, float3 x, float tol, float3& rsu) {
+// Containment of x in one cell: Newton's method on the position map, in FP32
+// relative to the first vertex, from the centre of the kind's domain (a
+// pyramid's r and s steps count times 1 - u: near the apex they move the point
+// that much less).  A non-affine map can have a second root outside the
+// domain, which the iteration may reach when x lies near a vertex of a warped
+// cell: a first start that does not end inside is retried once from the
+// parametric point of the vertex nearest to x, a fifth of the way to the
+// centre, and the last start decides.  Returns 1 when it converges inside the
+// domain widened by tol, 0 when it converges outside (rsu then locates x beyond
+// the cell's faces), -1 when it does not converge.
+__device__ __forceinline__ int hex_contains(const float4* rec, float3 x, float tol, int kind, float3& rsu) {
   const float4 q0 = rec[0], q1 = rec[1], q2 = rec[2], q3 = rec[3], q4 = rec[4], q5 = rec[5];
   // c[k][a] = coefficient k (1, r, s, rs, u, ru, su, rsu), component a
   const float c[8][3] = {{q0.x, q0.y, q0.z}, {q0.w, q1.x, q1.y}, {q1.z, q1.w, q2.x}, {q2.y, q2.z, q2.w},
                          {q3.x, q3.y, q3.z}, {q3.w, q4.x, q4.y}, {q4.z, q4.w, q5.x}, {q5.y, q5.z, q5.w}};
   const float d[3] = {x.x - c[0][0], x.y - c[0][1], x.z - c[0][2]};
-  // an affine cell (a parallelepiped: no rs, ru, su, rsu terms, e.g. a voxel) has a constant
-  // Jacobian, so the first Newton step is the solution
+  // an affine cell (no rs, ru, su, rsu terms: a tetrahedron, a parallelepiped such as a voxel)
+  // has a constant Jacobian and one root, so the first Newton step is the solution
   bool affine = true;
 #pragma unroll
   for (int a = 0; a < 3; ++a) affine = affine && c[3][a] == 0.0f && c[5][a] == 0.0f && c[6][a] == 0.0f && c[7][a] == 0.0f;
-  float r = 0.5f, s = 0.5f, u = 0.5f;
-  bool conv = false;
+  const float cr = kind == HK_TETRA ? 0.25f : kind == HK_WEDGE ? 1.0f / 3.0f : 0.5f;
+  const float cu = kind == HK_TETRA ? 0.25f : 0.5f;
+  const float lo = -tol, hi = 1.0f + tol;
+  float r = cr, s = cr, u = cu;
+  int result = -1;
 #pragma unroll 1
-  for (int it = 0; it < 8; ++it) {
-    const float rs = r * s, ru = r * u, su = s * u, rsu3 = rs * u;
-    float F[3], Jr[3], Js[3], Ju[3];
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    if (attempt == 1) {
+      if (result > 0 || affine) break;
+      // the vertex nearest to x: X(vertex) - X(vertex 0) against d
+      const int nv = kind == HK_HEX ? 8 : kind == HK_WEDGE ? 6 : 5;
+      float best = INFINITY;
+#pragma unroll 1
+      for (int i = 0; i < nv; ++i) {
+        float vr, vs, vu;
+        if (kind == HK_HEX) {
+          vr = (float)(i & 1); vs = (float)((i >> 1) & 1); vu = (float)(i >> 2);
+        } else if (kind == HK_WEDGE) {
+          vr = (float)(i % 3 == 1); vs = (float)(i % 3 == 2); vu = (float)(i / 3);
+        } else {
+          vr = i == 4 ? 0.5f : (float)(i == 1 || i == 2); vs = i == 4 ? 0.5f : (float)(i >= 2); vu = (float)(i == 4);
+        }
+        float dist = 0.0f;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      F[a] = fmaf(c[1][a], r, fmaf(c[2][a], s, fmaf(c[3][a], rs, fmaf(c[4][a], u, fmaf(c[5][a], ru,
-                  fmaf(c[6][a], su, fmaf(c[7][a], rsu3, -d[a])))))));
-      Jr[a] = fmaf(c[3][a], s, fmaf(c[5][a], u, fmaf(c[7][a], su, c[1][a])));
-      Js[a] = fmaf(c[3][a], r, fmaf(c[6][a], u, fmaf(c[7][a], ru, c[2][a])));
-      Ju[a] = fmaf(c[5][a], r, fmaf(c[6][a], s, fmaf(c[7][a], rs, c[4][a])));
+        for (int a = 0; a < 3; ++a) {
+          const float e = fmaf(c[1][a], vr, fmaf(c[2][a], vs, fmaf(c[3][a], vr * vs, fmaf(c[4][a], vu,
+                          fmaf(c[5][a], vr * vu, fmaf(c[6][a], vs * vu, fmaf(c[7][a], vr * vs * vu, -d[a])))))));
+          dist = fmaf(e, e, dist);
+        }
+        if (dist < best) {
+          best = dist;
+          r = fmaf(0.8f, vr, 0.2f * cr);
+          s = fmaf(0.8f, vs, 0.2f * cr);
+          u = fmaf(0.8f, vu, 0.2f * cu);
+        }
+      }
     }
-    // Cramer's rule for [Jr Js Ju] delta = F
-    const float x0 = Js[1] * Ju[2] - Js[2] * Ju[1], x1 = Js[2] * Ju[0] - Js[0] * Ju[2],
-                x2 = Js[0] * Ju[1] - Js[1] * Ju[0];  // Js x Ju
-    const float det = Jr[0] * x0 + Jr[1] * x1 + Jr[2] * x2;
-    if (!(fabsf(det) > 0.0f)) break;  // degenerate cell (or NaN): contains nothing
-    const float inv = 1.0f / det;
-    const float y0 = F[1] * Ju[2] - F[2] * Ju[1], y1 = F[2] * Ju[0] - F[0] * Ju[2],
-                y2 = F[0] * Ju[1] - F[1] * Ju[0];  // F x Ju
-    const float z0 = Js[1] * F[2] - Js[2] * F[1], z1 = Js[2] * F[0] - Js[0] * F[2],
-                z2 = Js[0] * F[1] - Js[1] * F[0];  // Js x F
-    const float dr = (F[0] * x0 + F[1] * x1 + F[2] * x2) * inv;
-    const float ds = (Jr[0] * y0 + Jr[1] * y1 + Jr[2] * y2) * inv;
-    const float du = (Jr[0] * z0 + Jr[1] * z1 + Jr[2] * z2) * inv;
-    r -= dr;
-    s -= ds;
-    u -= du;
-    if (affine || fmaxf(fabsf(dr), fmaxf(fabsf(ds), fabsf(du))) <= 1e-5f) {
-      conv = true;
-      break;
+    bool conv = false;
+#pragma unroll 1
+    for (int it = 0; it < 8; ++it) {
+      const float rs = r * s, ru = r * u, su = s * u, rsu3 = rs * u;
+      float F[3], Jr[3], Js[3], Ju[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        F[a] = fmaf(c[1][a], r, fmaf(c[2][a], s, fmaf(c[3][a], rs, fmaf(c[4][a], u, fmaf(c[5][a], ru,
+                    fmaf(c[6][a], su, fmaf(c[7][a], rsu3, -d[a])))))));
+        Jr[a] = fmaf(c[3][a], s, fmaf(c[5][a], u, fmaf(c[7][a], su, c[1][a])));
+        Js[a] = fmaf(c[3][a], r, fmaf(c[6][a], u, fmaf(c[7][a], ru, c[2][a])));
+        Ju[a] = fmaf(c[5][a], r, fmaf(c[6][a], s, fmaf(c[7][a], rs, c[4][a])));
+      }
+      // Cramer's rule for [Jr Js Ju] delta = F
+      const float x0 = Js[1] * Ju[2] - Js[2] * Ju[1], x1 = Js[2] * Ju[0] - Js[0] * Ju[2],
+                  x2 = Js[0] * Ju[1] - Js[1] * Ju[0];  // Js x Ju
+      const float det = Jr[0] * x0 + Jr[1] * x1 + Jr[2] * x2;
+      if (!(fabsf(det) > 0.0f)) break;  // degenerate cell (or NaN): contains nothing
+      const float inv = 1.0f / det;
+      const float y0 = F[1] * Ju[2] - F[2] * Ju[1], y1 = F[2] * Ju[0] - F[0] * Ju[2],
+                  y2 = F[0] * Ju[1] - F[1] * Ju[0];  // F x Ju
+      const float z0 = Js[1] * F[2] - Js[2] * F[1], z1 = Js[2] * F[0] - Js[0] * F[2],
+                  z2 = Js[0] * F[1] - Js[1] * F[0];  // Js x F
+      const float dr = (F[0] * x0 + F[1] * x1 + F[2] * x2) * inv;
+      const float ds = (Jr[0] * y0 + Jr[1] * y1 + Jr[2] * y2) * inv;
+      const float du = (Jr[0] * z0 + Jr[1] * z1 + Jr[2] * z2) * inv;
+      r -= dr;
+      s -= ds;
+      u -= du;
+      const float w = kind == HK_PYRAMID ? fabsf(1.0f - u) : 1.0f;
+      if (affine || fmaxf(w * fmaxf(fabsf(dr), fabsf(ds)), fabsf(du)) <= 1e-5f) {
+        conv = true;
+        break;
+      }
     }
+    if (!conv) {
+      result = -1;
+      continue;
+    }
+    bool in = r >= lo && s >= lo && u >= lo;
+    if (kind == HK_TETRA) in = in && r + s + u <= hi;
+    else if (kind == HK_WEDGE) in = in && r + s <= hi && u <= hi;
+    else in = in && r <= hi && s <= hi && u <= hi;
+    result = in ? 1 : 0;
   }
   rsu = make_float3(r, s, u);
-  const float lo = -tol, hi = 1.0f + tol;
-  if (!conv) return -1;
-  return (r >= lo && r <= hi && s >= lo && s <= hi && u >= lo && u <= hi) ? 1 : 0;
+  return result;
 }
 
-// The face (0: r=0, 1: r=1, 2: s=0, 3: s=1, 4: u=0, 5: u=1) beyond which the
-// parametric point lies farthest.
-__device__ __forceinline__ int hex_exit_face(float3 q) {
+// The face beyond which the parametric point lies farthest, numbered per kind:
+//   hexahedron r=0, r=1, s=0, s=1, u=0, u=1;  tetrahedron r=0, s=0, u=0, r+s+u=1;
+//   wedge r=0, s=0, r+s=1, u=0, u=1;  pyramid r=0, r=1, s=0, s=1, u=0.
+__device__ __forceinline__ int hex_exit_face(int kind, float3 q) {
   float w = -q.x;
   int f = 0;
+  if (kind == HK_TETRA) {
+    if (-q.y > w) { w = -q.y; f = 1; }
+    if (-q.z > w) { w = -q.z; f = 2; }
+    if (q.x + q.y + q.z - 1.0f > w) { f = 3; }
+    return f;
+  }
+  if (kind == HK_WEDGE) {
+    if (-q.y > w) { w = -q.y; f = 1; }
+    if (q.x + q.y - 1.0f > w) { w = q.x + q.y - 1.0f; f = 2; }
+    if (-q.z > w) { w = -q.z; f = 3; }
+    if (q.z - 1.0f > w) { f = 4; }
+    return f;
+  }
   if (q.x - 1.0f > w) { w = q.x - 1.0f; f = 1; }
   if (-q.y > w) { w = -q.y; f = 2; }
   if (q.y - 1.0f > w) { w = q.y - 1.0f; f = 3; }
   if (-q.z > w) { w = -q.z; f = 4; }
-  if (q.z - 1.0f > w) { f = 5; }
+  if (kind == HK_HEX && q.z - 1.0f > w) { f = 5; }
   return f;
 }
 
@@ -123,12 +203,13 @@ __device__ __forceinline__ float3 hex_value(const float4* rec, float3 rsu) {
   return make_float3(v[0], v[1], v[2]);
 }
 
-// sample() of a hexahedral field: the cell a lane sampled last is tested
+// sample() of an unstructured field: the cell a lane sampled last is tested
 // first, then up to HEX_HOPS neighbours across the faces the point lies beyond;
 // otherwise the BVH walk finds the first leaf cell (in preorder) holding x.
 // False where no cell holds x (Sec. 3.1.1).
 struct HexSampler {
   int cell = -1;
+  int kind = HK_HEX;     // the kind of `cell`
   unsigned gathers = 0;  // BVH walks
   __device__ __forceinline__ void reset() { cell = -1; }
   __device__ __forceinline__ bool sample(const BlockDev&, const char* base, float3 x, float, float3& v, bool = false) {
@@ -137,19 +218,23 @@ struct HexSampler {
     const float4* recs = blob + H.cell_off;
     float3 rsu;
     int found = -1;
+    int fkind = kind;
     if (cell >= 0) {
-      int c = cell;
+      int c = cell, k = kind;
 #pragma unroll 1
       for (int hop = 0; hop <= HEX_HOPS; ++hop) {
-        const int st = hex_contains(recs + (size_t)HEX_REC_UNITS * c, x, H.tol, rsu);
+        const int st = hex_contains(recs + (size_t)HEX_REC_UNITS * c, x, H.tol, k, rsu);
         if (st > 0) {
           found = c;
+          fkind = k;
           break;
         }
         if (st < 0 || hop == HEX_HOPS) break;
         const int* nb = reinterpret_cast<const int*>(blob + H.neigh_off + 2 * (size_t)c);
-        c = nb[hex_exit_face(rsu)];
-        if (c < 0) break;
+        const int e = nb[hex_exit_face(k, rsu)];
+        if (e < 0) break;
+        c = e & HEX_REC_MASK;
+        k = e >> HEX_KIND_SHIFT;
       }
     }
     if (found < 0) {
@@ -167,11 +252,15 @@ struct HexSampler {
           ++i;
         } else {
           const int first = leaf >> 3, cnt = (leaf & 7) + 1;
-          for (int k = 0; k < cnt; ++k)
-            if (hex_contains(recs + (size_t)HEX_REC_UNITS * (first + k), x, H.tol, rsu) > 0) {
-              found = first + k;
+          for (int k = 0; k < cnt; ++k) {
+            const int c = first + k;
+            const int ck = reinterpret_cast<const int*>(blob + H.neigh_off + 2 * (size_t)c)[6];
+            if (hex_contains(recs + (size_t)HEX_REC_UNITS * c, x, H.tol, ck, rsu) > 0) {
+              found = c;
+              fkind = ck;
               break;
             }
+          }
           if (found >= 0) break;
           i = skip;
         }
@@ -182,6 +271,7 @@ struct HexSampler {
       }
     }
     cell = found;
+    kind = fkind;
     v = hex_value(recs + (size_t)HEX_REC_UNITS * cell, rsu);
     return true;
   }

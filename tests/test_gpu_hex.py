@@ -1,8 +1,9 @@
-"""GPU tests of the hexahedral (unstructured) field: streami_field_create_hex.
+"""GPU tests of the unstructured field: streami_field_create_hex.
 
 Voxel hexahedra (every cell of a structured grid) sample what the structured grid samples
 (pinned on the CPU for the two oracles), so their lines are checked against the structured
-FP64 oracle, which runs fast; general (jittered) hexahedra against the hexahedral oracle.
+FP64 oracle, which runs fast; general (jittered) hexahedra, and tetrahedra, wedges and
+pyramids (jittered cubes split into conforming cells), against the unstructured oracle.
 Per-step rule at every vertex; step counts and codes from a late restart; exits, halo misses
 and destinations from the outbox."""
 import sys
@@ -33,7 +34,7 @@ def S():
 
 def hex_oracle(mesh):
     return ohex.HexField(mesh["vertices"], mesh["values"], mesh["cells"], mesh["lo"], mesh["hi"],
-                         mesh["rank_grid"], mesh["rank_coord"])
+                         mesh["rank_grid"], mesh["rank_coord"], cell_types=mesh.get("cell_types"))
 
 
 def test_voxel_hexahedra_follow_the_structured_field(S):
@@ -101,6 +102,44 @@ def test_general_hexahedra_against_the_hex_oracle(S):
     g.close()
 
 
+@pytest.mark.parametrize("kind", ["tetra", "wedge", "pyramid", "hex+pyramid"])
+def test_split_cells_against_the_unstructured_oracle(S, kind):
+    """Tetrahedra, wedges, pyramids and a hexahedron/pyramid checkerboard (6 x 6 x 5 jittered
+    cubes split into conforming cells, owned bounds one cube inside): per-step rule at every
+    vertex, late-restart codes and steps, exits with their destinations; neighbour hops and the
+    BVH walk both run (a walk per step is far rarer than a cell change).  A fifth of the seeds
+    start within 0.06 of a lattice vertex, where Newton from a warped cell's centre can end at
+    the map's second root: no stage point inside the mesh goes unfound (no halo miss)."""
+    note("unstructured:", kind)
+    mesh = fg.split_hex_mesh(fg.distorted_hex_mesh(21, (6, 6, 5), jitter=0.2, sub=len(kind)), kind)
+    mesh.update(lo=(1.0, 1.0, 1.0), hi=(5.0, 5.0, 4.0), rank_grid=(3, 3, 3), rank_coord=(1, 1, 1))
+    H = hex_oracle(mesh)
+    k, j, i = np.meshgrid(np.arange(2, 4), np.arange(2, 5), np.arange(2, 5), indexing="ij")
+    near = np.repeat(mesh["vertices"][(i + 7 * (j + 7 * k)).ravel()], 3, 0).astype(np.float64)
+    near += np.random.default_rng(len(kind)).uniform(-0.06, 0.06, near.shape)
+    seeds = np.concatenate([fg.uniform_seeds(21, 196, (1, 1, 1), (5, 5, 4), sub=len(kind)),
+                            near.astype(np.float32)])
+    assert len(seeds) == 250
+    f = S.Field.hex(mesh)
+    f.seed(0, seeds, default_max_steps=200)
+    st = f.advect(0.08)
+    L = f.lines(0)
+    ratio, npairs = parity.local_check(H, L, 0.08, 6.0)
+    frac, bad = parity.restart_check(H, L, 0.08, mesh["lo"], mesh["hi"], 200)
+    note(f"{kind}: {len(mesh['cells'])} cells, {npairs} steps, local ratio {ratio:.3f}, restart compares "
+         f"{frac:.4f}, {st.gathers / max(1, st.steps):.4f} BVH walks per step; codes "
+         f"{np.bincount(L['codes'], minlength=6).tolist()}")
+    assert ratio <= 1.0 and npairs > 250 * 15, (ratio, npairs)
+    assert frac >= 0.95 and len(bad) == 0, (frac, bad[:10])
+    assert st.active == 0 and st.terminated[S.EXIT] > 20 and st.terminated[S.HALO_MISS] == 0
+    assert 0 < st.gathers < 0.1 * st.steps
+    ob = f.outbox(cap=len(seeds))
+    assert len(ob) == st.terminated[S.EXIT] + st.terminated[S.HALO_MISS]
+    ex = ob["code"] == S.EXIT
+    np.testing.assert_array_equal(ob["dest"][ex], H.dest(ob["pos"][ex].astype(np.float64)))
+    f.close()
+
+
 def test_hex_refusals(S):
     note("hex: refusals")
     mesh = fg.distorted_hex_mesh(17, (3, 3, 3), jitter=0.1)
@@ -112,6 +151,12 @@ def test_hex_refusals(S):
     st = f.advect(0.3)
     assert st.active == 0
     f.close()
+    # an unknown cell type (VTK_QUAD) is refused, naming the cell
+    types = np.full(len(mesh["cells"]), 12, np.uint8)
+    types[5] = 9
+    with pytest.raises(S.StreamiError) as e:
+        S.Field.hex(dict(mesh, cell_types=types))
+    assert e.value.code == S.E_ARG and "cell 5" in str(e.value)
 
 
 def test_hex256_full_size_sampled(S):

@@ -173,6 +173,21 @@ def test_split_cubes_hold_each_point_once(kind):
     assert (cell >= 0).all()
 
 
+@pytest.mark.parametrize("kind", ["wedge", "pyramid", "hex+pyramid"])
+def test_points_near_warped_cell_vertices_are_found(kind):
+    """Near a vertex of a warped (jittered) cell, Newton from the domain's centre can end at a
+    second root of the map outside the domain; the nearest-vertex restart still finds the cell.
+    Points within 0.06 of every interior lattice vertex of 6 x 6 x 5 jittered cubes."""
+    mesh = fg.split_hex_mesh(fg.distorted_hex_mesh(21, (6, 6, 5), jitter=0.2, sub=len(kind)), kind)
+    H = mixedfield(mesh)
+    k, j, i = np.meshgrid(np.arange(1, 5), np.arange(1, 6), np.arange(1, 6), indexing="ij")
+    lattice = (i + 7 * (j + 7 * k)).ravel()  # interior vertices of the 7 x 7 x 6 vertex lattice
+    rng = np.random.default_rng(9)
+    x = np.repeat(mesh["vertices"][lattice].astype(np.float64), 8, 0) + rng.uniform(-0.06, 0.06, (8 * len(lattice), 3))
+    cell, _ = H.locate(x)
+    assert (cell >= 0).all(), np.nonzero(cell < 0)[0][:10]
+
+
 def test_tetra_coordinates_are_volume_ratios():
     """A tetrahedron's parametric coordinates are its barycentric coordinates: the volume of
     the tetrahedron with the point in place of a vertex over the whole volume."""
