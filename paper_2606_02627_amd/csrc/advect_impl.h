@@ -569,7 +569,6 @@ __device__ __forceinline__ void advect_body(const AdvectArgs& A) {
   smp.reset();
   bool queue_done = false;  // wave-uniform
   const unsigned long long all = __ballot(1);
-  const long long n_work = A.order ? (long long)*A.n_work : A.n_particles;
   int q = (int)(blockIdx.x % (unsigned)A.n_queues), tries = 0;
 
   while (true) {
@@ -577,10 +576,11 @@ __device__ __forceinline__ void advect_body(const AdvectArgs& A) {
     if (!queue_done && dead != 0 && (__popcll(dead) >= A.refill || dead == all)) {
       const int cnt = __popcll(dead);
       const int leader = __ffsll((long long)dead) - 1;
-      // queue q: positions q, q + n_queues, ... of the order (qn of them); the slots
-      // claimed here belong to this queue even when q moves on below
+      // queue q: its range of every class (qn positions); the slots claimed here
+      // belong to this queue even when q moves on below
       const int qc = q;
-      const long long qn = (n_work - qc + A.n_queues - 1) / A.n_queues;
+      const unsigned* qrow = A.order ? A.qtab + qc * QTAB_STRIDE : nullptr;
+      const long long qn = A.order ? (long long)qrow[0] : A.n_particles;
       unsigned long long qbase = 0;
       if (lane == leader) qbase = atomicAdd(&A.qctr[q * QCTR_STRIDE], (unsigned long long)cnt);
       qbase = __shfl(qbase, leader, 64);
@@ -592,7 +592,18 @@ __device__ __forceinline__ void advect_body(const AdvectArgs& A) {
       if (p < 0) {
         const long long k = first + (long long)lanes_below(dead);
         if (k < qn) {
-          const long long slot = k * A.n_queues + qc;
+          long long slot = k;
+          if (A.order) {  // the queue's range in each class in turn
+            unsigned kk = (unsigned)k;
+            for (int c = 0; c < A.n_classes; ++c) {
+              const unsigned len = qrow[2 + 2 * c];
+              if (kk < len) {
+                slot = (long long)(qrow[1 + 2 * c] + kk);
+                break;
+              }
+              kk -= len;
+            }
+          }
           const long long my = A.order ? (long long)A.order[slot] : slot;
           const int4 mt = A.meta[my];
           const float4 ps = A.pos[my];

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -41,7 +42,7 @@ int launch_fill_u32(unsigned* p, long long n, unsigned v, hipStream_t st);
 int launch_max_abs(const void* src, int fmt, long long n, unsigned* out, hipStream_t st);
 int launch_work_order(const float4* pos, const int4* meta, const int4* meta2, const BlockDev* blocks, long long n,
                       int bits, unsigned n_buckets, int n_classes, int span, float h, float t_end, unsigned* key,
-                      unsigned* hist, unsigned* cursor, int* order, unsigned* n_work, hipStream_t st);
+                      unsigned* hist, unsigned* cursor, int* order, unsigned* qtab, hipStream_t st);
 int launch_fill_u64(unsigned long long* p, long long n, unsigned long long v, hipStream_t st);
 int launch_seed_bound(const SeedJobs& J, long long total, unsigned long long* out, hipStream_t st);
 std::string build_hex_blob(const float* V, long long nv, const float* val, const int* cells,
@@ -197,6 +198,7 @@ struct streami_field_s {
   DevBuf d_dhat, d_dhat2, d_xh;                      // surrogate jumps
   bool strides_mult16 = true;                        // every seed batch's record stride % 16 == 0
   int max_m = 0;                                     // largest per-particle step limit seeded
+  int min_m = INT_MAX;                               // smallest (equal to max_m: one class of work)
   long long active_hint = -1;  // particles known ACTIVE (after an exchange), -1: not known
   unsigned long long next_auto_id = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -784,9 +786,9 @@ int seed_batches(streami_field_s* f, const streami_seed_batch* bt, int nb, const
   if (f->n_particles + total >= (1LL << 31)) return fail(STREAMI_E_ARG, "more than 2^31 particles per handle");
   // every particle may record at most max_steps/stride + 2 vertices: reserve
   // that in the log; limits on the device are reduced on the device, all
-  // batches into one accumulator (24 bytes come back, one wait)
+  // batches into one accumulator (32 bytes come back, one wait)
   long long bound = 0;
-  int batch_max = 0;
+  int batch_max = 0, batch_min = INT_MAX;
   int rc;
   if (any_dev_ms) {
     if ((rc = f->d_seedred.reserve(32, 0, f->stream))) return rc;
@@ -795,6 +797,7 @@ int seed_batches(streami_field_s* f, const streami_seed_batch* bt, int nb, const
       return fail(STREAMI_E_NOMEM, "pinned host allocation failed");
     }
     launch_fill_u64((unsigned long long*)f->d_seedred.p, 3, 0, f->stream);
+    launch_fill_u64((unsigned long long*)f->d_seedred.p + 3, 1, ~0ull, f->stream);
     SeedJobs J;
     std::memset(&J, 0, sizeof J);
     J.stride = opts->record_stride;
@@ -813,11 +816,12 @@ int seed_batches(streami_field_s* f, const streami_seed_batch* bt, int nb, const
       }
     }
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(f->h_seedred, f->d_seedred.p, 24, hipMemcpyDeviceToHost, f->stream));
+    HIP_TRY(hipMemcpyAsync(f->h_seedred, f->d_seedred.p, 32, hipMemcpyDeviceToHost, f->stream));
     HIP_TRY(hipStreamSynchronize(f->stream));
     if (f->h_seedred[2]) return fail(STREAMI_E_ARG, "max_steps has a negative entry");
     bound = (long long)f->h_seedred[0];
     batch_max = (int)f->h_seedred[1];
+    if (f->h_seedred[3] <= (unsigned long long)INT_MAX) batch_min = (int)f->h_seedred[3];
   }
   for (int k = 0; k < nb; ++k) {
     const streami_seed_batch& b = bt[k];
@@ -827,6 +831,7 @@ int seed_batches(streami_field_s* f, const streami_seed_batch* bt, int nb, const
       if (m < 0) return fail(STREAMI_E_ARG, "batch %d: max_steps[%lld] < 0", k, i);
       bound += m / opts->record_stride + 2;
       batch_max = std::max(batch_max, m);
+      batch_min = std::min(batch_min, m);
     }
   }
   drop_graph(f);
@@ -904,6 +909,7 @@ int seed_batches(streami_field_s* f, const streami_seed_batch* bt, int nb, const
   }
   if (!dev_in) HIP_TRY(hipStreamSynchronize(f->stream));  // staging buffers are freed on return
   f->max_m = std::max(f->max_m, batch_max);
+  f->min_m = std::min(f->min_m, batch_min);
   f->active_hint = -1;  // new particles: the active count is no longer known
   if (opts->record_stride % 16 != 0) f->strides_mult16 = false;
   return STREAMI_OK;
@@ -1061,7 +1067,8 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
   const bool spatial = p->work_order == 0;
   // spatial work order: classes of remaining steps (longest first), then block and Morton brick
   const int bits = f->blocks.size() == 1 ? 5 : 3;
-  const int n_classes = ORDER_CLASSES;
+  // one class when every seeded limit is the same (the spatial order alone, fewer buckets)
+  const int n_classes = f->min_m < f->max_m ? ORDER_CLASSES : 1;
   const int span = (int)std::max<long long>(1, p->step_budget > 0 ? std::min<long long>(p->step_budget, f->max_m) : f->max_m);
   const unsigned n_buckets = (unsigned)n_classes * (unsigned)f->blocks.size() * (1u << (3 * bits)) + 1;
   {
@@ -1071,12 +1078,13 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
       if ((rc = f->d_key.reserve(f->n_particles * 4, 0, f->stream)) ||
           (rc = f->d_order.reserve(f->n_particles * 4, 0, f->stream)) ||
           (rc = f->d_hist.reserve(n_buckets * 4, 0, f->stream)) ||
-          (rc = f->d_cursor.reserve(n_buckets * 4, 0, f->stream)) || (rc = f->d_nwork.reserve(8, 0, f->stream)))
+          (rc = f->d_cursor.reserve(n_buckets * 4, 0, f->stream)) || (rc = f->d_nwork.reserve(4 * MAX_QUEUES * QTAB_STRIDE, 0, f->stream)))
         return rc;
     }
   }
   a.order = spatial ? (const int*)f->d_order.p : nullptr;
-  a.n_work = spatial ? (const unsigned*)f->d_nwork.p : nullptr;
+  a.qtab = spatial ? (const unsigned*)f->d_nwork.p : nullptr;
+  a.n_classes = spatial ? n_classes : 1;
   a.qctr = (unsigned long long*)f->d_qctr.p;
   a.n_queues = spatial ? MAX_QUEUES : 1;
   const bool batched = f->blocks.size() > 1;
@@ -1141,6 +1149,7 @@ int streami_clear(streami_field f) {
   f->active_hint = -1;
   f->vert_bound = 0;
   f->max_m = 0;
+  f->min_m = INT_MAX;
   f->strides_mult16 = true;
   f->next_auto_id = 0;
   f->log_need_known = true;  // the counters below restart at zero

@@ -106,13 +106,16 @@ struct AdvectArgs {
   unsigned long long* ctr;           // per-call counters
   long long n_particles;
   // work order: particles are claimed in the order of `order` (NULL: index
-  // order), the first *n_work entries only; the order is dealt to n_queues
-  // queues, one per XCD (workgroups are dispatched to the XCDs round-robin):
-  // queue q holds positions q, q + n_queues, q + 2 n_queues, ..., so every
-  // queue starts with the longest work; a wave that empties its queue steals
-  // from the next
+  // order, one queue), which holds n_classes classes of remaining work, longest
+  // first.  Each class is split into MAX_QUEUES contiguous ranges, one per queue
+  // and XCD (workgroups are dispatched to the XCDs round-robin); queue q runs
+  // its range of every class in turn, so each XCD starts with long work on a
+  // compact part of the field.  qtab holds, per queue, the total count and then
+  // (start, length) of its range in each class (QTAB_STRIDE unsigned per queue).
+  // A wave that empties its queue steals from the next.
   const int* order;
-  const unsigned* n_work;
+  const unsigned* qtab;
+  int n_classes;
   unsigned long long* qctr;  // n_queues counters, QCTR_STRIDE apart
   int n_queues;
   float h;
@@ -158,6 +161,7 @@ __device__ __forceinline__ void to_monomial(float3 c[8]) {
 constexpr int QCTR_STRIDE = 16;  // one 128-byte line per queue counter
 constexpr int MAX_QUEUES = 8;
 constexpr int ORDER_CLASSES = 8;  // classes of remaining steps in the spatial work order
+constexpr int QTAB_STRIDE = 1 + 2 * ORDER_CLASSES;
 
 // Per-axis offsets of node i within a slice of a block.
 template <int LAYOUT>

@@ -278,7 +278,7 @@ int launch_fill_u64(unsigned long long* p, long long n, unsigned long long v, hi
 // largest m, and a flag for a negative m, accumulated into out[0..2] (the
 // caller clears it); grid-stride over every job in turn
 __global__ void k_seed_bound(SeedJobs J, unsigned long long* out) {
-  unsigned long long s = 0, mx = 0, neg = 0;
+  unsigned long long s = 0, mx = 0, neg = 0, mn = ~0ull;
   const long long t0 = blockIdx.x * (long long)blockDim.x + threadIdx.x, dt = (long long)gridDim.x * blockDim.x;
   for (int j = 0; j < J.n_jobs; ++j) {
     const int* ms = J.j[j].max_steps;
@@ -289,6 +289,7 @@ __global__ void k_seed_bound(SeedJobs J, unsigned long long* out) {
       } else {
         s += (unsigned long long)(m / J.stride + 2);
         mx = mx > (unsigned long long)m ? mx : (unsigned long long)m;
+        mn = mn < (unsigned long long)m ? mn : (unsigned long long)m;
       }
     }
   }
@@ -296,11 +297,14 @@ __global__ void k_seed_bound(SeedJobs J, unsigned long long* out) {
     s += __shfl_xor(s, o, 64);
     const unsigned long long m2 = __shfl_xor(mx, o, 64);
     mx = mx > m2 ? mx : m2;
+    const unsigned long long m3 = __shfl_xor(mn, o, 64);
+    mn = mn < m3 ? mn : m3;
     neg |= __shfl_xor(neg, o, 64);
   }
   if (__lane_id() == 0) {
     if (s) atomicAdd(&out[0], s);
     if (mx) atomicMax(&out[1], mx);
+    if (mn != ~0ull) atomicMin(&out[3], mn);
     if (neg) atomicOr(&out[2], neg);
   }
 }
@@ -449,16 +453,21 @@ __global__ void k_order_keys(const float4* pos, const int4* meta, const int4* me
     }
     key[i] = k;
     // idle particles (terminated, or outside the window) take no slot: only the
-    // first n_work entries of the order are read, and one shared bucket would
+    // counted entries of the order are read, and one shared bucket would
     // serialise millions of atomics on one address
     if (k != n_buckets - 1) atomicAdd(&hist[k], 1u);
   }
 }
 
-// Exclusive scan of hist[0..nb) into cursor[], one workgroup of 1024 threads;
-// n_work = number of particles outside the last (idle, never counted) bucket.
-__global__ void __launch_bounds__(1024) k_order_scan(const unsigned* hist, unsigned nb, unsigned* cursor,
-                                                     unsigned* n_work) {
+// Exclusive scan of hist[0..nb) into cursor[], one workgroup of 1024 threads,
+// and the queue table: class c starts at its first bucket's prefix and ends
+// where the next starts (the last at the number of particles outside the
+// idle bucket); queue q takes [start + n q / Q, start + n (q+1) / Q) of each
+// class of n particles (Q = MAX_QUEUES).
+__global__ void __launch_bounds__(1024) k_order_scan(const unsigned* hist, unsigned nb, unsigned n_classes,
+                                                     unsigned* cursor, unsigned* qtab) {
+  __shared__ unsigned cls[ORDER_CLASSES + 1];
+  const unsigned n_spatial = (nb - 1) / n_classes;
   __shared__ unsigned part[1024];
   const unsigned t = threadIdx.x;
   const unsigned per = (nb + 1023) / 1024;
@@ -476,9 +485,23 @@ __global__ void __launch_bounds__(1024) k_order_scan(const unsigned* hist, unsig
   unsigned run = part[t] - s;  // exclusive prefix of this thread's chunk
   for (unsigned b = b0; b < b1; ++b) {
     cursor[b] = run;
+    if (b < nb - 1 && b % n_spatial == 0) cls[b / n_spatial] = run;
     run += hist[b];
   }
-  if (t == 1023) *n_work = part[1023] - hist[nb - 1];
+  if (t == 1023) cls[n_classes] = part[1023] - hist[nb - 1];
+  __syncthreads();
+  if (t < (unsigned)MAX_QUEUES) {
+    unsigned* row = qtab + t * QTAB_STRIDE;
+    unsigned total = 0;
+    for (unsigned c = 0; c < n_classes; ++c) {
+      const unsigned long long n = cls[c + 1] - cls[c];
+      const unsigned lo = cls[c] + (unsigned)(n * t / MAX_QUEUES), hi = cls[c] + (unsigned)(n * (t + 1) / MAX_QUEUES);
+      row[1 + 2 * c] = lo;
+      row[2 + 2 * c] = hi - lo;
+      total += hi - lo;
+    }
+    row[0] = total;
+  }
 }
 
 __global__ void k_order_scatter(const unsigned* key, long long n, unsigned idle, unsigned* cursor, int* order) {
@@ -492,14 +515,14 @@ __global__ void k_order_scatter(const unsigned* key, long long n, unsigned idle,
 
 int launch_work_order(const float4* pos, const int4* meta, const int4* meta2, const BlockDev* blocks, long long n,
                       int bits, unsigned n_buckets, int n_classes, int span, float h, float t_end, unsigned* key,
-                      unsigned* hist, unsigned* cursor, int* order, unsigned* n_work, hipStream_t st) {
+                      unsigned* hist, unsigned* cursor, int* order, unsigned* qtab, hipStream_t st) {
   if (n <= 0) return 0;
   long long grid = (n + 255) / 256;
   if (grid > 16384) grid = 16384;
   launch_fill_u32(hist, n_buckets, 0u, st);
   hipLaunchKernelGGL(k_order_keys, dim3((unsigned)grid), dim3(256), 0, st, pos, meta, meta2, blocks, n, bits,
                      n_buckets, n_classes, span, h, t_end, key, hist);
-  hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(1024), 0, st, hist, n_buckets, cursor, n_work);
+  hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(1024), 0, st, hist, n_buckets, (unsigned)n_classes, cursor, qtab);
   hipLaunchKernelGGL(k_order_scatter, dim3((unsigned)grid), dim3(256), 0, st, key, n, n_buckets - 1, cursor, order);
   return 0;
 }
