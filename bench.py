@@ -500,7 +500,7 @@ def forward_bench(args):
     wall = (time.perf_counter() - t) / args.steps
     steps = int(st0.steps)
     gran = []
-    for budget in (64, 8, 1):
+    for budget in (512, 256, 128, 64, 8, 1):
         torch.cuda.synchronize()
         t = time.perf_counter()
         rk, stk = one(budget, stats=True)
