@@ -203,30 +203,38 @@ __device__ __forceinline__ float3 hex_value(const float4* rec, float3 rsu) {
   return make_float3(v[0], v[1], v[2]);
 }
 
-// sample() of an unstructured field: the cell a lane sampled last is tested
-// first, then up to HEX_HOPS neighbours across the faces the point lies beyond;
-// otherwise the BVH walk finds the first leaf cell (in preorder) holding x.
-// False where no cell holds x (Sec. 3.1.1).
+// sample() of an unstructured field: the record of the cell a lane sampled
+// last stays in registers (a particle samples the same cell several times in a
+// row), and is tested first; then up to HEX_HOPS neighbours across the faces
+// the point lies beyond, each record loaded into the same registers; otherwise
+// the BVH walk finds the first leaf cell (in preorder) holding x.  False where
+// no cell holds x (Sec. 3.1.1).
 struct HexSampler {
-  int cell = -1;
-  int kind = HK_HEX;     // the kind of `cell`
-  unsigned gathers = 0;  // BVH walks
+  int cell = -1;          // the cell whose record rc holds (-1: none)
+  int kind = HK_HEX;      // its kind
+  unsigned gathers = 0;   // BVH walks
+  float4 rc[HEX_REC_UNITS];
   __device__ __forceinline__ void reset() { cell = -1; }
+  __device__ __forceinline__ void load(const float4* recs, int c) {
+    const float4* r = recs + (size_t)HEX_REC_UNITS * c;
+#pragma unroll
+    for (int i = 0; i < HEX_REC_UNITS; ++i) rc[i] = r[i];
+  }
   __device__ __forceinline__ bool sample(const BlockDev&, const char* base, float3 x, float, float3& v, bool = false) {
     const HexHeader& H = *reinterpret_cast<const HexHeader*>(base);
     const float4* blob = reinterpret_cast<const float4*>(base);
     const float4* recs = blob + H.cell_off;
     float3 rsu;
-    int found = -1;
-    int fkind = kind;
+    bool found = false;
     if (cell >= 0) {
       int c = cell, k = kind;
 #pragma unroll 1
       for (int hop = 0; hop <= HEX_HOPS; ++hop) {
-        const int st = hex_contains(recs + (size_t)HEX_REC_UNITS * c, x, H.tol, k, rsu);
+        const int st = hex_contains(rc, x, H.tol, k, rsu);
         if (st > 0) {
-          found = c;
-          fkind = k;
+          found = true;
+          cell = c;
+          kind = k;
           break;
         }
         if (st < 0 || hop == HEX_HOPS) break;
@@ -235,12 +243,15 @@ struct HexSampler {
         if (e < 0) break;
         c = e & HEX_REC_MASK;
         k = e >> HEX_KIND_SHIFT;
+        load(recs, c);
       }
+      if (!found) cell = -1;  // rc holds the last cell tried
     }
-    if (found < 0) {
+    if (!found) {
       ++gathers;
       const float4* nodes = blob + H.node_off;
       unsigned i = 0;
+      int hit = -1, hk = HK_HEX;
       while (i < H.n_nodes) {
         const float4 a = nodes[2 * (size_t)i], b = nodes[2 * (size_t)i + 1];
         const bool in = x.x >= a.x && x.x <= b.x && x.y >= a.y && x.y <= b.y && x.z >= a.z && x.z <= b.z;
@@ -252,27 +263,25 @@ struct HexSampler {
           ++i;
         } else {
           const int first = leaf >> 3, cnt = (leaf & 7) + 1;
-          for (int k = 0; k < cnt; ++k) {
-            const int c = first + k;
+          for (int q = 0; q < cnt; ++q) {
+            const int c = first + q;
             const int ck = reinterpret_cast<const int*>(blob + H.neigh_off + 2 * (size_t)c)[6];
             if (hex_contains(recs + (size_t)HEX_REC_UNITS * c, x, H.tol, ck, rsu) > 0) {
-              found = c;
-              fkind = ck;
+              hit = c;
+              hk = ck;
               break;
             }
           }
-          if (found >= 0) break;
+          if (hit >= 0) break;
           i = skip;
         }
       }
-      if (found < 0) {
-        cell = -1;
-        return false;
-      }
+      if (hit < 0) return false;
+      cell = hit;
+      kind = hk;
+      load(recs, hit);
     }
-    cell = found;
-    kind = fkind;
-    v = hex_value(recs + (size_t)HEX_REC_UNITS * cell, rsu);
+    v = hex_value(rc, rsu);
     return true;
   }
 };
