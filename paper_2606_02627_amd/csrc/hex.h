@@ -212,13 +212,55 @@ __device__ __forceinline__ float3 hex_value(const float4* rec, float3 rsu) {
 struct HexSampler {
   int cell = -1;          // the cell whose record rc holds (-1: none)
   int kind = HK_HEX;      // its kind
+  bool affine = false;    // its position map is affine: rc holds the inverse Jacobian (below)
   unsigned gathers = 0;   // BVH walks
   float4 rc[HEX_REC_UNITS];
   __device__ __forceinline__ void reset() { cell = -1; }
+  // Load record c.  An affine map (no rs, ru, su, rsu terms: voxels, tetrahedra) is inverted
+  // once here: its inverse Jacobian (rows), by Cramer's rule, takes the 12 zero slots of the
+  // non-affine coefficients, so a cached sample locates x with 9 multiply-adds.
   __device__ __forceinline__ void load(const float4* recs, int c) {
     const float4* r = recs + (size_t)HEX_REC_UNITS * c;
 #pragma unroll
     for (int i = 0; i < HEX_REC_UNITS; ++i) rc[i] = r[i];
+    // c1 = (q0.w, q1.x, q1.y), c2 = (q1.z, q1.w, q2.x), c4 = (q3.x, q3.y, q3.z); the zero slots:
+    // c3 = (q2.y, q2.z, q2.w), c5 = (q3.w, q4.x, q4.y), c6 = (q4.z, q4.w, q5.x), c7 = (q5.y, q5.z, q5.w)
+    affine = rc[2].y == 0.0f && rc[2].z == 0.0f && rc[2].w == 0.0f && rc[3].w == 0.0f && rc[4].x == 0.0f &&
+             rc[4].y == 0.0f && rc[4].z == 0.0f && rc[4].w == 0.0f && rc[5].x == 0.0f && rc[5].y == 0.0f &&
+             rc[5].z == 0.0f && rc[5].w == 0.0f;
+    if (affine) {
+      const float a0 = rc[0].w, a1 = rc[1].x, a2 = rc[1].y;  // column r: c1
+      const float b0 = rc[1].z, b1 = rc[1].w, b2 = rc[2].x;  // column s: c2
+      const float e0 = rc[3].x, e1 = rc[3].y, e2 = rc[3].z;  // column u: c4
+      // rows of the inverse: (b x e), (e x a), (a x b) over det
+      const float x0 = b1 * e2 - b2 * e1, x1 = b2 * e0 - b0 * e2, x2 = b0 * e1 - b1 * e0;
+      const float det = a0 * x0 + a1 * x1 + a2 * x2;
+      if (!(fabsf(det) > 0.0f)) {
+        affine = false;  // degenerate: the general path finds nothing
+        return;
+      }
+      const float inv = 1.0f / det;
+      const float y0 = e1 * a2 - e2 * a1, y1 = e2 * a0 - e0 * a2, y2 = e0 * a1 - e1 * a0;
+      const float z0 = a1 * b2 - a2 * b1, z1 = a2 * b0 - a0 * b2, z2 = a0 * b1 - a1 * b0;
+      rc[2].y = x0 * inv; rc[2].z = x1 * inv; rc[2].w = x2 * inv;
+      rc[3].w = y0 * inv; rc[4].x = y1 * inv; rc[4].y = y2 * inv;
+      rc[4].z = z0 * inv; rc[4].w = z1 * inv; rc[5].x = z2 * inv;
+    }
+  }
+  // containment of x in the cached cell (hex_contains' contract)
+  __device__ __forceinline__ int contains_cached(float3 x, float tol, float3& rsu) const {
+    if (!affine) return hex_contains(rc, x, tol, kind, rsu);
+    const float d0 = x.x - rc[0].x, d1 = x.y - rc[0].y, d2 = x.z - rc[0].z;
+    const float r = fmaf(rc[2].y, d0, fmaf(rc[2].z, d1, rc[2].w * d2));
+    const float s = fmaf(rc[3].w, d0, fmaf(rc[4].x, d1, rc[4].y * d2));
+    const float u = fmaf(rc[4].z, d0, fmaf(rc[4].w, d1, rc[5].x * d2));
+    rsu = make_float3(r, s, u);
+    const float lo = -tol, hi = 1.0f + tol;
+    bool in = r >= lo && s >= lo && u >= lo;
+    if (kind == HK_TETRA) in = in && r + s + u <= hi;
+    else if (kind == HK_WEDGE) in = in && r + s <= hi && u <= hi;
+    else in = in && r <= hi && s <= hi && u <= hi;
+    return in ? 1 : 0;
   }
   __device__ __forceinline__ bool sample(const BlockDev&, const char* base, float3 x, float, float3& v, bool = false) {
     const HexHeader& H = *reinterpret_cast<const HexHeader*>(base);
@@ -230,7 +272,8 @@ struct HexSampler {
       int c = cell, k = kind;
 #pragma unroll 1
       for (int hop = 0; hop <= HEX_HOPS; ++hop) {
-        const int st = hex_contains(rc, x, H.tol, k, rsu);
+        kind = k;
+        const int st = contains_cached(x, H.tol, rsu);
         if (st > 0) {
           found = true;
           cell = c;
