@@ -1078,7 +1078,7 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
       if ((rc = f->d_key.reserve(f->n_particles * 4, 0, f->stream)) ||
           (rc = f->d_order.reserve(f->n_particles * 4, 0, f->stream)) ||
           (rc = f->d_hist.reserve(n_buckets * 4, 0, f->stream)) ||
-          (rc = f->d_cursor.reserve(n_buckets * 4, 0, f->stream)) || (rc = f->d_nwork.reserve(4 * MAX_QUEUES * QTAB_STRIDE, 0, f->stream)))
+          (rc = f->d_cursor.reserve(n_buckets * 4, 0, f->stream)) || (rc = f->d_nwork.reserve(4 * (MAX_QUEUES * QTAB_STRIDE + ORDER_CLASSES + 1 + ORDER_SCAN_WG), 0, f->stream)))
         return rc;
     }
   }

@@ -162,6 +162,7 @@ constexpr int QCTR_STRIDE = 16;  // one 128-byte line per queue counter
 constexpr int MAX_QUEUES = 8;
 constexpr int ORDER_CLASSES = 8;  // classes of remaining steps in the spatial work order
 constexpr int QTAB_STRIDE = 1 + 2 * ORDER_CLASSES;
+constexpr int ORDER_SCAN_WG = 256;  // workgroups of the work order's bucket scan
 
 // Per-axis offsets of node i within a slice of a block.
 template <int LAYOUT>

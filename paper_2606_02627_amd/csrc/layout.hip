@@ -459,49 +459,92 @@ __global__ void k_order_keys(const float4* pos, const int4* meta, const int4* me
   }
 }
 
-// Exclusive scan of hist[0..nb) into cursor[], one workgroup of 1024 threads,
-// and the queue table: class c starts at its first bucket's prefix and ends
-// where the next starts (the last at the number of particles outside the
-// idle bucket); queue q takes [start + n q / Q, start + n (q+1) / Q) of each
-// class of n particles (Q = MAX_QUEUES).
-__global__ void __launch_bounds__(1024) k_order_scan(const unsigned* hist, unsigned nb, unsigned n_classes,
-                                                     unsigned* cursor, unsigned* qtab) {
-  __shared__ unsigned cls[ORDER_CLASSES + 1];
-  const unsigned n_spatial = (nb - 1) / n_classes;
-  __shared__ unsigned part[1024];
-  const unsigned t = threadIdx.x;
-  const unsigned per = (nb + 1023) / 1024;
-  const unsigned b0 = t * per, b1 = min(nb, b0 + per);
+// Exclusive scan of hist[0..nb) into cursor[] over SCAN_WG workgroups, each
+// owning a contiguous range of the buckets: k_scan_part sums each range,
+// k_scan_apply scans its range in tiles of SCAN_T from the sum of the ranges
+// before it.  The class starts (each class's first bucket's prefix; the last
+// entry, the idle bucket's prefix, is the number of particles counted) go to
+// cls[]; k_scan_qtab then gives queue q the range [start + n q / Q,
+// start + n (q+1) / Q) of each class of n particles (Q = MAX_QUEUES).
+constexpr unsigned SCAN_WG = ORDER_SCAN_WG, SCAN_T = 256;
+
+__device__ __forceinline__ unsigned block_sum(unsigned v, unsigned* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const unsigned w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  unsigned t = 0;
+  for (unsigned i = 0; i < SCAN_T / 64; ++i) t += sh[i];
+  __syncthreads();
+  return t;
+}
+
+// exclusive prefix of v over the workgroup's threads; total = the workgroup's sum
+__device__ __forceinline__ unsigned block_exclusive(unsigned v, unsigned* sh, unsigned& total) {
+  const unsigned w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  unsigned incl = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned u = __shfl_up(incl, (unsigned)o, 64);
+    if (l >= (unsigned)o) incl += u;
+  }
+  if (l == 63) sh[w] = incl;
+  __syncthreads();
+  unsigned off = 0;
+  total = 0;
+  for (unsigned i = 0; i < SCAN_T / 64; ++i) {
+    if (i < w) off += sh[i];
+    total += sh[i];
+  }
+  __syncthreads();
+  return off + incl - v;
+}
+
+__global__ void __launch_bounds__(SCAN_T) k_scan_part(const unsigned* hist, unsigned nb, unsigned* part) {
+  __shared__ unsigned sh[SCAN_T / 64];
+  const unsigned per = (nb + SCAN_WG - 1) / SCAN_WG;
+  const unsigned b0 = blockIdx.x * per, b1 = min(nb, b0 + per);
   unsigned s = 0;
-  for (unsigned b = b0; b < b1; ++b) s += hist[b];
-  part[t] = s;
-  __syncthreads();
-  for (unsigned o = 1; o < 1024; o <<= 1) {  // Hillis-Steele inclusive scan
-    const unsigned v = t >= o ? part[t - o] : 0u;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
-  }
-  unsigned run = part[t] - s;  // exclusive prefix of this thread's chunk
-  for (unsigned b = b0; b < b1; ++b) {
-    cursor[b] = run;
-    if (b < nb - 1 && b % n_spatial == 0) cls[b / n_spatial] = run;
-    run += hist[b];
-  }
-  if (t == 1023) cls[n_classes] = part[1023] - hist[nb - 1];
-  __syncthreads();
-  if (t < (unsigned)MAX_QUEUES) {
-    unsigned* row = qtab + t * QTAB_STRIDE;
-    unsigned total = 0;
-    for (unsigned c = 0; c < n_classes; ++c) {
-      const unsigned long long n = cls[c + 1] - cls[c];
-      const unsigned lo = cls[c] + (unsigned)(n * t / MAX_QUEUES), hi = cls[c] + (unsigned)(n * (t + 1) / MAX_QUEUES);
-      row[1 + 2 * c] = lo;
-      row[2 + 2 * c] = hi - lo;
-      total += hi - lo;
+  for (unsigned b = b0 + threadIdx.x; b < b1; b += SCAN_T) s += hist[b];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(SCAN_T) k_scan_apply(const unsigned* hist, unsigned nb, unsigned n_classes,
+                                                       const unsigned* part, unsigned* cursor, unsigned* cls) {
+  __shared__ unsigned sh[SCAN_T / 64];
+  const unsigned per = (nb + SCAN_WG - 1) / SCAN_WG;
+  const unsigned b0 = blockIdx.x * per, b1 = min(nb, b0 + per);
+  const unsigned n_spatial = (nb - 1) / n_classes;
+  unsigned o = 0;
+  for (unsigned i = threadIdx.x; i < blockIdx.x; i += SCAN_T) o += part[i];
+  unsigned run = block_sum(o, sh);  // the buckets before this range
+  for (unsigned t0 = b0; t0 < b1; t0 += SCAN_T) {
+    const unsigned b = t0 + threadIdx.x;
+    const unsigned h = b < b1 ? hist[b] : 0u;
+    unsigned tot;
+    const unsigned ex = run + block_exclusive(h, sh, tot);
+    if (b < b1) {
+      cursor[b] = ex;
+      if (b == nb - 1) cls[n_classes] = ex;
+      else if (b % n_spatial == 0) cls[b / n_spatial] = ex;
     }
-    row[0] = total;
+    run += tot;
   }
+}
+
+__global__ void k_scan_qtab(const unsigned* cls, unsigned n_classes, unsigned* qtab) {
+  const unsigned t = threadIdx.x;
+  if (t >= (unsigned)MAX_QUEUES) return;
+  unsigned* row = qtab + t * QTAB_STRIDE;
+  unsigned total = 0;
+  for (unsigned c = 0; c < n_classes; ++c) {
+    const unsigned long long n = cls[c + 1] - cls[c];
+    const unsigned lo = cls[c] + (unsigned)(n * t / MAX_QUEUES), hi = cls[c] + (unsigned)(n * (t + 1) / MAX_QUEUES);
+    row[1 + 2 * c] = lo;
+    row[2 + 2 * c] = hi - lo;
+    total += hi - lo;
+  }
+  row[0] = total;
 }
 
 __global__ void k_order_scatter(const unsigned* key, long long n, unsigned idle, unsigned* cursor, int* order) {
@@ -522,7 +565,13 @@ int launch_work_order(const float4* pos, const int4* meta, const int4* meta2, co
   launch_fill_u32(hist, n_buckets, 0u, st);
   hipLaunchKernelGGL(k_order_keys, dim3((unsigned)grid), dim3(256), 0, st, pos, meta, meta2, blocks, n, bits,
                      n_buckets, n_classes, span, h, t_end, key, hist);
-  hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(1024), 0, st, hist, n_buckets, (unsigned)n_classes, cursor, qtab);
+  // qtab's buffer also holds the class starts and the range sums after the table
+  unsigned* cls = qtab + MAX_QUEUES * QTAB_STRIDE;
+  unsigned* part = cls + ORDER_CLASSES + 1;
+  hipLaunchKernelGGL(k_scan_part, dim3(SCAN_WG), dim3(SCAN_T), 0, st, hist, n_buckets, part);
+  hipLaunchKernelGGL(k_scan_apply, dim3(SCAN_WG), dim3(SCAN_T), 0, st, hist, n_buckets, (unsigned)n_classes, part,
+                     cursor, cls);
+  hipLaunchKernelGGL(k_scan_qtab, dim3(1), dim3(64), 0, st, cls, (unsigned)n_classes, qtab);
   hipLaunchKernelGGL(k_order_scatter, dim3((unsigned)grid), dim3(256), 0, st, key, n, n_buckets - 1, cursor, order);
   return 0;
 }
