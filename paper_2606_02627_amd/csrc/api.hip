@@ -1067,8 +1067,11 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
   const bool spatial = p->work_order == 0;
   // spatial work order: classes of remaining steps (longest first), then block and Morton brick
   const int bits = f->blocks.size() == 1 ? 5 : 3;
-  // one class when every seeded limit is the same (the spatial order alone, fewer buckets)
-  const int n_classes = f->min_m < f->max_m ? ORDER_CLASSES : 1;
+  // one class when every seeded limit is the same (the spatial order alone, fewer buckets), or
+  // when the launch has many particles per lane: its end is then a small part of it, and the
+  // classes would only cost the queues spatial locality
+  const long long n_work_est = f->active_hint >= 0 ? std::min(f->active_hint, f->n_particles) : f->n_particles;
+  const int n_classes = f->min_m < f->max_m && n_work_est <= 64 * grid * 256 ? ORDER_CLASSES : 1;
   const int span = (int)std::max<long long>(1, p->step_budget > 0 ? std::min<long long>(p->step_budget, f->max_m) : f->max_m);
   const unsigned n_buckets = (unsigned)n_classes * (unsigned)f->blocks.size() * (1u << (3 * bits)) + 1;
   {
