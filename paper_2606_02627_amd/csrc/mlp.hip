@@ -276,13 +276,18 @@ struct InferArgs {
   float* out;
 };
 
-// One workgroup = 4 waves = 128 particles; each layer's weight fragments
-// (<= 128 KB) and biases are staged in LDS and shared by the 4 waves; each
-// wave keeps its 32 particles' activations in registers as the B operand and
-// the 8 output tiles' accumulators (128 registers) as independent MFMA chains.
+// One workgroup = 4 waves = 128 particles; each wave keeps its 32 particles'
+// activations in registers as the B operand.  A layer is computed in two
+// halves of 4 output tiles: each half's weight fragments (<= 64 KB) are staged
+// in LDS and shared by the 4 waves, and its 4 tiles' accumulators (64
+// registers) run as independent MFMA chains.  The first half's activations wait
+// in 32 registers until the second half has read the layer's input; with 64 KB
+// of LDS and <= 256 registers per wave, two workgroups share a CU, so one
+// workgroup's epilogue (SiLU: an exp and a reciprocal per value) overlaps the
+// other's matrix work.
 constexpr int INFER_WAVES = 4;
-__global__ void __launch_bounds__(64 * INFER_WAVES) k_mlp_infer(InferArgs a) {
-  __shared__ uint4 wl[8192];
+__global__ void __launch_bounds__(64 * INFER_WAVES, 2) k_mlp_infer(InferArgs a) {
+  __shared__ uint4 wl[4096];
   __shared__ float bl[256];
   const int tid = threadIdx.x, lane = tid & 63, hi = lane >> 5;
   const long long p = (long long)blockIdx.x * (32 * INFER_WAVES) + (tid >> 6) * 32 + (lane & 31);
@@ -301,41 +306,52 @@ __global__ void __launch_bounds__(64 * INFER_WAVES) k_mlp_infer(InferArgs a) {
 #pragma unroll
     for (int s = 1; s < 16; ++s) B[s] = zero;  // layer 0 reads B[0] only
   }
-  f32x16 acc[8];
+  f32x16 acc[4];
+  bf16x8 Bn[8];  // the first half's outputs (features 0..127), until the second half is done
 #pragma unroll
   for (int l = 0; l < NL; ++l) {
     const int tiles = FR_TILES[l], ks = FR_KSTEPS[l];
-    __syncthreads();  // every wave is done with the previous layer's LDS
-    for (int i = tid; i < tiles * ks * 64; i += 64 * INFER_WAVES) wl[i] = a.frag[FR_OFF[l] + i];
-    for (int i = tid; i < 256; i += 64 * INFER_WAVES) bl[i] = i < WID[l + 1] ? a.b[l][i] : 0.0f;
-    __syncthreads();
-    // the accumulators start at the bias of the feature each register holds
+    const int halves = tiles > 4 ? 2 : 1, th = tiles / halves;
 #pragma unroll
-    for (int t = 0; t < tiles; ++t)
+    for (int h = 0; h < halves; ++h) {
+      __syncthreads();  // every wave is done with the LDS contents
+      const uint4* src = a.frag + FR_OFF[l] + h * th * ks * 64;
+      for (int i = tid; i < th * ks * 64; i += 64 * INFER_WAVES) wl[i] = src[i];
+      if (h == 0)
+        for (int i = tid; i < 256; i += 64 * INFER_WAVES) bl[i] = i < WID[l + 1] ? a.b[l][i] : 0.0f;
+      __syncthreads();
+      // the accumulators start at the bias of the feature each register holds
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[t][r] = bl[32 * t + 8 * (r / 4) + 4 * hi + r % 4];
+      for (int t = 0; t < th; ++t)
 #pragma unroll
-    for (int s = 0; s < ks; ++s)
+        for (int r = 0; r < 16; ++r) acc[t][r] = bl[32 * (h * th + t) + 8 * (r / 4) + 4 * hi + r % 4];
 #pragma unroll
-      for (int t = 0; t < tiles; ++t) {
-        const uint4 w = wl[(t * ks + s) * 64 + lane];
-        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, w), B[s], acc[t], 0, 0, 0);
-      }
-    if (l < NL - 1) {
+      for (int s = 0; s < ks; ++s) {
 #pragma unroll
-      for (int t = 0; t < 8; ++t)
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          f32x8 h;
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const int r = 8 * q + j;
-            h[j] = silu_fast(acc[t][r]);
-          }
-          B[2 * t + q] = __builtin_convertvector(h, bf16x8);
+        for (int t = 0; t < th; ++t) {
+          const uint4 w = wl[(t * ks + s) * 64 + lane];
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, w), B[s], acc[t], 0, 0, 0);
         }
-    } else if (live && hi == 0) {
-      for (int c = 0; c < 3; ++c) a.out[p * 3 + c] = a.sigma[c] * acc[0][c];
+        if (s % 4 == 3) __builtin_amdgcn_sched_barrier(0);  // bound how far fragment loads run ahead
+      }
+      if (l < NL - 1) {
+#pragma unroll
+        for (int t = 0; t < th; ++t)
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            f32x8 hv;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) hv[j] = silu_fast(acc[t][8 * q + j]);
+            if (h == 0) Bn[2 * t + q] = __builtin_convertvector(hv, bf16x8);
+            else B[8 + 2 * t + q] = __builtin_convertvector(hv, bf16x8);
+          }
+        if (h == 1) {
+#pragma unroll
+          for (int k = 0; k < 8; ++k) B[k] = Bn[k];
+        }
+      } else if (live && hi == 0) {
+        for (int c = 0; c < 3; ++c) a.out[p * 3 + c] = a.sigma[c] * acc[0][c];
+      }
     }
   }
 }
