@@ -28,7 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
-LAYOUT_NAMES = {1: "linear", 2: "brick4", 3: "cell"}
+LAYOUT_NAMES = {1: "linear", 2: "brick4", 3: "cell", 5: "brick8"}
 CLOCK_GHZ = 2.4  # MI355X peak engine clock
 MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak, published
 # one network evaluation: 2 * (3*256 + 3*256*256 + 256*3) multiply-adds
@@ -575,7 +575,7 @@ def main():
                                                  "hex256-f32", "forward256-f32"])
     ap.add_argument("--window-steps", type=int, default=0,
                     help="streaklines: advance in global-time windows of this many steps (0: one launch)")
-    ap.add_argument("--layout", type=int, default=0, help="0 auto, 1 linear, 2 brick4, 3 cell records (FP32)")
+    ap.add_argument("--layout", type=int, default=0, help="0 auto, 1 linear, 2 brick4, 5 brick8, 3 cell records (FP32)")
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--refill", type=int, default=0)
     ap.add_argument("--no-cell-cache", action="store_true")

@@ -79,6 +79,8 @@ extern "C" {
  * fields. */
 #define STREAMI_LAYOUT_CELL 3
 #define STREAMI_LAYOUT_HEX 4 /* reported by streami_field_info for a hexahedral field (never requested) */
+#define STREAMI_LAYOUT_BRICK8 5 /* 8x8x8-node bricks, bricks in x-fastest order (each axis padded to a
+                                   multiple of 8; a plane of bricks must stay below 16 MiB) */
 
 /* ---- advection modes ---- */
 #define STREAMI_MODE_PLAIN 0

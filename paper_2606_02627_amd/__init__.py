@@ -26,7 +26,7 @@ SHAPE_LINE, SHAPE_PLANE = 0, 1
 F32, F16, BF16 = 0, 1, 2
 BOUNDARY_BLOCK, BOUNDARY_PERIODIC = 0, 1
 ACTIVE, MAX_STEPS, EXIT, STAGNANT, HALO_MISS, NONFINITE = range(6)
-LAYOUT_AUTO, LAYOUT_LINEAR, LAYOUT_BRICK4, LAYOUT_CELL, LAYOUT_HEX = 0, 1, 2, 3, 4
+LAYOUT_AUTO, LAYOUT_LINEAR, LAYOUT_BRICK4, LAYOUT_CELL, LAYOUT_HEX, LAYOUT_BRICK8 = 0, 1, 2, 3, 4, 5
 MODE_PLAIN, MODE_SURROGATE = 0, 1
 
 

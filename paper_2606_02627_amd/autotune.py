@@ -1,8 +1,8 @@
 """Launch-configuration autotuner for the batched advection launch.
 
 Times the caller's whole pass (seeding plus every advect call of it) under each
-candidate -- node layout (x-fastest rows, 4x4x4 bricks, and for steady FP32
-fields per-cell coefficient records), waves per CU,
+candidate -- node layout (x-fastest rows, 4x4x4 or 8x8x8 bricks: the brick size, and
+for steady FP32 fields per-cell coefficient records), waves per CU,
 refill threshold, work order -- through the C-ABI, and caches the fastest per
 (device, dtype, block shapes, caller's signature) in a JSON file
 (STREAMI_TUNE_CACHE, default ~/.cache/streami/autotune.json).  Results are
@@ -21,7 +21,7 @@ CANDIDATES = [dict(waves_per_cu=w, refill_threshold=r, work_order=o)
 
 def _layouts(blocks, fmt):
     steady_f32 = fmt == 0 and all(int(b.n_slices) == 1 for b in blocks)
-    return (1, 2, 3) if steady_f32 else (1, 2)
+    return (1, 2, 5, 3) if steady_f32 else (1, 2, 5)
 
 
 def _cache_path():
@@ -58,8 +58,16 @@ def tune(blocks, fmt, pass_fn, sig, log=None, repeats=2, nodes=None, candidates=
     import torch
     best = None
     trials = []
+    from . import StreamiError, E_UNSUPPORTED
     for layout in _layouts(blocks, fmt):
-        f = Field(blocks, fmt, layout=layout, nodes=nodes)
+        try:
+            f = Field(blocks, fmt, layout=layout, nodes=nodes)
+        except StreamiError as e:  # a layout the blocks' shapes do not fit (32-bit plane offsets)
+            if e.code != E_UNSUPPORTED:
+                raise
+            if log:
+                log(f"tune layout={layout}: not possible for these blocks ({e})")
+            continue
 
         def one(cfg):
             torch.cuda.synchronize()

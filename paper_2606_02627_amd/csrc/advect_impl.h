@@ -89,18 +89,21 @@ __device__ __forceinline__ float3 load_node<FMT_BF16>(const char* p) {
 // record of the cell whose lowest corner is node i/j/k).
 template <int LAYOUT, unsigned NB>
 __device__ __forceinline__ unsigned off_x(int i) {
-  if (LAYOUT == LAYOUT_BRICK4) return __umul24((unsigned)(((i >> 2) << 6) + (i & 3)), NB);
+  constexpr int S = brick_shift(LAYOUT), M = (1 << S) - 1;
+  if (S) return __umul24((unsigned)(((i >> S) << (3 * S)) + (i & M)), NB);
   if (LAYOUT == LAYOUT_CELL) return __umul24((unsigned)i, 96u);
   return __umul24((unsigned)i, NB);
 }
 template <int LAYOUT, unsigned NB>
 __device__ __forceinline__ unsigned off_y(const BlockDev& B, int j) {
-  if (LAYOUT == LAYOUT_BRICK4) return __umul24((unsigned)(j >> 2), B.ys) + (unsigned)(j & 3) * (4 * NB);
+  constexpr int S = brick_shift(LAYOUT), M = (1 << S) - 1;
+  if (S) return __umul24((unsigned)(j >> S), B.ys) + (unsigned)(j & M) * ((1u << S) * NB);
   return __umul24((unsigned)j, B.ys);
 }
 template <int LAYOUT, unsigned NB>
 __device__ __forceinline__ unsigned off_z(const BlockDev& B, int k) {
-  if (LAYOUT == LAYOUT_BRICK4) return __umul24((unsigned)(k >> 2), B.zs) + (unsigned)(k & 3) * (16 * NB);
+  constexpr int S = brick_shift(LAYOUT), M = (1 << S) - 1;
+  if (S) return __umul24((unsigned)(k >> S), B.zs) + (unsigned)(k & M) * ((1u << (2 * S)) * NB);
   return __umul24((unsigned)k, B.zs);
 }
 
@@ -196,7 +199,7 @@ struct Sampler {
     // signed deltas: a periodic wrap steps back to index 0 (a slice is < 2 GiB,
     // so every byte offset and delta fits in int)
     int dx, r10, r01;
-    if (PERIODIC || LAYOUT == LAYOUT_BRICK4) {
+    if (PERIODIC || brick_shift(LAYOUT)) {
       dx = (int)off_x<LAYOUT, NB>(x1) - (int)off_x<LAYOUT, NB>(x0);
       r10 = (int)off_y<LAYOUT, NB>(B, y1) - (int)off_y<LAYOUT, NB>(B, y0);
       r01 = (int)off_z<LAYOUT, NB>(B, z1) - (int)off_z<LAYOUT, NB>(B, z0);
@@ -349,7 +352,7 @@ struct PackedSlicesSampler {
   __device__ __forceinline__ void gather(const BlockDev& B, const char* base, unsigned o000, int x0, int x1, int y0,
                                          int y1, int z0, int z1, unsigned* xyo, unsigned* zzo) {
     int dx, r10, r01;
-    if (PERIODIC || LAYOUT == LAYOUT_BRICK4) {
+    if (PERIODIC || brick_shift(LAYOUT)) {
       dx = (int)off_x<LAYOUT, NB>(x1) - (int)off_x<LAYOUT, NB>(x0);
       r10 = (int)off_y<LAYOUT, NB>(B, y1) - (int)off_y<LAYOUT, NB>(B, y0);
       r01 = (int)off_z<LAYOUT, NB>(B, z1) - (int)off_z<LAYOUT, NB>(B, z0);
@@ -936,6 +939,8 @@ int launch_surrogate_fmt(const SurrogateArgs& s, int layout, bool periodic, bool
   }
   if (layout == LAYOUT_BRICK4) {
     if (periodic) { STREAMI_S(LAYOUT_BRICK4, true) } else { STREAMI_S(LAYOUT_BRICK4, false) }
+  } else if (layout == LAYOUT_BRICK8) {
+    if (periodic) { STREAMI_S(LAYOUT_BRICK8, true) } else { STREAMI_S(LAYOUT_BRICK8, false) }
   } else {
     if (periodic) { STREAMI_S(LAYOUT_LINEAR, true) } else { STREAMI_S(LAYOUT_LINEAR, false) }
   }
@@ -997,6 +1002,8 @@ int launch_advect_fmt(const AdvectArgs& a, int layout, bool periodic, int mode, 
   }
   if (layout == LAYOUT_BRICK4) {
     STREAMI_L(LAYOUT_BRICK4)
+  } else if (layout == LAYOUT_BRICK8) {
+    STREAMI_L(LAYOUT_BRICK8)
   } else {
     STREAMI_L(LAYOUT_LINEAR)
   }

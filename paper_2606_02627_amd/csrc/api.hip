@@ -269,8 +269,9 @@ BlockDev make_dev(const streami_block_desc& d, int layout, int fmt, long long ba
     B.inv_ext[a] = (float)(1.0 / (d.bounds_hi[a] - d.bounds_lo[a]));
     B.rgrid[a] = d.rank_grid[a];
     B.rcoord[a] = d.rank_coord[a];
-    B.nb[a] = (B.nst[a] + 3) / 4;
-    slice *= layout == LAYOUT_BRICK4 ? (long long)B.nb[a] * 4 : B.nst[a];
+    const int be = 1 << brick_shift(layout);  // brick edge (1: no bricks)
+    B.nb[a] = (B.nst[a] + be - 1) / be;
+    slice *= brick_shift(layout) ? (long long)B.nb[a] * be : B.nst[a];
   }
   // cell layout: one record per cell (a periodic axis wraps, so it has as many
   // cells as nodes), counted as 8 pool units of 12 bytes
@@ -289,9 +290,10 @@ BlockDev make_dev(const streami_block_desc& d, int layout, int fmt, long long ba
   B.slice_nodes = slice;
   const long long nb = pool_node_bytes(fmt);
   long long ys, zs;
-  if (layout == LAYOUT_BRICK4) {
-    ys = (long long)B.nb[0] * 64 * nb;
-    zs = (long long)B.nb[0] * B.nb[1] * 64 * nb;
+  if (brick_shift(layout)) {
+    const long long brick = 1LL << (3 * brick_shift(layout));  // nodes per brick
+    ys = (long long)B.nb[0] * brick * nb;
+    zs = (long long)B.nb[0] * B.nb[1] * brick * nb;
   } else if (layout == LAYOUT_CELL) {
     ys = cells[0] * 96;
     zs = cells[0] * cells[1] * 96;
@@ -516,7 +518,7 @@ int streami_field_create(const streami_block_desc* blocks, int32_t n_blocks, int
     return fail(STREAMI_E_ARG, "dtype must be STREAMI_F32, STREAMI_F16 or STREAMI_BF16");
   int layout = opts ? opts->layout : STREAMI_LAYOUT_AUTO;
   if (layout != STREAMI_LAYOUT_AUTO && layout != STREAMI_LAYOUT_LINEAR && layout != STREAMI_LAYOUT_BRICK4 &&
-      layout != STREAMI_LAYOUT_CELL)
+      layout != STREAMI_LAYOUT_CELL && layout != STREAMI_LAYOUT_BRICK8)
     return fail(STREAMI_E_ARG, "unknown layout %d", layout);
   if (layout == STREAMI_LAYOUT_CELL && dtype != STREAMI_F32)
     return fail(STREAMI_E_UNSUPPORTED, "the cell layout stores FP32 coefficients: dtype must be STREAMI_F32");
@@ -566,7 +568,7 @@ int streami_field_create(const streami_block_desc* blocks, int32_t n_blocks, int
     return cleanup(fail(STREAMI_E_UNSUPPORTED, "periodic boundaries are supported for one steady block"));
   int rc;
   if ((rc = f->d_nodes.reserve((size_t)base * pool_node_bytes(dtype), 0, f->stream))) return cleanup(rc);
-  if (layout == STREAMI_LAYOUT_BRICK4 || dtype != STREAMI_F32)  // padding stays zero
+  if (brick_shift(layout) || dtype != STREAMI_F32)  // padding stays zero
     if (hipMemsetAsync(f->d_nodes.p, 0, f->d_nodes.bytes, f->stream) != hipSuccess)
       return cleanup(fail(STREAMI_E_DEVICE, "hipMemsetAsync failed"));
   std::vector<BlockDev> devs(n_blocks);

@@ -6,13 +6,18 @@
 namespace streami {
 
 enum Fmt { FMT_F32 = 0, FMT_F16 = 1, FMT_BF16 = 2 };
-// LINEAR: x-fastest node rows.  BRICK4: 4x4x4-node bricks.  CELL (FP32 only):
+// LINEAR: x-fastest node rows.  BRICK4 / BRICK8: 4x4x4- / 8x8x8-node bricks
+// (nodes x-fastest inside a brick, bricks x-fastest).  CELL (FP32 only):
 // one 96-byte record per cell holding its trilinear interpolant's monomial
 // coefficients, so a cell-cache miss is six aligned 16-byte loads and no
 // arithmetic (8x the node bytes; `base` and `slice_nodes` then count 12-byte
 // units, 8 per cell).
 // HEX (FP32 only): an unstructured hexahedral field (BVH + cell records, hex.h).
-enum Layout { LAYOUT_LINEAR = 1, LAYOUT_BRICK4 = 2, LAYOUT_CELL = 3, LAYOUT_HEX = 4 };
+enum Layout { LAYOUT_LINEAR = 1, LAYOUT_BRICK4 = 2, LAYOUT_CELL = 3, LAYOUT_HEX = 4, LAYOUT_BRICK8 = 5 };
+// log2 of a brick layout's edge (0: not a brick layout)
+__host__ __device__ constexpr int brick_shift(int layout) {
+  return layout == LAYOUT_BRICK4 ? 2 : layout == LAYOUT_BRICK8 ? 3 : 0;
+}
 enum Code { ACTIVE = 0, MAX_STEPS = 1, EXIT = 2, STAGNANT = 3, HALO_MISS = 4, NONFINITE = 5 };
 
 // One block as the kernels see it.  Storage coordinate along an axis:
@@ -167,17 +172,20 @@ constexpr int ORDER_SCAN_WG = 256;  // workgroups of the work order's bucket sca
 // Per-axis offsets of node i within a slice of a block.
 template <int LAYOUT>
 __device__ __forceinline__ int ax_off(const BlockDev& B, int i) {
-  if (LAYOUT == LAYOUT_BRICK4) return ((i >> 2) << 6) + (i & 3);
+  constexpr int S = brick_shift(LAYOUT), M = (1 << S) - 1;
+  if (S) return ((i >> S) << (3 * S)) + (i & M);
   return i;
 }
 template <int LAYOUT>
 __device__ __forceinline__ int ay_off(const BlockDev& B, int j) {
-  if (LAYOUT == LAYOUT_BRICK4) return (j >> 2) * (B.nb[0] << 6) + ((j & 3) << 2);
+  constexpr int S = brick_shift(LAYOUT), M = (1 << S) - 1;
+  if (S) return (j >> S) * (B.nb[0] << (3 * S)) + ((j & M) << S);
   return j * B.nst[0];
 }
 template <int LAYOUT>
 __device__ __forceinline__ int az_off(const BlockDev& B, int k) {
-  if (LAYOUT == LAYOUT_BRICK4) return (k >> 2) * ((B.nb[0] * B.nb[1]) << 6) + ((k & 3) << 4);
+  constexpr int S = brick_shift(LAYOUT), M = (1 << S) - 1;
+  if (S) return (k >> S) * ((B.nb[0] * B.nb[1]) << (3 * S)) + ((k & M) << (2 * S));
   return k * (B.nst[0] * B.nst[1]);
 }
 

@@ -130,6 +130,8 @@ int launch_ingest(const void* src, void* pool, const BlockDev& B, int fmt, int l
                        reinterpret_cast<float4*>(pool), B, nx, ny, nz, n_slices);
   } else if (layout == LAYOUT_BRICK4) {
     if (fmt == FMT_F32) STREAMI_INGEST(FMT_F32, LAYOUT_BRICK4); else STREAMI_INGEST(FMT_F16, LAYOUT_BRICK4);
+  } else if (layout == LAYOUT_BRICK8) {
+    if (fmt == FMT_F32) STREAMI_INGEST(FMT_F32, LAYOUT_BRICK8); else STREAMI_INGEST(FMT_F16, LAYOUT_BRICK8);
   } else {
     if (fmt == FMT_F32) STREAMI_INGEST(FMT_F32, LAYOUT_LINEAR); else STREAMI_INGEST(FMT_F16, LAYOUT_LINEAR);
   }

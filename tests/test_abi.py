@@ -151,6 +151,7 @@ def test_binding_structs_match_the_header_layout(tmp_path):
     ((1600, 1600, 2), "f16", 0, "16 MiB"),  # 1602^2 x 8 B (16-bit nodes padded to 8 B)
     ((300, 300, 300), "f32", 3, "2 GiB"),   # 301^3 cell records x 96 B > 2 GiB
     ((450, 450, 2), "f32", 3, "16 MiB"),    # a z plane of 451^2 cell records x 96 B > 16 MiB
+    ((510, 510, 2), "f16", 5, "16 MiB"),    # a plane of 64^2 8^3-node bricks x 8 B = 2^24 B
 ])
 def test_field_create_rejects_shapes_beyond_the_addressing_limits(dims, dtype, layout, msg):
     """The kernels address a slice with 32-bit byte offsets and 24-bit row/plane products;

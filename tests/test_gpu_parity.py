@@ -74,7 +74,7 @@ def test_uniform_flow_bit_exact(S):
                                hi=(9, 9, 9), rank_grid=(3, 3, 3), rank_coord=(1, 1, 1))
     rng = np.random.default_rng(1)
     seeds = (rng.integers(0, 9 * 64, size=(777, 3)) / 64.0).astype(np.float32)
-    for layout in (S.LAYOUT_LINEAR, S.LAYOUT_BRICK4, S.LAYOUT_CELL):
+    for layout in (S.LAYOUT_LINEAR, S.LAYOUT_BRICK4, S.LAYOUT_BRICK8, S.LAYOUT_CELL):
         f, lines, ob, st = run(S, [blk], [seeds], 0.5, 1000, fg.F32, layout=layout)
         segs = parity.split_lines(lines[0])
         for i, s in enumerate(segs):
@@ -267,14 +267,15 @@ def test_turbulence_block_parity(S, dtype, layout):
 
 
 def test_bit_identical_variants(S):
-    """Cell cache on/off (in registers or in LDS), node rows / bricks / cell records, the
-    interior test on/off, hipGraph replay and chunked resume all give bit-identical lines, steps,
-    codes and outbox contents."""
+    """Cell cache on/off (in registers or in LDS), node rows / 4^3 and 8^3 bricks / cell records,
+    the interior test on/off, hipGraph replay and chunked resume all give bit-identical lines,
+    steps, codes and outbox contents; for 16-bit nodes, rows and both brick sizes agree too."""
     note("variants")
     blk = fg.turbulence_block(2, edge=32, rank_grid=(3, 3, 3), rank_coord=(1, 1, 1))
     seeds = fg.uniform_seeds(2, 2500, (0, 0, 0), (32, 32, 32), sub=9)
     base = run(S, [blk], [seeds], 0.5, 300, fg.F32)
-    variants = [dict(no_cell_cache=1), dict(layout=1), dict(layout=2), dict(layout=3),
+    variants = [dict(no_cell_cache=1), dict(layout=1), dict(layout=2), dict(layout=5), dict(layout=5, no_cell_cache=1),
+                dict(layout=3),
                 dict(layout=3, no_cell_cache=1), dict(checked_samples=1), dict(layout=1, checked_samples=1),
                 dict(use_graph=1), dict(chunk=37),
                 dict(waves_per_cu=8, refill_threshold=1), dict(work_order=1), dict(lds_cell_cache=1),
@@ -286,6 +287,14 @@ def test_bit_identical_variants(S):
         for k in ("offsets", "xyz", "steps", "codes", "ids"):
             np.testing.assert_array_equal(got[1][0][k], base[1][0][k])
         np.testing.assert_array_equal(np.sort(got[2], order="id"), np.sort(base[2], order="id"))
+    b16 = fg.turbulence_block(2, edge=30, fmt=fg.F16, rank_grid=(3, 3, 3), rank_coord=(1, 1, 1))
+    s16 = fg.uniform_seeds(2, 1500, (0, 0, 0), (30, 30, 30), sub=10)
+    base = run(S, [b16], [s16], 0.5, 300, fg.F16, layout=1)
+    for layout in (2, 5):
+        note("variant 16-bit layout", layout)
+        got = run(S, [b16], [s16], 0.5, 300, fg.F16, layout=layout)
+        for k in ("offsets", "xyz", "steps", "codes", "ids"):
+            np.testing.assert_array_equal(got[1][0][k], base[1][0][k])
 
 
 @pytest.mark.parametrize("dtype", [fg.BF16, fg.F16])
