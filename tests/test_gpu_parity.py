@@ -301,8 +301,9 @@ def test_bit_identical_variants(S):
 @pytest.mark.parametrize("kind", ["steady", "unsteady", "batched"])
 def test_packed_16bit_cache_bit_identical(S, dtype, kind):
     """16-bit nodes keep their cached corners packed (two per register) and widen them at
-    each sample; the results equal those of re-gathering every sample, bit for bit,
-    for one block, for time-blended slices and for several blocks in one launch."""
+    each sample; the results equal those of re-gathering every sample, and those of 8^3-node
+    bricks, bit for bit, for one block, for time-blended slices and for several blocks in one
+    launch."""
     note("packed 16-bit cache", fg.DTYPE_NAMES[dtype], kind)
     if kind == "batched":
         blocks = [fg.turbulence_block(4, dims=d, fmt=dtype, sub=b, rank_grid=(1, 1, 1), rank_coord=(0, 0, 0),
@@ -314,12 +315,14 @@ def test_packed_16bit_cache_bit_identical(S, dtype, kind):
                                       n_slices=ns, slice_dt=40.0)]
     seeds = [fg.uniform_seeds(2, 1300 + 100 * b, (0, 0, 0), blk.dims, sub=20 + b) for b, blk in enumerate(blocks)]
     base = run(S, blocks, seeds, 0.5, 300, dtype)
-    got = run(S, blocks, seeds, 0.5, 300, dtype, no_cell_cache=1)
-    assert got[3].steps == base[3].steps > 0
-    for b in range(len(blocks)):
-        for k in ("offsets", "xyz", "steps", "codes", "ids"):
-            np.testing.assert_array_equal(got[1][b][k], base[1][b][k])
-    np.testing.assert_array_equal(np.sort(got[2], order=["block", "id"]), np.sort(base[2], order=["block", "id"]))
+    for extra in (dict(no_cell_cache=1), dict(layout=S.LAYOUT_BRICK8)):
+        got = run(S, blocks, seeds, 0.5, 300, dtype, **extra)
+        assert got[3].steps == base[3].steps > 0
+        for b in range(len(blocks)):
+            for k in ("offsets", "xyz", "steps", "codes", "ids"):
+                np.testing.assert_array_equal(got[1][b][k], base[1][b][k])
+        np.testing.assert_array_equal(np.sort(got[2], order=["block", "id"]),
+                                      np.sort(base[2], order=["block", "id"]))
 
 
 def test_graph_replays(S):
