@@ -24,6 +24,7 @@
 #include <new>
 #include <string>
 #include <vector>
+#include <utility>
 
 #include "../../include/streami.h"
 
@@ -277,21 +278,73 @@ struct InferArgs {
 };
 
 // One workgroup = 4 waves = 128 particles; each wave keeps its 32 particles'
-// activations in registers as the B operand.  A layer is computed in two
-// halves of 4 output tiles: each half's weight fragments (<= 64 KB) are staged
-// in LDS and shared by the 4 waves, and its 4 tiles' accumulators (64
-// registers) run as independent MFMA chains.  The first half's activations wait
-// in 32 registers until the second half has read the layer's input; with 64 KB
-// of LDS and <= 256 registers per wave, two workgroups share a CU, so one
-// workgroup's epilogue (SiLU: an exp and a reciprocal per value) overlaps the
-// other's matrix work.
+// activations in registers as the B operand, and the network runs as a
+// software pipeline of 17 compute steps:
+//   layer 0 in 4 quarters (output tiles 2q, 2q+1; one k-step each),
+//   layers 1..3 in 4 quarters each (2 tiles x 16 k-steps),
+//   layer 4 in one step (1 tile x 16 k-steps).
+// The weight fragments come through LDS in 14 stages (layer 0 whole, the 12
+// hidden quarters, layer 4; at most 32 KB each) and two buffers: a stage is
+// copied by direct global-to-LDS loads, which hold no registers, while the
+// previous stage computes.  The SiLU epilogue of a step runs between the MFMAs
+// of the next one (two accumulator sets), so the matrix cores are not idle
+// while the transcendentals execute.  A quarter's outputs are the next layer's
+// k-steps 4q..4q+3; quarters 0..2 wait in registers until the layer's last
+// quarter has read its input, quarter 3 is produced while the next layer's
+// first step consumes k-steps 0..11.  Two workgroups share a CU (69 KB of LDS
+// each).
 constexpr int INFER_WAVES = 4;
+constexpr int N_STEPS = 17, N_STAGES = 14, STAGE_UNITS = 2048;  // 16-byte units
+__host__ __device__ constexpr int step_layer(int c) { return c < 4 ? 0 : c < 16 ? 1 + (c - 4) / 4 : 4; }
+__host__ __device__ constexpr int step_quarter(int c) { return c < 4 ? c : c < 16 ? (c - 4) % 4 : 0; }
+__host__ __device__ constexpr int step_tiles(int c) { return c < 16 ? 2 : 1; }
+__host__ __device__ constexpr int step_stage(int c) { return c < 4 ? 0 : c - 3; }
+__host__ __device__ constexpr bool step_opens(int c) { return c == 0 || c >= 4; }
+// first fragment of step c within its stage (layer 0's quarters share one stage)
+__host__ __device__ constexpr int step_base(int c) { return c < 4 ? 2 * c * 64 : 0; }
+__host__ __device__ constexpr int stage_off(int d) {
+  return d == 0 ? FR_OFF[0] : d < 13 ? FR_OFF[1 + (d - 1) / 4] + ((d - 1) % 4) * STAGE_UNITS : FR_OFF[4];
+}
+__host__ __device__ constexpr int stage_units(int d) {
+  return d == 0 ? FR_OFF[1] - FR_OFF[0] : d < 13 ? STAGE_UNITS : FR_OFF[5] - FR_OFF[4];
+}
+static_assert(FR_OFF[1] - FR_OFF[0] <= STAGE_UNITS && FR_OFF[5] - FR_OFF[4] <= STAGE_UNITS, "stage size");
+static_assert((FR_OFF[1] - FR_OFF[0]) % 256 == 0 && (FR_OFF[5] - FR_OFF[4]) % 256 == 0, "whole copies");
+static_assert(FR_OFF[2] - FR_OFF[1] == 4 * STAGE_UNITS, "a hidden layer is four stages");
+
+typedef __attribute__((__vector_size__(2 * sizeof(float)))) float f32x2;
+typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2;
+typedef __attribute__((__vector_size__(4 * sizeof(unsigned)))) unsigned u32x4;
+
+// Stage d into an LDS buffer: each lane copies 16 bytes per instruction, a
+// wave 1 KB to consecutive LDS addresses (the LDS base is wave-uniform).
+template <int D>
+__device__ __forceinline__ void stage_copy(const uint4* frag, uint4* buf, int tid) {
+  constexpr int off = stage_off(D), units = stage_units(D);
+#pragma unroll
+  for (int i = 0; i < units / 256; ++i)
+    __builtin_amdgcn_global_load_lds(static_cast<const void*>(frag + off + i * 256 + tid),
+                                     (__attribute__((address_space(3))) void*)(buf + i * 256 + (tid & ~63)),
+                                     16, 0, 0);
+}
+
+template <int... I, class F>
+__device__ __forceinline__ void for_steps(std::integer_sequence<int, I...>, F&& f) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+
 __global__ void __launch_bounds__(64 * INFER_WAVES, 2) k_mlp_infer(InferArgs a) {
-  __shared__ uint4 wl[4096];
-  __shared__ float bl[256];
+  __shared__ uint4 w0[STAGE_UNITS];
+  __shared__ uint4 w1[STAGE_UNITS];
+  __shared__ float bl[NL][256];
   const int tid = threadIdx.x, lane = tid & 63, hi = lane >> 5;
   const long long p = (long long)blockIdx.x * (32 * INFER_WAVES) + (tid >> 6) * 32 + (lane & 31);
   const bool live = p < a.n;
+  stage_copy<0>(a.frag, w0, tid);
+  for (int i = tid; i < NL * 256; i += 64 * INFER_WAVES) {
+    const int l = i >> 8, f = i & 255;
+    bl[l][f] = f < WID[l + 1] ? a.b[l][f] : 0.0f;
+  }
   bf16x8 B[16];
   {
     f32x8 x = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -306,54 +359,71 @@ __global__ void __launch_bounds__(64 * INFER_WAVES, 2) k_mlp_infer(InferArgs a) 
 #pragma unroll
     for (int s = 1; s < 16; ++s) B[s] = zero;  // layer 0 reads B[0] only
   }
-  f32x16 acc[4];
-  bf16x8 Bn[8];  // the first half's outputs (features 0..127), until the second half is done
-#pragma unroll
-  for (int l = 0; l < NL; ++l) {
-    const int tiles = FR_TILES[l], ks = FR_KSTEPS[l];
-    const int halves = tiles > 4 ? 2 : 1, th = tiles / halves;
-#pragma unroll
-    for (int h = 0; h < halves; ++h) {
-      __syncthreads();  // every wave is done with the LDS contents
-      const uint4* src = a.frag + FR_OFF[l] + h * th * ks * 64;
-      for (int i = tid; i < th * ks * 64; i += 64 * INFER_WAVES) wl[i] = src[i];
-      if (h == 0)
-        for (int i = tid; i < 256; i += 64 * INFER_WAVES) bl[i] = i < WID[l + 1] ? a.b[l][i] : 0.0f;
-      __syncthreads();
-      // the accumulators start at the bias of the feature each register holds
-#pragma unroll
-      for (int t = 0; t < th; ++t)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc[t][r] = bl[32 * (h * th + t) + 8 * (r / 4) + 4 * hi + r % 4];
-#pragma unroll
-      for (int s = 0; s < ks; ++s) {
-#pragma unroll
-        for (int t = 0; t < th; ++t) {
-          const uint4 w = wl[(t * ks + s) * 64 + lane];
-          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, w), B[s], acc[t], 0, 0, 0);
-        }
-        if (s % 4 == 3) __builtin_amdgcn_sched_barrier(0);  // bound how far fragment loads run ahead
-      }
-      if (l < NL - 1) {
-#pragma unroll
-        for (int t = 0; t < th; ++t)
-#pragma unroll
-          for (int q = 0; q < 2; ++q) {
-            f32x8 hv;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) hv[j] = silu_fast(acc[t][8 * q + j]);
-            if (h == 0) Bn[2 * t + q] = __builtin_convertvector(hv, bf16x8);
-            else B[8 + 2 * t + q] = __builtin_convertvector(hv, bf16x8);
-          }
-        if (h == 1) {
-#pragma unroll
-          for (int k = 0; k < 8; ++k) B[k] = Bn[k];
-        }
-      } else if (live && hi == 0) {
-        for (int c = 0; c < 3; ++c) a.out[p * 3 + c] = a.sigma[c] * acc[0][c];
-      }
+  f32x16 acc[2][2];
+  unsigned H[48];  // next layer's k-steps 0..11 (quarters 0..2), 4 words each
+  unsigned Q[16];  // next layer's k-steps 12..15 (quarter 3)
+
+  // SiLU of value pair e (0..15) of step C's accumulators into the words of
+  // the next layer's input: pair e = 8 tt + j of tile tt is word j % 4 of
+  // k-step 4 q + 2 tt + j / 4.
+  auto epilogue_pair = [&](auto Cc, int e) {
+    constexpr int C = decltype(Cc)::value;
+    constexpr int q = step_quarter(C);
+    const int tt = e >> 3, j = e & 7;
+    f32x2 z = {silu_fast(acc[C % 2][tt][2 * j]), silu_fast(acc[C % 2][tt][2 * j + 1])};
+    const unsigned w = __builtin_bit_cast(unsigned, __builtin_convertvector(z, bf16x2));
+    const int ks = 2 * tt + (j >> 2), wd = j & 3;
+    if (q < 3) H[(4 * q + ks) * 4 + wd] = w;
+    else Q[ks * 4 + wd] = w;
+  };
+
+  for_steps(std::make_integer_sequence<int, N_STEPS>{}, [&](auto Cc) {
+    constexpr int C = decltype(Cc)::value;
+    constexpr int l = step_layer(C), q = step_quarter(C), tiles = step_tiles(C), ks = FR_KSTEPS[l];
+    constexpr int d = step_stage(C);
+    uint4* const buf = d % 2 ? w1 : w0;
+    if constexpr (step_opens(C)) {
+      __syncthreads();  // stage d has landed; every wave is done with the other buffer
+      if constexpr (d + 1 < N_STAGES) stage_copy<(d + 1 < N_STAGES ? d + 1 : 0)>(a.frag, (d + 1) % 2 ? w1 : w0, tid);
     }
-  }
+    if constexpr (C > 0 && step_layer(C - 1) != l) {
+      // a new layer: its k-steps 0..11 are the previous layer's quarters 0..2
+#pragma unroll
+      for (int k = 0; k < 12; ++k)
+        B[k] = __builtin_bit_cast(bf16x8, u32x4{H[4 * k], H[4 * k + 1], H[4 * k + 2], H[4 * k + 3]});
+    }
+    // the accumulators start at the bias of the feature each register holds
+#pragma unroll
+    for (int tt = 0; tt < tiles; ++tt)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[C % 2][tt][r] = bl[l][32 * (2 * q + tt) + 8 * (r / 4) + 4 * hi + r % 4];
+#pragma unroll
+    for (int k = 0; k < ks; ++k) {
+      if constexpr (C > 0) {
+        // the previous step's epilogue, spread over this step's k-steps
+        constexpr int per = 16 / ks;
+#pragma unroll
+        for (int e = k * per; e < (k + 1) * per; ++e) epilogue_pair(std::integral_constant<int, C - 1>{}, e);
+        // a new layer's k-step 12 + i is complete once pairs 4i..4i+3 are (at
+        // k-step 4i + 3 <= 12 + i of this step)
+        if constexpr (step_layer(C - 1) != l) {
+          if (k >= 12) {
+            const int i = k - 12;
+            B[k] = __builtin_bit_cast(bf16x8, u32x4{Q[4 * i], Q[4 * i + 1], Q[4 * i + 2], Q[4 * i + 3]});
+          }
+        }
+      }
+#pragma unroll
+      for (int tt = 0; tt < tiles; ++tt) {
+        const uint4 w = buf[step_base(C) + (tt * ks + k) * 64 + lane];
+        acc[C % 2][tt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, w), B[k], acc[C % 2][tt], 0, 0, 0);
+      }
+      if (k % 4 == 3) __builtin_amdgcn_sched_barrier(0);  // bound how far fragment loads run ahead
+    }
+  });
+  // layer 4 (step 16, accumulator set 0): the three outputs are features 0..2 of the hi = 0 lanes
+  if (live && hi == 0)
+    for (int c = 0; c < 3; ++c) a.out[p * 3 + c] = a.sigma[c] * acc[0][0][c];
 }
 
 static int grid_for(long long n) {
