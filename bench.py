@@ -33,6 +33,7 @@ CLOCK_GHZ = 2.4  # MI355X peak engine clock
 MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak, published
 # one network evaluation: 2 * (3*256 + 3*256*256 + 256*3) multiply-adds
 MLP_FLOPS_PER_EVAL = 2 * (3 * 256 + 3 * 256 * 256 + 256 * 3)
+MLP_SILU_PER_EVAL = 4 * 256  # a SiLU after each of the four 256-wide layers
 
 
 def log(*a):
@@ -233,6 +234,21 @@ def surrogate_bench(args):
             "frac": flops / mlp_ms / 1e9 / MFMA_BF16_PEAK_TFLOPS, "traffic": None, "kernel": "k_mlp_infer",
             "flops_per_eval": MLP_FLOPS_PER_EVAL, "evals_per_launch": n_inf, "mean_launch_ms": mlp_ms}
     log(f"k_mlp_infer: {mlp_ms:.3f} ms for {n_inf} evaluations, {roof['achieved']:.1f} TFLOP/s")
+    # the SiLU epilogue's own floor: per hidden output one exp, one rcp, three VOP2 instructions
+    # (multiply, add, multiply) and half a packed BF16 conversion (VOP3), at the issue costs the
+    # VALU probe measures on this chip, spread over every SIMD
+    n_simd = 4 * torch.cuda.get_device_properties(0).multi_processor_count
+    cyc = {}
+    for kind, name in ((0, "fma_f32"), (1, "add_u32"), (2, "exp_f32"), (3, "rcp_f32")):
+        ms, n = S.streami_probe_valu(kind, 32)
+        cyc[name] = n_simd * CLOCK_GHZ * 1e9 * ms * 1e-3 / n
+    per64 = cyc["exp_f32"] + cyc["rcp_f32"] + 3 * cyc["add_u32"] + 0.5 * cyc["fma_f32"]
+    silu_per_eval = MLP_SILU_PER_EVAL
+    valu_ms = n_inf * silu_per_eval / 64 * per64 / (n_simd * CLOCK_GHZ * 1e9) * 1e3
+    roof["epilogue_valu"] = {"cycles_per_wave64_instruction": cyc, "cycles_per_64_outputs": per64,
+                             "silu_outputs_per_eval": silu_per_eval, "floor_ms": valu_ms,
+                             "floor_over_launch": valu_ms / mlp_ms}
+    log(f"SiLU epilogue VALU floor {valu_ms:.3f} ms ({per64:.1f} cycles per 64 outputs)")
     S.streami_mlp_destroy(net)
     plain = res[0]
     best_sur = max(res[2:], key=lambda r: r["equiv_steps_per_s"])

@@ -34,7 +34,8 @@ int streami_probe_gather(const void* buf, int64_t bytes, int32_t record_bytes, i
 
 /* VALU issue rate: waves_per_cu (a multiple of 4 in [4, 64]) waves per CU
  * each run 8 independent chains of one instruction kind -- kind 0 v_fma_f32
- * (a VOP3 encoding), kind 1 v_add_u32 (VOP2) -- 131,072 instructions per wave.
+ * (a VOP3 encoding), kind 1 v_add_u32 (VOP2), kind 2 v_exp_f32, kind 3
+ * v_rcp_f32 (the two transcendentals of a SiLU) -- 131,072 instructions per wave.
  * One untimed launch, then one timed with HIP events on hip_stream: *ms is
  * its time and *instructions (nullable) the wave-level instructions of the
  * chains, so (4 x CUs) x clock x time / instructions is the cycles a SIMD

@@ -379,7 +379,8 @@ def streami_probe_gather(buf, record_bytes, loads_per_lane, in_flight=4, waves_p
 
 
 def streami_probe_valu(kind, waves_per_cu=32, stream=None):
-    """VALU issue-rate probe (kind 0 v_fma_f32, 1 v_add_u32): (ms, wave-level instructions)."""
+    """VALU issue-rate probe (kind 0 v_fma_f32, 1 v_add_u32, 2 v_exp_f32, 3 v_rcp_f32): (ms, wave-level
+    instructions)."""
     ms, n = ctypes.c_float(), ctypes.c_int64()
     _check(_load().streami_probe_valu(int(kind), int(waves_per_cu), _stream(stream), ctypes.byref(ms),
                                       ctypes.byref(n)))

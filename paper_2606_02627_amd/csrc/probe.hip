@@ -53,19 +53,26 @@ __global__ void __launch_bounds__(256) k_probe_gather(const uint4* __restrict__ 
 }
 
 // VALU issue rate: 8 independent chains per lane of one instruction kind
-// (0: v_fma_f32, a VOP3 encoding; 1: v_add_u32, VOP2), 16 x 8 per iteration.
+// (0: v_fma_f32, a VOP3 encoding; 1: v_add_u32, VOP2; 2: v_exp_f32 of a
+// negated operand; 3: v_rcp_f32), 16 x 8 per iteration.  The float chains
+// start in [0.5, 0.51] and stay finite (2^-x maps [0.5, 1] into itself, 1/x
+// alternates between two values).
 template <int KIND>
 __global__ void __launch_bounds__(256) k_probe_valu(unsigned* __restrict__ sink, int iters) {
   unsigned x[8];
 #pragma unroll
-  for (int c = 0; c < 8; ++c) x[c] = threadIdx.x * 2654435761u + (unsigned)c;
+  for (int c = 0; c < 8; ++c)
+    x[c] = KIND >= 2 ? __float_as_uint(0.5f + 0.001f * (float)c + 0.00001f * (float)(threadIdx.x & 63))
+                     : threadIdx.x * 2654435761u + (unsigned)c;
   for (int i = 0; i < iters; ++i) {
 #pragma unroll
     for (int u = 0; u < 16; ++u)
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
         if (KIND == 0) x[c] = __float_as_uint(fmaf(__uint_as_float(x[c]), 0.999f, 0.5f));
-        else x[c] = x[c] + x[(c + 1) & 7];
+        else if (KIND == 1) x[c] = x[c] + x[(c + 1) & 7];
+        else if (KIND == 2) x[c] = __float_as_uint(__builtin_amdgcn_exp2f(-__uint_as_float(x[c])));
+        else x[c] = __float_as_uint(__builtin_amdgcn_rcpf(__uint_as_float(x[c])));
       }
   }
   unsigned acc = 0;
@@ -154,7 +161,8 @@ extern "C" int streami_probe_gather(const void* buf, int64_t bytes, int32_t reco
 extern "C" int streami_probe_valu(int32_t kind, int32_t waves_per_cu, void* hip_stream, float* ms,
                                   int64_t* instructions) {
   if (!ms) return perr(STREAMI_E_ARG, "ms must not be NULL");
-  if (kind != 0 && kind != 1) return perr(STREAMI_E_ARG, "kind must be 0 (v_fma_f32) or 1 (v_add_u32)");
+  if (kind < 0 || kind > 3)
+    return perr(STREAMI_E_ARG, "kind must be 0 (v_fma_f32), 1 (v_add_u32), 2 (v_exp_f32) or 3 (v_rcp_f32)");
   if (waves_per_cu < 4 || waves_per_cu > 64 || waves_per_cu % 4 != 0)
     return perr(STREAMI_E_ARG, "waves_per_cu must be a multiple of 4 in [4, 64]");
   hipStream_t st = (hipStream_t)hip_stream;
@@ -178,8 +186,12 @@ extern "C" int streami_probe_valu(int32_t kind, int32_t waves_per_cu, void* hip_
       if (rep == 1) (void)hipEventRecord(e0, st);
       if (kind == 0)
         hipLaunchKernelGGL(k_probe_valu<0>, dim3(grid), dim3(256), 0, st, sink, iters);
-      else
+      else if (kind == 1)
         hipLaunchKernelGGL(k_probe_valu<1>, dim3(grid), dim3(256), 0, st, sink, iters);
+      else if (kind == 2)
+        hipLaunchKernelGGL(k_probe_valu<2>, dim3(grid), dim3(256), 0, st, sink, iters);
+      else
+        hipLaunchKernelGGL(k_probe_valu<3>, dim3(grid), dim3(256), 0, st, sink, iters);
       if (hipGetLastError() != hipSuccess) rc = perr(STREAMI_E_DEVICE, "probe launch failed");
       if (rep == 1) (void)hipEventRecord(e1, st);
     }

@@ -111,7 +111,8 @@ def test_probe_rejects_invalid_arguments_before_device_work():
     assert probe(fake, 8, 16, 64, 4, 16) == S.E_ARG
     assert probe(fake, 1 << 40, 16, 64, 4, 16) == S.E_ARG
     assert b"record" in lib.streami_last_error()
-    assert lib.streami_probe_valu(2, 32, None, ctypes.byref(ms), None) == S.E_ARG
+    assert lib.streami_probe_valu(4, 32, None, ctypes.byref(ms), None) == S.E_ARG
+    assert lib.streami_probe_valu(-1, 32, None, ctypes.byref(ms), None) == S.E_ARG
     assert lib.streami_probe_valu(0, 30, None, ctypes.byref(ms), None) == S.E_ARG
     assert lib.streami_probe_valu(0, 32, None, None, None) == S.E_ARG
 

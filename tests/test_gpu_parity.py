@@ -137,7 +137,7 @@ def test_memory_probe_reads_what_it_reports(S):
         note(f"probe {rec} B: {n} records in {ms:.3f} ms")
     with pytest.raises(S.StreamiError):
         S.streami_probe_gather(buf[:8], 16, 8, 2, 4)
-    for kind in (0, 1):
+    for kind in (0, 1, 2, 3):
         ms, n = S.streami_probe_valu(kind, 4)
         assert ms > 0 and n == n_cu * 4 * 1024 * 128, (kind, ms, n)
         note(f"valu probe kind {kind}: {4 * n_cu * 2.4e6 * ms / n:.2f} cycles per wave64 instruction at 2.4 GHz")
