@@ -483,9 +483,10 @@ def forward_bench(args):
     """The default workload's field split into a 2 x 2 x 2 rank grid of 128^3 blocks in one handle,
     the same 1M seeds (each seeded in the block that owns it) and limits, traced with loopback
     forwarding (streami_trace): every exit routed on the device into the neighbouring block,
-    rounds until nothing is active.  Timed with run-to-exit rounds; one pass each with an
-    exchange every 64, 8 and 1 steps (the last is the paper's one exchange per step) shows
-    what the exchange granularity costs on one GPU."""
+    rounds until nothing is active.  Timed with an exchange every --exchange-steps steps (256, the
+    fastest measured for this field); one pass each with run-to-exit rounds and with an exchange
+    every 512 ... 1 steps (the last is the paper's one exchange per step) shows what the exchange
+    granularity costs on one GPU.  Every granularity gives the same lines."""
     import torch
     import fieldgen as fg
     import paper_2606_02627_amd as S
@@ -504,26 +505,27 @@ def forward_bench(args):
         f.seed_batches(batches, default_max_steps=m)
         return S.streami_trace(f.h, S.advect_params(h, step_budget=budget), want_stats=stats)
 
-    r0, st0 = one(0, stats=True)
+    k = max(0, args.exchange_steps)
+    r0, st0 = one(k, stats=True)
     assert st0.active == 0
     for _ in range(max(0, args.warmup - 1)):
-        one(0)
+        one(k)
     torch.cuda.synchronize()
     t = time.perf_counter()
     for _ in range(args.steps):
-        one(0)
+        one(k)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t) / args.steps
     steps = int(st0.steps)
     gran = []
-    for budget in (512, 256, 128, 64, 8, 1):
+    for budget in (0, 512, 256, 128, 64, 8, 1):
         torch.cuda.synchronize()
         t = time.perf_counter()
         rk, stk = one(budget, stats=True)
         torch.cuda.synchronize()
         sec = time.perf_counter() - t
         assert int(stk.steps) == steps and stk.active == 0
-        gran.append(dict(steps_per_exchange=budget, rounds=rk, seconds=sec, steps_per_s=steps / sec,
+        gran.append(dict(steps_per_exchange=budget or "run to exit", rounds=rk, seconds=sec, steps_per_s=steps / sec,
                          advect_device_ms=stk.device_ms))
         log(f"exchange every {budget} steps: {rk} rounds, {sec * 1e3:.1f} ms, {steps / sec:.3g} steps/s")
     f.close()
@@ -536,7 +538,8 @@ def forward_bench(args):
         "ms_per_step": wall * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "forward256-f32", "field": "256^3 turbulence split into 2x2x2 blocks of 128^3 + ghost",
-                   "seeds": len(seeds), "max_steps": m, "h": h, "rounds": r0, "particle_steps_per_step": steps,
+                   "seeds": len(seeds), "max_steps": m, "h": h, "steps_per_exchange": k or "run to exit",
+                   "rounds": r0, "particle_steps_per_step": steps,
                    "layout": LAYOUT_NAMES[layout]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_advect (8 blocks, forwarding)",
@@ -598,6 +601,9 @@ def main():
     ap.add_argument("--lds-cell-cache", action="store_true",
                     help="keep each lane's cached cell record in LDS instead of registers (cell records)")
     ap.add_argument("--graph", action="store_true")
+    ap.add_argument("--exchange-steps", type=int, default=256,
+                    help="forward256: steps each block runs between two exchanges (0: until every local particle "
+                         "has terminated or left)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a plain 1 GiB device copy first (scale for the HBM byte counters)")
