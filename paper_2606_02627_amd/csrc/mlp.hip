@@ -334,6 +334,8 @@ __device__ __forceinline__ void for_steps(std::integer_sequence<int, I...>, F&& 
 }
 
 __global__ void __launch_bounds__(64 * INFER_WAVES, 2) k_mlp_infer(InferArgs a) {
+  // two distinct arrays, so that the compiler sees that a copy in flight writes
+  // the other buffer and waits for it only at the barrier
   __shared__ uint4 w0[STAGE_UNITS];
   __shared__ uint4 w1[STAGE_UNITS];
   __shared__ float bl[NL][256];
