@@ -311,6 +311,25 @@ __host__ __device__ constexpr int stage_units(int d) {
 static_assert(FR_OFF[1] - FR_OFF[0] <= STAGE_UNITS && FR_OFF[5] - FR_OFF[4] <= STAGE_UNITS, "stage size");
 static_assert((FR_OFF[1] - FR_OFF[0]) % 256 == 0 && (FR_OFF[5] - FR_OFF[4]) % 256 == 0, "whole copies");
 static_assert(FR_OFF[2] - FR_OFF[1] == 4 * STAGE_UNITS, "a hidden layer is four stages");
+// the stages tile the fragment array in order, and every step reads only
+// within its own stage: its tiles x k-steps x 64 lanes from its first fragment
+__host__ __device__ constexpr bool stage_table_ok() {
+  int end = 0;
+  for (int d = 0; d < N_STAGES; ++d) {
+    if (stage_off(d) != end || stage_units(d) > STAGE_UNITS) return false;
+    end += stage_units(d);
+  }
+  if (end != FR_OFF[NL]) return false;
+  for (int c = 0; c < N_STEPS; ++c) {
+    const int l = step_layer(c), d = step_stage(c);
+    const int first = FR_OFF[l] + 2 * step_quarter(c) * FR_KSTEPS[l] * 64;  // tile 2q of layer l
+    if (first != stage_off(d) + step_base(c)) return false;
+    if (step_base(c) + step_tiles(c) * FR_KSTEPS[l] * 64 > stage_units(d)) return false;
+    if (c > 0 && step_stage(c) != step_stage(c - 1) + (step_opens(c) ? 1 : 0)) return false;
+  }
+  return true;
+}
+static_assert(stage_table_ok(), "stage table");
 
 typedef __attribute__((__vector_size__(2 * sizeof(float)))) float f32x2;
 typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2;
