@@ -717,7 +717,7 @@ def main():
                 if "valu_instructions" in tj:
                     # what bounds the kernel, from the same profiled revision's counters
                     counters = {"valu_instructions": tj["valu_instructions"], "l2_hit_rate": tj.get("l2_hit"),
-                                "source": os.path.relpath(tfile, ROOT)}
+                                "clock_ghz": tj.get("clock_ghz"), "source": os.path.relpath(tfile, ROOT)}
         except Exception:
             traffic = counters = None
     out = {
