@@ -610,7 +610,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on exactly one GPU (the multi-GPU exchange of the outbox is "
+        print("bench.py: the library runs on exactly one GPU (the multi-GPU exchange of the outbox is "
               "designed but not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 

@@ -49,7 +49,7 @@ extern "C" {
 #define STREAMI_E_DEVICE 3      /* a HIP call failed */
 #define STREAMI_E_STATE 4       /* call not valid in the handle's current state */
 #define STREAMI_E_CAPACITY 5    /* output buffer too small; required size reported */
-#define STREAMI_E_UNSUPPORTED 6 /* valid request this build does not implement */
+#define STREAMI_E_UNSUPPORTED 6 /* valid request the library does not implement */
 #define STREAMI_E_IO 7          /* a file could not be opened or written */
 
 /* ---- node storage formats (the GPU never quantises: nodes arrive in this format) ---- */
