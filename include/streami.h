@@ -407,7 +407,7 @@ int streami_forward(streami_field f, int64_t* n_forwarded, int64_t* n_active);
  * termination or exit first.  Every budget gives the same lines; the time
  * differs: a round ends with its longest trajectory, so a budget of a few
  * hundred steps, which lets long trajectories continue in the next round beside
- * the others, is usually fastest (256 steps: 1.5x the run-to-exit rounds on a
+ * the others, is usually fastest (256 steps: 1.6x the run-to-exit rounds on a
  * 256^3 field split into 2x2x2 blocks), while small budgets pay per round.
  * *rounds (nullable) receives the rounds run.
  * stats (nullable) sums steps, vertices, gathers, surrogate counts and device
