@@ -298,7 +298,8 @@ typedef struct {
   int32_t use_graph;        /* 1: capture the launch sequence in a hipGraph and replay it */
   int32_t no_cell_cache;    /* 1: re-gather a cell's corners at every sample (A/B measurement;
                                results are bit-identical either way) */
-  int32_t work_order;       /* 0: spatial order (block, Morton brick) split over per-XCD queues;
+  int32_t work_order;       /* 0: spatial order (block, Morton brick) split over per-XCD queues,
+                               except for calls with a step_budget of 1 (seed order there);
                                1: seed order, one queue (results are bit-identical either way) */
   int32_t use_t_end;        /* 1: advance in a time window: a particle takes a step only while its
                                time t_birth + steps*h is < t_end, and stays ACTIVE at t_end (PLAIN
@@ -407,7 +408,7 @@ int streami_forward(streami_field f, int64_t* n_forwarded, int64_t* n_active);
  * termination or exit first.  Every budget gives the same lines; the time
  * differs: a round ends with its longest trajectory, so a budget of a few
  * hundred steps, which lets long trajectories continue in the next round beside
- * the others, is usually fastest (256 steps: 1.6x the run-to-exit rounds on a
+ * the others, is usually fastest (256 steps: 1.7x the run-to-exit rounds on a
  * 256^3 field split into 2x2x2 blocks), while small budgets pay per round.
  * *rounds (nullable) receives the rounds run.
  * stats (nullable) sums steps, vertices, gathers, surrogate counts and device

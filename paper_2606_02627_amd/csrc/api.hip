@@ -167,6 +167,7 @@ struct streami_field_s {
   int device = 0;
   hipStream_t stream = nullptr;
   int fmt = 0, layout = LAYOUT_LINEAR;
+  long long ob_settled = 0;  // outbox records before this one stayed in an exchange (not read again)
   bool unsteady = false;
   bool periodic = false;
   int n_cu = 256;
@@ -1065,8 +1066,11 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
     if (rc) return rc;
   }
   a.log = f->log();
-  // spatial work order (bucket sort by block and Morton brick) over per-XCD queues
-  const bool spatial = p->work_order == 0;
+  // spatial work order (bucket sort by block and Morton brick) over per-XCD queues; not for
+  // one-step calls (the paper's per-step exchange rounds): there the sort of every particle
+  // record (~0.2 ms at 1.5M records) costs more than the order saves (with 8 steps per round it
+  // still saves more than it costs); the order changes no result
+  const bool spatial = p->work_order == 0 && p->step_budget != 1;
   // spatial work order: classes of remaining steps (longest first), then block and Morton brick
   const int bits = f->blocks.size() == 1 ? 5 : 3;
   // one class when every seeded limit is the same (the spatial order alone, fewer buckets), or
@@ -1159,6 +1163,7 @@ int streami_clear(streami_field f) {
   f->next_auto_id = 0;
   f->log_need_known = true;  // the counters below restart at zero
   f->log_need_hi = 0;
+  f->ob_settled = 0;
   for (auto& hb : f->blocks) {
     hb.ranges.clear();
     hb.n_particles = 0;
@@ -1305,6 +1310,7 @@ int streami_fetch_outbox(streami_field f, streami_outbox_rec* out, int64_t cap, 
     HIP_TRY(hipMemcpyAsync(out, src, take * sizeof(OutRec),
                            is_device_ptr(out) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, f->stream));
     unsigned long long rest = cnt - take;
+    f->ob_settled = std::min<long long>(f->ob_settled, (long long)rest);
     HIP_TRY(hipMemcpyAsync(f->outbox_count(), &rest, 8, hipMemcpyHostToDevice, f->stream));
     HIP_TRY(hipStreamSynchronize(f->stream));
   }
@@ -1330,11 +1336,14 @@ int streami_forward(streami_field f, int64_t* n_forwarded, int64_t* n_active) {
   long long* base = (long long*)(kept + 1);
   long long total = 0;
   std::vector<unsigned long long> h(nb + 1, 0);
-  if (ob > 0) {
+  // the records before `first` stayed in an earlier exchange (final exits): only the new ones are read
+  const long long first = std::min<long long>(f->ob_settled, (long long)ob);
+  if ((long long)ob > first) {
     FwdArgs a;
     a.outbox = (const OutRec*)f->d_outbox.p;
     a.outbox_src = (const int*)f->d_obsrc.p;
     a.outbox_count = f->outbox_count();
+    a.first = first;
     a.rank_map = (const int*)f->d_rankmap.p;
     a.n_ranks = f->n_ranks;
     a.n_blocks = nb;
@@ -1342,7 +1351,7 @@ int streami_forward(streami_field f, int64_t* n_forwarded, int64_t* n_active) {
     a.meta = (const int4*)f->d_meta.p;
     a.meta2 = (const int4*)f->d_meta2.p;
     launch_fill_u64(counts, 2LL * nb + 2, 0, f->stream);
-    launch_fwd_count(a, counts, (long long)ob, f->stream);
+    launch_fwd_count(a, counts, (long long)ob - first, f->stream);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(h.data(), counts, sizeof(unsigned long long) * (nb + 1), hipMemcpyDeviceToHost, f->stream));
     HIP_TRY(hipStreamSynchronize(f->stream));
@@ -1381,11 +1390,10 @@ int streami_forward(streami_field f, int64_t* n_forwarded, int64_t* n_active) {
       o.kept = (OutRec*)f->d_outbox2.p;
       o.kept_src = (int*)f->d_obsrc2.p;
       o.n_kept = kept;
-      launch_fwd_write(a, o, (long long)ob, f->stream);
-      launch_copy_u64(kept, f->outbox_count(), f->stream);
+      launch_fwd_write(a, o, (long long)ob - first, f->stream);
+      launch_fwd_settle(o.kept, o.kept_src, kept, (OutRec*)f->d_outbox.p, (int*)f->d_obsrc.p, first,
+                        f->outbox_count(), (long long)ob - first, f->stream);
       HIP_TRY(hipGetLastError());
-      std::swap(f->d_outbox, f->d_outbox2);
-      std::swap(f->d_obsrc, f->d_obsrc2);
       for (int b = 0; b < nb; ++b)
         if (h[b] > 0) {
           f->blocks[b].ranges.push_back({hb[b], (long long)h[b]});
@@ -1396,6 +1404,7 @@ int streami_forward(streami_field f, int64_t* n_forwarded, int64_t* n_active) {
       drop_graph(f);  // the cached launch holds the old buffers
     }
   }
+  f->ob_settled = (long long)ob - total;  // every record left in the outbox is final
   if (n_forwarded) *n_forwarded = total;
   if (n_active) {
     launch_fill_u64(f->code_counts(), 6, 0, f->stream);

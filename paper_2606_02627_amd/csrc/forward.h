@@ -11,6 +11,7 @@ struct FwdArgs {
   const OutRec* outbox;
   const int* outbox_src;
   const unsigned long long* outbox_count;
+  long long first;  // records before it stayed in an earlier exchange and are not looked at again
   const int* rank_map;  // macrocell id -> block of this handle, or -1
   int n_ranks;
   int n_blocks;
@@ -34,6 +35,8 @@ struct FwdOut {
 
 int launch_fwd_count(const FwdArgs& a, unsigned long long* counts, long long max_records, hipStream_t st);
 int launch_fwd_write(const FwdArgs& a, const FwdOut& o, long long max_records, hipStream_t st);
-int launch_copy_u64(const unsigned long long* src, unsigned long long* dst, hipStream_t st);
+int launch_fwd_settle(const OutRec* kept, const int* kept_src, const unsigned long long* n_kept, OutRec* outbox,
+                      int* outbox_src, long long first, unsigned long long* outbox_count, long long max_records,
+                      hipStream_t st);
 
 }  // namespace streami

@@ -7,12 +7,15 @@
 // position, which is vertex 0 of its new line segment.  Records for
 // macrocells outside the handle stay in the outbox.
 //
-// Two launches per exchange: k_fwd_count counts the records per destination
+// An exchange looks only at the records appended since the last one (from
+// `first` on): a record that stays is final, so the records before `first`
+// are not read again.  k_fwd_count counts the new records per destination
 // block and the vertex records their segments may still write; the host then
 // places each block's new particles in one contiguous range after the
-// existing ones, and k_fwd_write initialises them and compacts the records
-// that stay into a second outbox buffer.  Counting goes through LDS
-// histograms, so a workgroup issues one global atomic per destination block.
+// existing ones, k_fwd_write initialises them and compacts the new records
+// that stay into a scratch buffer, and k_fwd_settle copies those back behind
+// the settled ones.  Counting goes through LDS histograms, so a workgroup
+// issues one global atomic per destination block.
 #include <hip/hip_runtime.h>
 
 #include "forward.h"
@@ -40,7 +43,8 @@ __global__ void __launch_bounds__(FWD_THREADS) k_fwd_count(FwdArgs a, unsigned l
   __syncthreads();
   const long long n = (long long)*a.outbox_count;
   unsigned long long bound = 0;
-  for (long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x; r < n; r += (long long)gridDim.x * blockDim.x) {
+  for (long long r = a.first + blockIdx.x * (long long)blockDim.x + threadIdx.x; r < n;
+       r += (long long)gridDim.x * blockDim.x) {
     const OutRec rec = a.outbox[r];
     const int b = fwd_target(a, rec);
     if (b < 0) continue;
@@ -63,7 +67,7 @@ __global__ void __launch_bounds__(FWD_THREADS) k_fwd_write(FwdArgs a, FwdOut o) 
   const long long stride_all = (long long)gridDim.x * blockDim.x;
   // every workgroup walks its records in rounds of blockDim.x, so that the
   // LDS histogram of one round fits the slots it reserves
-  for (long long r0 = blockIdx.x * (long long)blockDim.x; r0 < n; r0 += stride_all) {
+  for (long long r0 = a.first + blockIdx.x * (long long)blockDim.x; r0 < n; r0 += stride_all) {
     for (int i = threadIdx.x; i < a.n_blocks; i += blockDim.x) hist[i] = 0;
     __syncthreads();
     const long long r = r0 + threadIdx.x;
@@ -126,8 +130,16 @@ __global__ void __launch_bounds__(FWD_THREADS) k_fwd_write(FwdArgs a, FwdOut o) 
   }
 }
 
-__global__ void k_copy_u64(const unsigned long long* src, unsigned long long* dst) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
+// The new records that stay, from the scratch buffer back to the outbox at
+// `first`, and the outbox count.
+__global__ void k_fwd_settle(const OutRec* kept, const int* kept_src, const unsigned long long* n_kept, OutRec* outbox,
+                             int* outbox_src, long long first, unsigned long long* outbox_count) {
+  const long long k = (long long)*n_kept;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < k; i += (long long)gridDim.x * blockDim.x) {
+    outbox[first + i] = kept[i];
+    outbox_src[first + i] = kept_src[i];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *outbox_count = (unsigned long long)(first + k);
 }
 
 int launch_fwd_count(const FwdArgs& a, unsigned long long* counts, long long max_records, hipStream_t st) {
@@ -146,8 +158,13 @@ int launch_fwd_write(const FwdArgs& a, const FwdOut& o, long long max_records, h
   return 0;
 }
 
-int launch_copy_u64(const unsigned long long* src, unsigned long long* dst, hipStream_t st) {
-  hipLaunchKernelGGL(k_copy_u64, dim3(1), dim3(64), 0, st, src, dst);
+int launch_fwd_settle(const OutRec* kept, const int* kept_src, const unsigned long long* n_kept, OutRec* outbox,
+                      int* outbox_src, long long first, unsigned long long* outbox_count, long long max_records,
+                      hipStream_t st) {
+  long long g = (max_records + FWD_THREADS - 1) / FWD_THREADS;
+  g = g < 1 ? 1 : (g > 1024 ? 1024 : g);
+  hipLaunchKernelGGL(k_fwd_settle, dim3((unsigned)g), dim3(FWD_THREADS), 0, st, kept, kept_src, n_kept, outbox,
+                     outbox_src, first, outbox_count);
   return 0;
 }
 
