@@ -712,8 +712,14 @@ __device__ __forceinline__ void advect_body(const AdvectArgs& A) {
     if (em != 0) {
       const int leader = __ffsll((long long)em) - 1;
       unsigned long long obase = 0;
-      if (lane == leader) obase = atomicAdd(A.ctr + CTR_N + PER_OUTBOX, (unsigned long long)__popcll(em));
+      // with segments, each XCD's waves reserve from their own counter (one shared by every
+      // wave with an exit cost 4% of the 256^3 launch in contention)
+      const unsigned seg = blockIdx.x & (OB_SEGS - 1);
+      unsigned long long* octr =
+          A.ob_segs ? A.qctr + (size_t)(MAX_QUEUES + seg) * QCTR_STRIDE : A.ctr + CTR_N + PER_OUTBOX;
+      if (lane == leader) obase = atomicAdd(octr, (unsigned long long)__popcll(em));
       obase = __shfl(obase, leader, 64);
+      if (A.ob_segs) obase += (unsigned long long)seg * (unsigned long long)A.n_particles;
       if (emit) {
         OutRec r;
         r.id = A.ids[p];

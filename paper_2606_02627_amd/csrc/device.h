@@ -131,6 +131,9 @@ struct AdvectArgs {
   int windowed;             // 0: no time window (the time is then only the sampler's)
   int checked;              // 1: test every sample's domain even deep inside the block
   unsigned log_chunk;       // records per log reservation of a wave (LOG_CHUNK_MIN .. LOG_CHUNK)
+  int ob_segs;              // OB_SEGS: outbox records go to per-XCD segments of n_particles records
+                            // (outbox/outbox_src point at them; counters after the queue counters
+                            // in qctr), appended to the outbox after the launch; 0: straight to it
 };
 
 // One surrogate jump (16 plain steps) for every active particle of a single
@@ -164,6 +167,7 @@ __device__ __forceinline__ void to_monomial(float3 c[8]) {
 }
 
 constexpr int QCTR_STRIDE = 16;  // one 128-byte line per queue counter
+constexpr int OB_SEGS = 8;       // outbox segments, one per XCD (workgroup index mod 8)
 constexpr int MAX_QUEUES = 8;
 constexpr int ORDER_CLASSES = 8;  // classes of remaining steps in the spatial work order
 constexpr int QTAB_STRIDE = 1 + 2 * ORDER_CLASSES;
