@@ -714,12 +714,24 @@ __device__ __forceinline__ void advect_body(const AdvectArgs& A) {
       unsigned long long obase = 0;
       // with segments, each XCD's waves reserve from their own counter (one shared by every
       // wave with an exit cost 4% of the 256^3 launch in contention)
-      const unsigned seg = blockIdx.x & (OB_SEGS - 1);
-      unsigned long long* octr =
-          A.ob_segs ? A.qctr + (size_t)(MAX_QUEUES + seg) * QCTR_STRIDE : A.ctr + CTR_N + PER_OUTBOX;
-      if (lane == leader) obase = atomicAdd(octr, (unsigned long long)__popcll(em));
+      if (lane == leader) {
+        const unsigned long long cnt = (unsigned long long)__popcll(em);
+        bool direct = true;
+        if (A.ob_seg_cap > 0) {
+          const unsigned seg = blockIdx.x & (OB_SEGS - 1);
+          const unsigned long long cap = (unsigned long long)A.ob_seg_cap;
+          unsigned long long* sc = A.qctr + (size_t)(MAX_QUEUES + seg) * QCTR_STRIDE;
+          const unsigned long long o = atomicAdd(sc, cnt);
+          if (o + cnt <= cap) {
+            obase = (unsigned long long)A.ob_seg_base + seg * cap + o;
+            direct = false;
+          } else if (o < cap) {
+            sc[1] = o + 1;  // the one reservation that crosses the end: the segment's records stop at o
+          }
+        }
+        if (direct) obase = atomicAdd(A.ctr + CTR_N + PER_OUTBOX, cnt);
+      }
       obase = __shfl(obase, leader, 64);
-      if (A.ob_segs) obase += (unsigned long long)seg * (unsigned long long)A.n_particles;
       if (emit) {
         OutRec r;
         r.id = A.ids[p];

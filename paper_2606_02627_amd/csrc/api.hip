@@ -54,8 +54,8 @@ int launch_gather_meta(const long long* idx, long long count, const int4* meta, 
                        const unsigned long long* pid, long long* nverts, int* steps, int* codes,
                        unsigned long long* ids, hipStream_t st);
 int launch_count_codes(const int4* meta, long long n, unsigned long long* counts, hipStream_t st);
-int launch_ob_concat(const OutRec* seg, const int* seg_src, const unsigned long long* seg_ctr, long long seg_cap,
-                     OutRec* outbox, int* outbox_src, unsigned long long* outbox_count, hipStream_t st);
+int launch_ob_concat(OutRec* outbox, int* outbox_src, long long seg_base, long long seg_cap,
+                     const unsigned long long* seg_ctr, unsigned long long* outbox_count, hipStream_t st);
 }  // namespace streami
 
 using namespace streami;
@@ -197,7 +197,6 @@ struct streami_field_s {
   unsigned long long* h_seedred = nullptr;  // pinned copy of it
   DevBuf d_ctr;        // CTR_N per-call counters, PER_N persistent counters, 6 code counts
   DevBuf d_qctr;       // per-queue work counters, then the per-XCD outbox segment counters
-  DevBuf d_obseg, d_obsegsrc;  // per-XCD outbox segments of one advect launch
   DevBuf d_key, d_order, d_hist, d_cursor, d_nwork;  // spatial work order
   DevBuf d_dhat, d_dhat2, d_xh;                      // surrogate jumps
   bool strides_mult16 = true;                        // every seed batch's record stride % 16 == 0
@@ -754,7 +753,7 @@ int streami_field_destroy(streami_field f) {
   drop_graph(f);
   for (DevBuf* b : {&f->d_blocks, &f->d_nodes, &f->d_pos, &f->d_meta, &f->d_meta2, &f->d_ids, &f->d_outbox,
                     &f->d_obsrc, &f->d_rankmap, &f->d_fwd, &f->d_outbox2, &f->d_obsrc2,
-                    &f->d_logv, &f->d_ctr, &f->d_qctr, &f->d_obseg, &f->d_obsegsrc, &f->d_key,
+                    &f->d_logv, &f->d_ctr, &f->d_qctr, &f->d_key,
                     &f->d_order, &f->d_hist, &f->d_cursor, &f->d_nwork, &f->d_dhat, &f->d_dhat2, &f->d_xh,
                     &f->d_seedred})
     b->release();
@@ -1086,15 +1085,19 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
   {
     int rc;
     if ((rc = f->d_qctr.reserve(sizeof(unsigned long long) * 2 * MAX_QUEUES * QCTR_STRIDE, 0, f->stream))) return rc;
-    // per-XCD outbox segments (OB_SEGS x n_particles records: a launch ends each particle at most
-    // once) for handles of up to 8M particles (2.3 GB); larger ones reserve straight from the outbox
-    if (f->n_particles > 0 && f->n_particles <= (8LL << 20)) {
-      if ((rc = f->d_obseg.reserve(sizeof(OutRec) * OB_SEGS * (size_t)f->n_particles, 0, f->stream)) ||
-          (rc = f->d_obsegsrc.reserve(sizeof(int) * OB_SEGS * (size_t)f->n_particles, 0, f->stream)))
+    // per-XCD outbox segments behind the outbox proper: n/8 + 64 records each (a launch ends
+    // each particle at most once, and the waves of each XCD take an even share of the work);
+    // a wave whose records do not fit its segment writes them straight to the outbox
+    if (f->n_particles > 0) {
+      const long long seg_cap = f->n_particles / OB_SEGS + 64;
+      const size_t recs = (size_t)f->cap_particles + (size_t)OB_SEGS * (size_t)seg_cap;
+      if ((rc = f->d_outbox.reserve(recs * sizeof(OutRec), (size_t)f->cap_particles * sizeof(OutRec), f->stream)) ||
+          (rc = f->d_obsrc.reserve(recs * sizeof(int), (size_t)f->cap_particles * sizeof(int), f->stream)))
         return rc;
-      a.outbox = (OutRec*)f->d_obseg.p;
-      a.outbox_src = (int*)f->d_obsegsrc.p;
-      a.ob_segs = OB_SEGS;
+      a.outbox = (OutRec*)f->d_outbox.p;
+      a.outbox_src = (int*)f->d_obsrc.p;
+      a.ob_seg_base = f->cap_particles;
+      a.ob_seg_cap = seg_cap;
     }
     if (spatial) {
       if ((rc = f->d_key.reserve(f->n_particles * 4, 0, f->stream)) ||
@@ -1119,8 +1122,8 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
   };
   // the segments' records to the end of the outbox
   auto append_segments = [&](hipStream_t st) {
-    launch_ob_concat(a.outbox, a.outbox_src, a.qctr + (size_t)MAX_QUEUES * QCTR_STRIDE, a.n_particles,
-                     (OutRec*)f->d_outbox.p, (int*)f->d_obsrc.p, f->outbox_count(), st);
+    launch_ob_concat(a.outbox, a.outbox_src, a.ob_seg_base, a.ob_seg_cap, a.qctr + (size_t)MAX_QUEUES * QCTR_STRIDE,
+                     f->outbox_count(), st);
   };
   HIP_TRY(hipEventRecord(f->ev0, f->stream));
   f->log_need_known = false;  // the launch appends records the host does not count
@@ -1146,7 +1149,7 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
                           (unsigned*)f->d_hist.p, (unsigned*)f->d_cursor.p, (int*)f->d_order.p,
                           (unsigned*)f->d_nwork.p, cs);
       launch(cs);
-      if (a.ob_segs) append_segments(cs);
+      if (a.ob_seg_cap) append_segments(cs);
       HIP_TRY(hipStreamEndCapture(cs, &g));
       HIP_TRY(hipGraphInstantiate(&f->graph, g, nullptr, nullptr, 0));
       (void)hipGraphDestroy(g);
@@ -1163,7 +1166,7 @@ int streami_advect(streami_field f, const streami_advect_params* p, streami_stat
                         (unsigned*)f->d_hist.p, (unsigned*)f->d_cursor.p, (int*)f->d_order.p,
                         (unsigned*)f->d_nwork.p, f->stream);
     launch(f->stream);
-    if (a.ob_segs) append_segments(f->stream);
+    if (a.ob_seg_cap) append_segments(f->stream);
   }
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipEventRecord(f->ev1, f->stream));

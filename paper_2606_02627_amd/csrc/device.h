@@ -131,9 +131,13 @@ struct AdvectArgs {
   int windowed;             // 0: no time window (the time is then only the sampler's)
   int checked;              // 1: test every sample's domain even deep inside the block
   unsigned log_chunk;       // records per log reservation of a wave (LOG_CHUNK_MIN .. LOG_CHUNK)
-  int ob_segs;              // OB_SEGS: outbox records go to per-XCD segments of n_particles records
-                            // (outbox/outbox_src point at them; counters after the queue counters
-                            // in qctr), appended to the outbox after the launch; 0: straight to it
+  // per-XCD outbox segments (ob_seg_cap > 0): segment s holds ob_seg_cap records from index
+  // ob_seg_base + s * ob_seg_cap of outbox/outbox_src (behind the outbox proper); its counter is
+  // qctr[(MAX_QUEUES + s) * QCTR_STRIDE], and the next word marks where a full segment's records
+  // end (o + 1).  A reservation that does not fit goes straight to the outbox.  The segments are
+  // appended to the outbox after the launch.  0: every record straight to the outbox.
+  long long ob_seg_base;
+  long long ob_seg_cap;
 };
 
 // One surrogate jump (16 plain steps) for every active particle of a single

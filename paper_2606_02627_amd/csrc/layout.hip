@@ -407,41 +407,49 @@ __global__ void __launch_bounds__(256) k_count_codes(const int4* meta, long long
   }
 }
 
-// The outbox records of the last launch, from the per-XCD segments (counts in
-// seg_ctr, QCTR_STRIDE apart) to the end of the outbox, segment after segment.
-__global__ void k_ob_concat(const OutRec* seg, const int* seg_src, const unsigned long long* seg_ctr, long long seg_cap,
-                            OutRec* outbox, int* outbox_src, const unsigned long long* outbox_count) {
+// The outbox records of the last launch, from the per-XCD segments (behind the
+// outbox proper, from index seg_base) to the end of the outbox, segment after
+// segment.  Records of segment s: its counter, capped at seg_cap, or the mark
+// of the reservation that did not fit (o + 1 in the counter's next word).
+__device__ __forceinline__ unsigned long long seg_records(const unsigned long long* seg_ctr, int s,
+                                                          unsigned long long cap) {
+  const unsigned long long* c = seg_ctr + (size_t)s * QCTR_STRIDE;
+  return c[1] ? c[1] - 1 : (c[0] < cap ? c[0] : cap);
+}
+
+__global__ void k_ob_concat(OutRec* outbox, int* outbox_src, long long seg_base, long long seg_cap,
+                            const unsigned long long* seg_ctr, const unsigned long long* outbox_count) {
   unsigned long long off[OB_SEGS + 1];
   off[0] = 0;
 #pragma unroll
-  for (int s = 0; s < OB_SEGS; ++s) off[s + 1] = off[s] + seg_ctr[(size_t)s * QCTR_STRIDE];
+  for (int s = 0; s < OB_SEGS; ++s) off[s + 1] = off[s] + seg_records(seg_ctr, s, (unsigned long long)seg_cap);
   const unsigned long long base = *outbox_count;
   for (unsigned long long i = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; i < off[OB_SEGS];
        i += (unsigned long long)gridDim.x * blockDim.x) {
     int s = 0;
     while (i >= off[s + 1]) ++s;
-    const size_t j = (size_t)s * (size_t)seg_cap + (size_t)(i - off[s]);
-    outbox[base + i] = seg[j];
-    outbox_src[base + i] = seg_src[j];
+    const size_t j = (size_t)seg_base + (size_t)s * (size_t)seg_cap + (size_t)(i - off[s]);
+    outbox[base + i] = outbox[j];
+    outbox_src[base + i] = outbox_src[j];
   }
 }
 
 // After k_ob_concat (a separate launch, so that no workgroup reads the old count late).
-__global__ void k_ob_commit(const unsigned long long* seg_ctr, unsigned long long* outbox_count) {
+__global__ void k_ob_commit(const unsigned long long* seg_ctr, long long seg_cap, unsigned long long* outbox_count) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     unsigned long long t = 0;
-    for (int s = 0; s < OB_SEGS; ++s) t += seg_ctr[(size_t)s * QCTR_STRIDE];
+    for (int s = 0; s < OB_SEGS; ++s) t += seg_records(seg_ctr, s, (unsigned long long)seg_cap);
     *outbox_count += t;
   }
 }
 
-int launch_ob_concat(const OutRec* seg, const int* seg_src, const unsigned long long* seg_ctr, long long seg_cap,
-                     OutRec* outbox, int* outbox_src, unsigned long long* outbox_count, hipStream_t st) {
-  int grid = (int)std::min<long long>((seg_cap + 255) / 256, 1024);
+int launch_ob_concat(OutRec* outbox, int* outbox_src, long long seg_base, long long seg_cap,
+                     const unsigned long long* seg_ctr, unsigned long long* outbox_count, hipStream_t st) {
+  int grid = (int)std::min<long long>((OB_SEGS * seg_cap + 255) / 256, 1024);
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(k_ob_concat, dim3(grid), dim3(256), 0, st, seg, seg_src, seg_ctr, seg_cap, outbox, outbox_src,
+  hipLaunchKernelGGL(k_ob_concat, dim3(grid), dim3(256), 0, st, outbox, outbox_src, seg_base, seg_cap, seg_ctr,
                      outbox_count);
-  hipLaunchKernelGGL(k_ob_commit, dim3(1), dim3(64), 0, st, seg_ctr, outbox_count);
+  hipLaunchKernelGGL(k_ob_commit, dim3(1), dim3(64), 0, st, seg_ctr, seg_cap, outbox_count);
   return 0;
 }
 
