@@ -713,11 +713,15 @@ __device__ __forceinline__ void advect_body(const AdvectArgs& A) {
       const int leader = __ffsll((long long)em) - 1;
       unsigned long long obase = 0;
       // with segments, each XCD's waves reserve from their own counter (one shared by every
-      // wave with an exit cost 4% of the 256^3 launch in contention)
+      // wave with an exit cost 4% of the 256^3 launch in contention).  Compiled into the batched
+      // and cell-record kernels only: the single-block node-row kernels (few exits per step,
+      // VALU-bound at 16 bits) lost 1.4% to the scalar registers the path takes; their segments
+      // stay empty
+      constexpr bool OB_SEG = BATCHED || LAYOUT == LAYOUT_CELL;
       if (lane == leader) {
         const unsigned long long cnt = (unsigned long long)__popcll(em);
         bool direct = true;
-        if (A.ob_seg_cap > 0) {
+        if (OB_SEG && A.ob_seg_cap > 0) {
           const unsigned seg = blockIdx.x & (OB_SEGS - 1);
           const unsigned long long cap = (unsigned long long)A.ob_seg_cap;
           unsigned long long* sc = A.qctr + (size_t)(MAX_QUEUES + seg) * QCTR_STRIDE;
